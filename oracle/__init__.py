@@ -1,0 +1,161 @@
+"""ORACLE -- test infrastructure only.
+
+Only the tests, the smoke check (`__graft_entry__.smoke`) and the CPU
+baseline leg of `bench.py` may import this package.  The product library
+(`paper_2605_01313_amd`) never imports, links or calls it, and shares no
+code with it.
+
+Contents
+  * `dfs_eval`   -- FP64 direct sum of the complex-exponential DFS series
+                    (section 5, eq. std_dfs_exp), plain C + OpenMP
+                    (`dfs_direct.c`), at arbitrary points.
+  * `dfs_eval_ld` -- the same sum in long double, used to certify the FP64
+                    oracle's own rounding at the largest sizes.
+  * `std_to_exp` -- the map of eq. dfs_fourier_coeffs from standard-DFS
+                    cos/sin coefficients to exp-form coefficients.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dfs_direct.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+               "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _open(path):
+    lib = ctypes.CDLL(path)
+    sig = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    for name in ("oracle_dfs_eval", "oracle_dfs_eval_ld"):
+        fn = getattr(lib, name)
+        fn.argtypes = sig
+        fn.restype = ctypes.c_int
+    lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        _lib = _open(_LIB)
+    return _lib
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    _load().oracle_set_num_threads(int(n))
+
+
+def _eval(fn_name, coeffs, phi, theta, lib=None):
+    lib = lib or _load()
+    c = np.asarray(coeffs, dtype=np.complex128)
+    if c.ndim == 2:
+        c = c[None]
+    if c.ndim != 3:
+        raise ValueError("coeffs must be (K_theta, K_phi) or (F, K_theta, K_phi)")
+    c = np.ascontiguousarray(c)
+    ph = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).ravel())
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).ravel())
+    if ph.shape != th.shape:
+        raise ValueError("phi and theta must have the same length")
+    F, Kt, Kp = c.shape
+    out = np.empty((F, ph.size), dtype=np.complex128)
+    rc = getattr(lib, fn_name)(c.ctypes.data, Kt, Kp, F, ph.ctypes.data,
+                               th.ctypes.data, ph.size, out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"{fn_name} failed ({rc})")
+    return out
+
+
+def load_variant(path):
+    """Open another build of `dfs_direct.c` (used to check that the pins
+    reject planted mistakes); returns an evaluator with `dfs_eval`'s signature."""
+    lib = _open(path)
+    return lambda coeffs, phi, theta: _eval("oracle_dfs_eval", coeffs, phi, theta, lib)
+
+
+def dfs_eval(coeffs, phi, theta):
+    """f_F(phi_j, theta_j) for every field F and point j, FP64 direct sum.
+
+    coeffs: (K_theta, K_phi) or (F, K_theta, K_phi) complex, centred indices
+    (row a <-> n = a - K_theta//2, column b <-> m = b - K_phi//2).
+    Returns (F, P) complex128.
+    """
+    return _eval("oracle_dfs_eval", coeffs, phi, theta)
+
+
+def dfs_eval_ld(coeffs, phi, theta):
+    """As `dfs_eval`, accumulated in long double (certification only)."""
+    return _eval("oracle_dfs_eval_ld", coeffs, phi, theta)
+
+
+def std_to_exp(fc, fs):
+    """Standard-DFS cos/sin coefficients -> exp-form coefficients (eq. dfs_fourier_coeffs).
+
+    fc, fs: real arrays (N+1, M+1) indexed [n, m], n = 0..N, m = 0..M, holding
+    the coefficients of the standard DFS basis (eq. std_dfs): for even m the
+    theta factor is cos(n theta), for odd m it is sin(n theta); fc multiplies
+    cos(m phi), fs multiplies sin(m phi).  Entries the basis does not use
+    (fs[:, 0]; n = 0 for odd m) are ignored.
+
+    Returns the centred (2N+1, 2M+1) complex array ft[n, m], n, m in
+    [-N, N] x [-M, M].  The paper's printed map leaves out the m = 0, n >= 1
+    entries and the sine part at n = 0 for even m; both are taken from the
+    cos/sin-to-exponential identities: ft[+-n, 0] = fc[n, 0]/2 and
+    ft[0, +-m] = (fc[0, m] -+ i fs[0, m])/2.
+    """
+    fc = np.asarray(fc, dtype=np.float64)
+    fs = np.asarray(fs, dtype=np.float64)
+    N, M = fc.shape[0] - 1, fc.shape[1] - 1
+    ft = np.zeros((2 * N + 1, 2 * M + 1), dtype=np.complex128)
+
+    def put(n, m, v):
+        ft[n + N, m + M] += v
+
+    put(0, 0, fc[0, 0])
+    for n in range(1, N + 1):                      # m = 0, n >= 1
+        put(n, 0, 0.5 * fc[n, 0])
+        put(-n, 0, 0.5 * fc[n, 0])
+    for m in range(1, M + 1):
+        if m % 2 == 0:
+            put(0, m, 0.5 * (fc[0, m] - 1j * fs[0, m]))
+            put(0, -m, 0.5 * (fc[0, m] + 1j * fs[0, m]))
+            for n in range(1, N + 1):
+                a = 0.25 * (fc[n, m] - 1j * fs[n, m])
+                b = 0.25 * (fc[n, m] + 1j * fs[n, m])
+                put(n, m, a)
+                put(-n, m, a)
+                put(n, -m, b)
+                put(-n, -m, b)
+        else:
+            for n in range(1, N + 1):              # n = 0 term vanishes (sin 0)
+                a = -0.25 * (1j * fc[n, m] + fs[n, m])
+                b = -0.25 * (1j * fc[n, m] - fs[n, m])
+                put(n, m, a)
+                put(-n, m, -a)
+                put(n, -m, b)
+                put(-n, -m, -b)
+    return ft
