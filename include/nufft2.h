@@ -1,0 +1,176 @@
+/*
+ * nufft2 -- type-2 NUFFT that evaluates double-Fourier-sphere (DFS) series at
+ * semi-Lagrangian departure points, on one AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (section 5, eq. std_dfs_exp): for every field F and point j
+ *
+ *     out[F][j] = sum_{n} sum_{m} c[F][n][m] * exp(i (m * phi_j + n * theta_j))
+ *
+ * with n over the K_theta theta (colatitude) modes and m over the K_phi phi
+ * (longitude) modes, centred: coefficient row a holds n = a - K_theta/2 and
+ * column b holds m = b - K_phi/2 (integer division).  The sign of the
+ * exponent is +i and there is no normalisation.  Section 5 recasts the
+ * evaluation as a type-II nonuniform DFT and evaluates it with an NUFFT to
+ * a user tolerance eps; this library does the same with three stages:
+ *   1. deconvolution by the kernel's Fourier transform and zero padding onto
+ *      a 2x upsampled periodic grid,
+ *   2. the 2-D inverse FFT of that grid,
+ *   3. a w x w "exponential of semicircle" kernel interpolation at each point.
+ * The relative l2 error of each field against the exact sum is about eps.
+ *
+ * Every entry point returns a status; arguments are checked before anything
+ * is enqueued and nothing is enqueued when a call fails.  Work is enqueued on
+ * the plan's HIP stream and is asynchronous with respect to the host.  A plan
+ * is not thread safe; distinct plans are independent.
+ */
+#ifndef NUFFT2_H
+#define NUFFT2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nufft2_plan_s *nufft2_handle;
+
+typedef enum {
+    NUFFT2_OK = 0,
+    NUFFT2_ERR_ARG = 1,        /* null pointer, bad size, unsupported shape */
+    NUFFT2_ERR_EPS_RANGE = 2,  /* eps below what the precision can reach */
+    NUFFT2_ERR_ALLOC = 3,      /* device allocation failed (nothing leaked) */
+    NUFFT2_ERR_NO_POINTS = 4,  /* exec before setpts */
+    NUFFT2_ERR_NONFINITE = 5,  /* check: a point coordinate was NaN or Inf */
+    NUFFT2_ERR_HIP = 6         /* HIP runtime or launch error; see info */
+} nufft2_status;
+
+typedef enum { NUFFT2_FP32 = 1, NUFFT2_FP64 = 2 } nufft2_prec;
+
+/* Optional settings; a zero field selects the default. */
+typedef struct {
+    int32_t w;            /* kernel width in fine-grid cells, 2..16; default from eps */
+    double beta_over_w;   /* kernel shape beta / w; default 2.30 */
+    int32_t tile_theta;   /* gather tile rows (power of two, 4..128); default 32 */
+    int32_t tile_phi;     /* gather tile columns (power of two, 4..128); default 32 */
+    int32_t real_output;  /* 1: write only the real part (fields known to be real) */
+    int32_t reserved;     /* must be 0 */
+} nufft2_opts;
+
+typedef struct {
+    int32_t prec;          /* nufft2_prec */
+    int32_t w;             /* kernel width */
+    double beta;           /* kernel shape parameter */
+    int64_t n_modes_theta, n_modes_phi;
+    int64_t nf_theta, nf_phi;  /* upsampled grid, powers of two >= 2 * modes */
+    int32_t n_fields;
+    int32_t real_output;
+    int32_t tile_theta, tile_phi;
+    int64_t n_bins;
+    int64_t n_pts;         /* -1 before the first setpts */
+    uint64_t workspace_bytes;
+    int32_t last_hip_error;  /* hipError_t of the last failure, 0 if none */
+    int32_t device;
+} nufft2_info;
+
+/*
+ * nufft2_plan -- create a plan for n_fields fields of n_modes_theta x
+ * n_modes_phi coefficients at tolerance eps.
+ *   prec    NUFFT2_FP32: FFT and interpolation in FP32 (coefficients and
+ *           output FP32); point coordinates are still wrapped and split in
+ *           FP64.  eps >= 1e-7.
+ *           NUFFT2_FP64: everything in FP64.  eps >= 1e-15.
+ *   The kernel width is w = ceil(log10(1/eps)) + 1 (13 at 1e-12, 7 at 1e-6)
+ *   unless opts->w is set.  The fine grid is the smallest power of two
+ *   >= max(2 * modes, 2 * w, 16) per dimension and must not exceed 4096.
+ *   opts may be NULL.  stream is a hipStream_t (NULL: the null stream).
+ *   The plan owns every device workspace; it allocates on the current device.
+ *   Errors: ERR_ARG, ERR_EPS_RANGE, ERR_ALLOC, ERR_HIP.  *out is set only on
+ *   success.
+ */
+nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, int64_t n_modes_phi,
+                          int32_t n_fields, double eps, const nufft2_opts *opts,
+                          void *stream, nufft2_handle *out);
+
+/*
+ * nufft2_setpts -- set the n_pts departure points (device arrays of FP64
+ * longitude phi and colatitude theta, any real values: both coordinates are
+ * taken modulo 2 pi on the doubled torus, so a point past a pole is given
+ * as theta < 0 or theta > pi).  Wraps, splits each coordinate into a grid
+ * cell and an offset in FP64, and bin-sorts the points; the result is kept
+ * in the plan and reused by every exec.  The caller's arrays may be reused
+ * once the plan's stream has passed this call.  n_pts = 0 is allowed.
+ * Non-finite coordinates do not fail here: their outputs are NaN and
+ * nufft2_check reports them.  Errors: ERR_ARG, ERR_ALLOC, ERR_HIP.
+ */
+nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const double *phi_dev,
+                            const double *theta_dev);
+
+/*
+ * nufft2_exec -- evaluate all fields at the current points.
+ *   coeffs_dev  [n_fields][n_modes_theta][n_modes_phi] complex (re, im
+ *               interleaved) in the plan's precision, row-major, centred.
+ *   out_dev     [n_fields][n_pts] complex in the plan's precision, in the
+ *               caller's point order; with real_output, [n_fields][n_pts] real.
+ * Both are device memory owned by the caller; they must not overlap.
+ * Errors: ERR_ARG, ERR_NO_POINTS, ERR_HIP.
+ */
+nufft2_status nufft2_exec(nufft2_handle p, const void *coeffs_dev, void *out_dev);
+
+/* nufft2_destroy -- synchronise the plan's stream and free everything. NULL is ignored. */
+nufft2_status nufft2_destroy(nufft2_handle p);
+
+/* nufft2_strerror -- static text for a status. */
+const char *nufft2_strerror(nufft2_status s);
+
+/* nufft2_get_info -- copy the plan's parameters into *info (host). */
+nufft2_status nufft2_get_info(nufft2_handle p, nufft2_info *info);
+
+/*
+ * nufft2_check -- synchronise the plan's stream and report device-side
+ * conditions: ERR_NONFINITE if the current points hold a NaN or Inf
+ * coordinate, ERR_HIP if a launch failed, else OK.
+ */
+nufft2_status nufft2_check(nufft2_handle p);
+
+/* nufft2_set_stream -- move the plan to another hipStream_t (orders after the old one). */
+nufft2_status nufft2_set_stream(nufft2_handle p, void *stream);
+
+/*
+ * Host-only helpers (no device work; usable without a GPU).
+ *
+ * nufft2_kernel_params -- the width and shape the plan would choose for eps
+ * and prec (same rule as nufft2_plan).
+ *
+ * nufft2_kernel_correction -- the deconvolution factors for K centred modes
+ * on an nf-point grid:  corr[a] = 2 / (w * Phi(pi * w * k / nf)),
+ * k = a - K/2, with Phi(xi) = int_{-1}^{1} exp(beta (sqrt(1 - z^2) - 1)) cos(xi z) dz
+ * evaluated by Gauss-Legendre quadrature in FP64.  corr is a host array of K doubles.
+ */
+nufft2_status nufft2_kernel_params(nufft2_prec prec, double eps, int32_t *w, double *beta);
+nufft2_status nufft2_kernel_correction(int64_t K, int64_t nf, int32_t w, double beta,
+                                       double *corr);
+
+/*
+ * Diagnostics for stage tests: a read-only view of a plan workspace.
+ *   which 0: fine grid   [n_fields][nf_theta][nf_phi] complex (rows not
+ *                        touched by the current points are stale)
+ *         1: point records in bin order (struct {int32 i0_theta, i0_phi;
+ *            real v_theta, v_phi}; real = plan precision)
+ *         2: permutation, int32 [n_pts]: record r belongs to point perm[r]
+ *         3: bin counts, int32 [n_bins]
+ *         4: bin starts, int32 [n_bins]
+ *         5: touched theta rows, uint8 [nf_theta]
+ *         6: theta-pass output [n_fields][nf_theta][n_modes_phi] complex
+ * *dev_ptr and *bytes describe device memory the plan owns; valid until the
+ * next setpts or destroy.  Errors: ERR_ARG, ERR_NO_POINTS (points-derived
+ * buffers before setpts).
+ */
+nufft2_status nufft2_debug_buffer(nufft2_handle p, int32_t which, void **dev_ptr,
+                                  uint64_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUFFT2_H */

@@ -1,0 +1,74 @@
+// Internal declarations shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nufft2 {
+
+template <typename T> struct cplx_sel;
+template <> struct cplx_sel<float> { using type = float2; };
+template <> struct cplx_sel<double> { using type = double2; };
+template <typename T> using cplx = typename cplx_sel<T>::type;
+
+// One departure point after setpts: the first tap's fine-grid cell in each
+// direction (already reduced modulo the grid size) and the offset
+// v = (t - i0) - floor(w/2), with t the point's coordinate in grid units.
+template <typename T> struct PointRec;
+template <> struct alignas(16) PointRec<float> { int32_t it, ip; float vt, vp; };
+template <> struct alignas(8) PointRec<double> { int32_t it, ip; double vt, vp; };
+
+// Coordinate split parameters (one per direction).
+struct AxisParams {
+    double to_grid;   // nf / (2 pi)
+    int32_t nf;       // fine grid size (power of two)
+    int32_t tile;     // bin tile size along this axis (power of two)
+};
+
+struct SetptsParams {
+    AxisParams th, ph;
+    int32_t w;
+    int32_t nbins_phi;
+    int64_t n;
+};
+
+// ---- launchers (each returns the hipError_t of its launch) ----
+hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, const double *theta,
+                         int32_t *bincount, int32_t *binstart, int64_t nbins, int2 *keyrank,
+                         uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
+                         int32_t *flags, hipStream_t s);
+
+struct FFTParams {
+    int32_t Kt, Kp;       // modes
+    int32_t nft, nfp;     // fine grid
+    int32_t log_nft, log_nfp;
+    int32_t n_fields;
+    int32_t theta_batch, log_theta_batch;   // columns per theta-pass workgroup
+    int32_t phi_batch, log_phi_batch;       // rows per phi-pass workgroup
+};
+
+hipError_t launch_theta_pass(int prec, const FFTParams &fp, const void *coeffs, const void *corr_t,
+                             const void *corr_p, const void *tw_t, const uint8_t *rowtouched,
+                             void *S, hipStream_t s);
+hipError_t launch_phi_pass(int prec, const FFTParams &fp, const void *S, const void *tw_p,
+                           const uint8_t *rowtouched, void *grid, hipStream_t s);
+
+struct GatherParams {
+    int32_t nft, nfp;
+    int32_t tile_t, tile_p;
+    int32_t nbins_phi;
+    int64_t nbins;
+    int32_t w;
+    double beta;
+    int32_t n_fields;
+    int64_t n_pts;
+    int32_t real_output;
+};
+
+hipError_t launch_gather(int prec, const GatherParams &gp, const void *grid, const void *rec,
+                         const int32_t *perm, const int32_t *bincount, const int32_t *binstart,
+                         void *out, hipStream_t s);
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace nufft2

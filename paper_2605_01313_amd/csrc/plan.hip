@@ -1,0 +1,538 @@
+// Host side of the C ABI: plan construction, kernel parameters and
+// deconvolution factors, workspace ownership, and the launch sequence of
+// setpts / exec.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "nufft2.h"
+#include "nufft2_internal.hpp"
+
+#define NUFFT2_API extern "C" __attribute__((visibility("default")))
+
+using namespace nufft2;
+
+namespace {
+
+constexpr int kMaxNf = 4096;
+constexpr int kMaxW = 16;
+constexpr double kDefaultBetaOverW = 2.30;
+constexpr int kDefaultTile = 32;
+constexpr size_t kThetaPassLdsBudget = 65536;
+constexpr size_t kGatherLdsLimit = 65536;
+
+}  // namespace
+
+struct nufft2_plan_s {
+    int prec = 0;
+    int64_t Kt = 0, Kp = 0;
+    int F = 0;
+    int w = 0;
+    double beta = 0;
+    int nft = 0, nfp = 0;
+    int tile_t = 0, tile_p = 0;
+    int nbins_t = 0, nbins_p = 0;
+    int64_t nbins = 0;
+    int real_output = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    size_t csize = 0;  // bytes per complex
+    size_t rsize = 0;  // bytes per real
+    FFTParams fp{};
+
+    // device workspaces
+    void *corr_t = nullptr, *corr_p = nullptr;
+    void *tw_t = nullptr, *tw_p = nullptr;
+    void *S = nullptr, *grid = nullptr;
+    int32_t *bincount = nullptr, *binstart = nullptr;
+    uint8_t *rowmark = nullptr, *rowtouched = nullptr;
+    int32_t *flags = nullptr;
+    // point workspaces (grown by setpts)
+    int64_t pts_cap = 0;
+    int2 *keyrank = nullptr;
+    void *rec = nullptr;
+    int32_t *perm = nullptr;
+
+    int64_t n_pts = -1;
+    size_t ws_bytes = 0;
+    hipError_t last_err = hipSuccess;
+};
+
+namespace {
+
+int ilog2(int64_t x)
+{
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// w = ceil(log10(1/eps)) + 1 at upsampling 2 (13 for 1e-12, 7 for 1e-6).
+nufft2_status kernel_params(int prec, double eps, int32_t *w_out, double *beta_out)
+{
+    if (!(eps > 0.0) || !isfinite(eps)) return NUFFT2_ERR_ARG;
+    if (prec != NUFFT2_FP32 && prec != NUFFT2_FP64) return NUFFT2_ERR_ARG;
+    const double floor_eps = prec == NUFFT2_FP32 ? 1e-7 : 1e-15;
+    if (eps < floor_eps * (1.0 - 1e-12)) return NUFFT2_ERR_EPS_RANGE;
+    int w = (int)ceil(-log10(eps) - 1e-9) + 1;
+    if (w < 2) w = 2;
+    if (w > kMaxW) w = kMaxW;
+    *w_out = w;
+    *beta_out = kDefaultBetaOverW * w;
+    return NUFFT2_OK;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n, long double).
+void gauss_legendre(int n, std::vector<long double> &x, std::vector<long double> &wt)
+{
+    x.assign(n, 0.0L);
+    wt.assign(n, 0.0L);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        long double z = cosl(pi * (i + 0.75L) / (n + 0.5L)), pp = 1.0L;
+        for (int it = 0; it < 100; ++it) {
+            long double p1 = 1.0L, p2 = 0.0L;
+            for (int j = 1; j <= n; ++j) {
+                const long double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0L * j - 1.0L) * z * p2 - (j - 1.0L) * p3) / j;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1.0L);
+            const long double z1 = z;
+            z = z1 - p1 / pp;
+            if (fabsl(z - z1) < 1e-19L) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        wt[i] = wt[n - 1 - i] = 2.0L / ((1.0L - z * z) * pp * pp);
+    }
+}
+
+// Phi(xi) = int_{-1}^{1} exp(beta (sqrt(1 - z^2) - 1)) cos(xi z) dz, by the
+// substitution z = sin s (which removes the square-root edge of the kernel)
+// and Gauss-Legendre in s on [-pi/2, pi/2].
+long double kernel_ft(long double xi, long double beta, const std::vector<long double> &x,
+                      const std::vector<long double> &wt)
+{
+    const long double half_pi = 1.570796326794896619231321691639751442L;
+    long double acc = 0.0L;
+    for (size_t q = 0; q < x.size(); ++q) {
+        const long double s = half_pi * x[q];
+        const long double cs = cosl(s);
+        acc += wt[q] * expl(beta * (cs - 1.0L)) * cosl(xi * sinl(s)) * cs;
+    }
+    return acc * half_pi;
+}
+
+nufft2_status kernel_correction(int64_t K, int64_t nf, int w, double beta, double *corr)
+{
+    if (K <= 0 || nf <= 0 || w < 2 || w > kMaxW || !(beta > 0) || !corr) return NUFFT2_ERR_ARG;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<long double> prev(K), cur(K), x, wt;
+    // Double the node count until no factor moves by more than 1e-16 relative.
+    for (int n = 32;; n *= 2) {
+        gauss_legendre(n, x, wt);
+        long double change = 0.0L;
+        for (int64_t a = 0; a < K; ++a) {
+            const long double k = (long double)(a - K / 2);
+            cur[a] = kernel_ft(pi * w * k / (long double)nf, beta, x, wt);
+            if (n > 32) {
+                const long double d = fabsl(cur[a] - prev[a]) / fabsl(cur[a]);
+                if (d > change) change = d;
+            }
+        }
+        prev.swap(cur);
+        if ((n > 32 && change < 1e-17L) || n >= 2048) break;
+    }
+    for (int64_t a = 0; a < K; ++a) corr[a] = (double)(2.0L / ((long double)w * prev[a]));
+    return NUFFT2_OK;
+}
+
+template <typename T> void fill_twiddles(std::vector<T> &buf, int N)
+{
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    buf.resize(2 * (size_t)N);
+    for (int t = 0; t < N; ++t) {
+        const long double ang = two_pi * (long double)t / (long double)N;
+        buf[2 * t] = (T)cosl(ang);
+        buf[2 * t + 1] = (T)sinl(ang);
+    }
+}
+
+void free_all(nufft2_plan_s *p)
+{
+    void *ptrs[] = {p->corr_t, p->corr_p, p->tw_t,  p->tw_p,     p->S,     p->grid,
+                    p->bincount, p->binstart, p->rowmark, p->rowtouched, p->flags, p->keyrank,
+                    p->rec,    p->perm};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    p->corr_t = p->corr_p = p->tw_t = p->tw_p = p->S = p->grid = nullptr;
+    p->bincount = p->binstart = p->flags = p->perm = nullptr;
+    p->rowmark = p->rowtouched = nullptr;
+    p->keyrank = nullptr;
+    p->rec = nullptr;
+}
+
+bool dev_alloc(nufft2_plan_s *p, void **ptr, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(ptr, bytes) != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return false;
+    }
+    p->ws_bytes += bytes;
+    return true;
+}
+
+nufft2_status fail_hip(nufft2_plan_s *p, hipError_t e)
+{
+    p->last_err = e;
+    return NUFFT2_ERR_HIP;
+}
+
+template <typename T> nufft2_status upload_tables(nufft2_plan_s *p)
+{
+    std::vector<double> ct(p->Kt), cp(p->Kp);
+    nufft2_status st = kernel_correction(p->Kt, p->nft, p->w, p->beta, ct.data());
+    if (st != NUFFT2_OK) return st;
+    st = kernel_correction(p->Kp, p->nfp, p->w, p->beta, cp.data());
+    if (st != NUFFT2_OK) return st;
+    std::vector<T> ctT(ct.begin(), ct.end()), cpT(cp.begin(), cp.end());
+    std::vector<T> twt, twp;
+    fill_twiddles<T>(twt, p->nft);
+    fill_twiddles<T>(twp, p->nfp);
+    hipError_t e;
+    if ((e = hipMemcpy(p->corr_t, ctT.data(), sizeof(T) * ctT.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->corr_p, cpT.data(), sizeof(T) * cpT.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->tw_t, twt.data(), sizeof(T) * twt.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->tw_p, twp.data(), sizeof(T) * twp.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail_hip(p, e);
+    return NUFFT2_OK;
+}
+
+int choose_tile(int32_t requested, int nf, bool *bad)
+{
+    int t = requested > 0 ? requested : kDefaultTile;
+    if (requested > 0 && (!is_pow2(requested) || requested < 4 || requested > 128)) *bad = true;
+    if (t > nf) t = nf;
+    return t;
+}
+
+}  // namespace
+
+NUFFT2_API const char *nufft2_strerror(nufft2_status s)
+{
+    switch (s) {
+    case NUFFT2_OK: return "ok";
+    case NUFFT2_ERR_ARG: return "invalid argument";
+    case NUFFT2_ERR_EPS_RANGE: return "tolerance below what the precision can reach";
+    case NUFFT2_ERR_ALLOC: return "device allocation failed";
+    case NUFFT2_ERR_NO_POINTS: return "exec before setpts";
+    case NUFFT2_ERR_NONFINITE: return "non-finite point coordinate";
+    case NUFFT2_ERR_HIP: return "HIP runtime or launch error";
+    }
+    return "unknown status";
+}
+
+NUFFT2_API nufft2_status nufft2_kernel_params(nufft2_prec prec, double eps, int32_t *w, double *beta)
+{
+    if (!w || !beta) return NUFFT2_ERR_ARG;
+    return kernel_params(prec, eps, w, beta);
+}
+
+NUFFT2_API nufft2_status nufft2_kernel_correction(int64_t K, int64_t nf, int32_t w, double beta,
+                                                  double *corr)
+{
+    return kernel_correction(K, nf, w, beta, corr);
+}
+
+NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, int64_t n_modes_phi,
+                                     int32_t n_fields, double eps, const nufft2_opts *opts,
+                                     void *stream, nufft2_handle *out)
+{
+    if (!out) return NUFFT2_ERR_ARG;
+    if (prec != NUFFT2_FP32 && prec != NUFFT2_FP64) return NUFFT2_ERR_ARG;
+    if (n_modes_theta <= 0 || n_modes_phi <= 0 || n_fields <= 0) return NUFFT2_ERR_ARG;
+    if (n_modes_theta > kMaxNf / 2 || n_modes_phi > kMaxNf / 2) return NUFFT2_ERR_ARG;
+    nufft2_opts o{};
+    if (opts) o = *opts;
+    if (o.reserved != 0 || o.w < 0 || o.w > kMaxW || o.w == 1 || o.beta_over_w < 0 ||
+        !isfinite(o.beta_over_w) || (o.real_output != 0 && o.real_output != 1))
+        return NUFFT2_ERR_ARG;
+
+    int32_t w;
+    double beta;
+    nufft2_status st = kernel_params(prec, eps, &w, &beta);
+    if (st != NUFFT2_OK) return st;
+    if (o.w > 0) w = o.w;
+    beta = (o.beta_over_w > 0 ? o.beta_over_w : kDefaultBetaOverW) * w;
+
+    auto fine = [&](int64_t K) {
+        int64_t n = 2 * K;
+        if (n < 2 * w) n = 2 * w;
+        if (n < 16) n = 16;
+        return int64_t(1) << ilog2(n);
+    };
+    const int64_t nft = fine(n_modes_theta), nfp = fine(n_modes_phi);
+    if (nft > kMaxNf || nfp > kMaxNf) return NUFFT2_ERR_ARG;
+    if ((int64_t)n_fields * nft * nfp > (int64_t(1) << 34)) return NUFFT2_ERR_ARG;
+
+    bool bad_tile = false;
+    const int tt = choose_tile(o.tile_theta, (int)nft, &bad_tile);
+    const int tp = choose_tile(o.tile_phi, (int)nfp, &bad_tile);
+    if (bad_tile) return NUFFT2_ERR_ARG;
+    {
+        // the gather stages a (tile + w - 1)^2 patch of one field in LDS
+        const size_t cs = prec == NUFFT2_FP32 ? sizeof(float2) : sizeof(double2);
+        if (cs * (size_t)(tt + w - 1) * (size_t)(tp + w - 1) > kGatherLdsLimit) return NUFFT2_ERR_ARG;
+    }
+
+    nufft2_plan_s *p = new (std::nothrow) nufft2_plan_s();
+    if (!p) return NUFFT2_ERR_ALLOC;
+    p->prec = prec;
+    p->Kt = n_modes_theta;
+    p->Kp = n_modes_phi;
+    p->F = n_fields;
+    p->w = w;
+    p->beta = beta;
+    p->nft = (int)nft;
+    p->nfp = (int)nfp;
+    p->tile_t = tt;
+    p->tile_p = tp;
+    p->nbins_t = (int)(nft / tt);
+    p->nbins_p = (int)(nfp / tp);
+    p->nbins = (int64_t)p->nbins_t * p->nbins_p;
+    p->real_output = o.real_output;
+    p->stream = (hipStream_t)stream;
+    p->csize = prec == NUFFT2_FP32 ? sizeof(float2) : sizeof(double2);
+    p->rsize = prec == NUFFT2_FP32 ? sizeof(float) : sizeof(double);
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        hipError_t e = hipGetLastError();
+        (void)e;
+        delete p;
+        return NUFFT2_ERR_HIP;
+    }
+
+    FFTParams &fp = p->fp;
+    fp.Kt = (int)p->Kt;
+    fp.Kp = (int)p->Kp;
+    fp.nft = p->nft;
+    fp.nfp = p->nfp;
+    fp.log_nft = ilog2(p->nft);
+    fp.log_nfp = ilog2(p->nfp);
+    fp.n_fields = p->F;
+    {
+        int64_t b = (int64_t)(kThetaPassLdsBudget / (p->csize * (size_t)p->nft));
+        if (b > 64) b = 64;
+        if (b < 1) b = 1;
+        while ((int64_t)p->nft * b < 1024) b *= 2;
+        while ((int64_t)p->nft * b > 16384) b /= 2;
+        b = int64_t(1) << (ilog2(b + 1) - 1);  // power of two not above b
+        fp.theta_batch = (int)b;
+        fp.log_theta_batch = ilog2(b);
+    }
+    {
+        int64_t b = 4096 / p->nfp;
+        if (b < 1) b = 1;
+        if (b > p->nft) b = p->nft;
+        fp.phi_batch = (int)b;
+        fp.log_phi_batch = ilog2(b);
+    }
+
+    const size_t rs = p->rsize, cs = p->csize;
+    bool ok = dev_alloc(p, &p->corr_t, rs * p->Kt) && dev_alloc(p, &p->corr_p, rs * p->Kp) &&
+              dev_alloc(p, &p->tw_t, cs * p->nft) && dev_alloc(p, &p->tw_p, cs * p->nfp) &&
+              dev_alloc(p, &p->S, cs * (size_t)p->F * p->nft * p->Kp) &&
+              dev_alloc(p, &p->grid, cs * (size_t)p->F * p->nft * p->nfp) &&
+              dev_alloc(p, (void **)&p->bincount, sizeof(int32_t) * (size_t)p->nbins) &&
+              dev_alloc(p, (void **)&p->binstart, sizeof(int32_t) * (size_t)p->nbins) &&
+              dev_alloc(p, (void **)&p->rowmark, (size_t)p->nft) &&
+              dev_alloc(p, (void **)&p->rowtouched, (size_t)p->nft) &&
+              dev_alloc(p, (void **)&p->flags, sizeof(int32_t) * 4);
+    if (!ok) {
+        free_all(p);
+        delete p;
+        return NUFFT2_ERR_ALLOC;
+    }
+    st = prec == NUFFT2_FP32 ? upload_tables<float>(p) : upload_tables<double>(p);
+    if (st == NUFFT2_OK) {
+        hipError_t e;
+        if ((e = hipMemset(p->S, 0, cs * (size_t)p->F * p->nft * p->Kp)) != hipSuccess ||
+            (e = hipMemset(p->grid, 0, cs * (size_t)p->F * p->nft * p->nfp)) != hipSuccess ||
+            (e = hipMemset(p->rowtouched, 0, (size_t)p->nft)) != hipSuccess ||
+            (e = hipMemset(p->flags, 0, sizeof(int32_t) * 4)) != hipSuccess ||
+            (e = hipDeviceSynchronize()) != hipSuccess)
+            st = NUFFT2_ERR_HIP;
+    }
+    if (st != NUFFT2_OK) {
+        free_all(p);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const double *phi_dev,
+                                       const double *theta_dev)
+{
+    if (!p || n_pts < 0 || n_pts > (int64_t)0x7fffffff) return NUFFT2_ERR_ARG;
+    if (n_pts > 0 && (!phi_dev || !theta_dev)) return NUFFT2_ERR_ARG;
+    if (n_pts > p->pts_cap) {
+        // grow the point workspaces; wait for work that may still use them
+        hipError_t e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return fail_hip(p, e);
+        void *ptrs[] = {p->keyrank, p->rec, p->perm};
+        for (void *q : ptrs)
+            if (q) (void)hipFree(q);
+        p->ws_bytes -= (size_t)p->pts_cap * (sizeof(int2) + 2 * p->rsize + 8 + sizeof(int32_t));
+        p->keyrank = nullptr;
+        p->rec = nullptr;
+        p->perm = nullptr;
+        p->pts_cap = 0;
+        p->n_pts = -1;
+        const size_t recsz = p->prec == NUFFT2_FP32 ? sizeof(PointRec<float>) : sizeof(PointRec<double>);
+        const size_t before = p->ws_bytes;
+        if (!dev_alloc(p, (void **)&p->keyrank, sizeof(int2) * (size_t)n_pts) ||
+            !dev_alloc(p, &p->rec, recsz * (size_t)n_pts) ||
+            !dev_alloc(p, (void **)&p->perm, sizeof(int32_t) * (size_t)n_pts)) {
+            void *q2[] = {p->keyrank, p->rec, p->perm};
+            for (void *q : q2)
+                if (q) (void)hipFree(q);
+            p->keyrank = nullptr;
+            p->rec = nullptr;
+            p->perm = nullptr;
+            p->ws_bytes = before;
+            return NUFFT2_ERR_ALLOC;
+        }
+        p->ws_bytes = before + (size_t)n_pts * (sizeof(int2) + 2 * p->rsize + 8 + sizeof(int32_t));
+        p->pts_cap = n_pts;
+    }
+    SetptsParams sp{};
+    const double inv_two_pi = 0.15915494309189533576888376337251436;
+    sp.th.to_grid = (double)p->nft * inv_two_pi;
+    sp.th.nf = p->nft;
+    sp.th.tile = p->tile_t;
+    sp.ph.to_grid = (double)p->nfp * inv_two_pi;
+    sp.ph.nf = p->nfp;
+    sp.ph.tile = p->tile_p;
+    sp.w = p->w;
+    sp.nbins_phi = p->nbins_p;
+    sp.n = n_pts;
+    hipError_t e = launch_setpts(p->prec, sp, phi_dev, theta_dev, p->bincount, p->binstart, p->nbins,
+                                 p->keyrank, p->rowmark, p->rowtouched, p->rec, p->perm, p->flags,
+                                 p->stream);
+    if (e != hipSuccess) return fail_hip(p, e);
+    p->n_pts = n_pts;
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_exec(nufft2_handle p, const void *coeffs_dev, void *out_dev)
+{
+    if (!p) return NUFFT2_ERR_ARG;
+    if (p->n_pts < 0) return NUFFT2_ERR_NO_POINTS;
+    if (p->n_pts == 0) return NUFFT2_OK;
+    if (!coeffs_dev || !out_dev) return NUFFT2_ERR_ARG;
+    hipError_t e = launch_theta_pass(p->prec, p->fp, coeffs_dev, p->corr_t, p->corr_p, p->tw_t,
+                                     p->rowtouched, p->S, p->stream);
+    if (e != hipSuccess) return fail_hip(p, e);
+    e = launch_phi_pass(p->prec, p->fp, p->S, p->tw_p, p->rowtouched, p->grid, p->stream);
+    if (e != hipSuccess) return fail_hip(p, e);
+    GatherParams gp{};
+    gp.nft = p->nft;
+    gp.nfp = p->nfp;
+    gp.tile_t = p->tile_t;
+    gp.tile_p = p->tile_p;
+    gp.nbins_phi = p->nbins_p;
+    gp.nbins = p->nbins;
+    gp.w = p->w;
+    gp.beta = p->beta;
+    gp.n_fields = p->F;
+    gp.n_pts = p->n_pts;
+    gp.real_output = p->real_output;
+    e = launch_gather(p->prec, gp, p->grid, p->rec, p->perm, p->bincount, p->binstart, out_dev,
+                      p->stream);
+    if (e != hipSuccess) return fail_hip(p, e);
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_check(nufft2_handle p)
+{
+    if (!p) return NUFFT2_ERR_ARG;
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return fail_hip(p, e);
+    if (p->last_err != hipSuccess) return NUFFT2_ERR_HIP;
+    int32_t flags = 0;
+    e = hipMemcpy(&flags, p->flags, sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail_hip(p, e);
+    if (p->n_pts > 0 && (flags & 1)) return NUFFT2_ERR_NONFINITE;
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_set_stream(nufft2_handle p, void *stream)
+{
+    if (!p) return NUFFT2_ERR_ARG;
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return fail_hip(p, e);
+    p->stream = (hipStream_t)stream;
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_destroy(nufft2_handle p)
+{
+    if (!p) return NUFFT2_OK;
+    (void)hipStreamSynchronize(p->stream);
+    free_all(p);
+    delete p;
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_get_info(nufft2_handle p, nufft2_info *info)
+{
+    if (!p || !info) return NUFFT2_ERR_ARG;
+    memset(info, 0, sizeof(*info));
+    info->prec = p->prec;
+    info->w = p->w;
+    info->beta = p->beta;
+    info->n_modes_theta = p->Kt;
+    info->n_modes_phi = p->Kp;
+    info->nf_theta = p->nft;
+    info->nf_phi = p->nfp;
+    info->n_fields = p->F;
+    info->real_output = p->real_output;
+    info->tile_theta = p->tile_t;
+    info->tile_phi = p->tile_p;
+    info->n_bins = p->nbins;
+    info->n_pts = p->n_pts;
+    info->workspace_bytes = p->ws_bytes;
+    info->last_hip_error = (int32_t)p->last_err;
+    info->device = p->device;
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_debug_buffer(nufft2_handle p, int32_t which, void **dev_ptr,
+                                             uint64_t *bytes)
+{
+    if (!p || !dev_ptr || !bytes) return NUFFT2_ERR_ARG;
+    const bool needs_pts = which == 1 || which == 2;
+    if (needs_pts && p->n_pts < 0) return NUFFT2_ERR_NO_POINTS;
+    const size_t recsz = p->prec == NUFFT2_FP32 ? sizeof(PointRec<float>) : sizeof(PointRec<double>);
+    switch (which) {
+    case 0: *dev_ptr = p->grid; *bytes = p->csize * (size_t)p->F * p->nft * p->nfp; break;
+    case 1: *dev_ptr = p->rec; *bytes = recsz * (size_t)p->n_pts; break;
+    case 2: *dev_ptr = p->perm; *bytes = sizeof(int32_t) * (size_t)p->n_pts; break;
+    case 3: *dev_ptr = p->bincount; *bytes = sizeof(int32_t) * (size_t)p->nbins; break;
+    case 4: *dev_ptr = p->binstart; *bytes = sizeof(int32_t) * (size_t)p->nbins; break;
+    case 5: *dev_ptr = p->rowtouched; *bytes = (size_t)p->nft; break;
+    case 6: *dev_ptr = p->S; *bytes = p->csize * (size_t)p->F * p->nft * p->Kp; break;
+    default: return NUFFT2_ERR_ARG;
+    }
+    return NUFFT2_OK;
+}

@@ -1,0 +1,258 @@
+"""Python binding of libnufft2.so: the C ABI of include/nufft2.h, same names.
+
+Argument marshalling only: every step of the interpolation runs in the HIP
+kernels behind the C ABI.  PyTorch is used for device memory and the current
+stream in the `Plan` convenience class; the `nufft2_*` functions take raw
+device pointers (ints) like the C functions do.
+
+If the library has not been built this module raises on import; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnufft2.so")
+
+NUFFT2_OK = 0
+NUFFT2_ERR_ARG = 1
+NUFFT2_ERR_EPS_RANGE = 2
+NUFFT2_ERR_ALLOC = 3
+NUFFT2_ERR_NO_POINTS = 4
+NUFFT2_ERR_NONFINITE = 5
+NUFFT2_ERR_HIP = 6
+
+NUFFT2_FP32 = 1
+NUFFT2_FP64 = 2
+
+EXPORTED = (
+    "nufft2_plan", "nufft2_setpts", "nufft2_exec", "nufft2_destroy", "nufft2_strerror",
+    "nufft2_get_info", "nufft2_check", "nufft2_set_stream", "nufft2_kernel_params",
+    "nufft2_kernel_correction", "nufft2_debug_buffer",
+)
+
+
+class nufft2_opts(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_int32), ("beta_over_w", ctypes.c_double),
+                ("tile_theta", ctypes.c_int32), ("tile_phi", ctypes.c_int32),
+                ("real_output", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class nufft2_info(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("w", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("n_modes_theta", ctypes.c_int64), ("n_modes_phi", ctypes.c_int64),
+                ("nf_theta", ctypes.c_int64), ("nf_phi", ctypes.c_int64),
+                ("n_fields", ctypes.c_int32), ("real_output", ctypes.c_int32),
+                ("tile_theta", ctypes.c_int32), ("tile_phi", ctypes.c_int32),
+                ("n_bins", ctypes.c_int64), ("n_pts", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_uint64), ("last_hip_error", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`"
+            " (there is no non-HIP fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    H = ctypes.c_void_p
+    sigs = {
+        "nufft2_plan": [i32, i64, i64, i32, dbl, ctypes.POINTER(nufft2_opts), vp, ctypes.POINTER(H)],
+        "nufft2_setpts": [H, i64, vp, vp],
+        "nufft2_exec": [H, vp, vp],
+        "nufft2_destroy": [H],
+        "nufft2_get_info": [H, ctypes.POINTER(nufft2_info)],
+        "nufft2_check": [H],
+        "nufft2_set_stream": [H, vp],
+        "nufft2_kernel_params": [i32, dbl, ctypes.POINTER(i32), ctypes.POINTER(dbl)],
+        "nufft2_kernel_correction": [i64, i64, i32, dbl, vp],
+        "nufft2_debug_buffer": [H, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_uint64)],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.nufft2_strerror.argtypes = [ctypes.c_int]
+    lib.nufft2_strerror.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+class Nufft2Error(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {nufft2_strerror(status)} (status {status})")
+
+
+def _check(status, where):
+    if status != NUFFT2_OK:
+        raise Nufft2Error(status, where)
+
+
+# ---- the C ABI, one function each ------------------------------------------
+def nufft2_strerror(status: int) -> str:
+    return _lib.nufft2_strerror(int(status)).decode()
+
+
+def nufft2_plan(prec, n_modes_theta, n_modes_phi, n_fields, eps, opts=None, stream=0):
+    """Returns (status, handle)."""
+    h = ctypes.c_void_p()
+    po = ctypes.byref(opts) if opts is not None else None
+    st = _lib.nufft2_plan(int(prec), int(n_modes_theta), int(n_modes_phi), int(n_fields),
+                          float(eps), po, ctypes.c_void_p(stream or None), ctypes.byref(h))
+    return st, h
+
+
+def nufft2_setpts(handle, n_pts, phi_ptr, theta_ptr):
+    return _lib.nufft2_setpts(handle, int(n_pts), ctypes.c_void_p(phi_ptr or None),
+                              ctypes.c_void_p(theta_ptr or None))
+
+
+def nufft2_exec(handle, coeffs_ptr, out_ptr):
+    return _lib.nufft2_exec(handle, ctypes.c_void_p(coeffs_ptr or None),
+                            ctypes.c_void_p(out_ptr or None))
+
+
+def nufft2_destroy(handle):
+    return _lib.nufft2_destroy(handle)
+
+
+def nufft2_get_info(handle):
+    info = nufft2_info()
+    st = _lib.nufft2_get_info(handle, ctypes.byref(info))
+    return st, info
+
+
+def nufft2_check(handle):
+    return _lib.nufft2_check(handle)
+
+
+def nufft2_set_stream(handle, stream):
+    return _lib.nufft2_set_stream(handle, ctypes.c_void_p(stream or None))
+
+
+def nufft2_kernel_params(prec, eps):
+    w = ctypes.c_int32()
+    beta = ctypes.c_double()
+    st = _lib.nufft2_kernel_params(int(prec), float(eps), ctypes.byref(w), ctypes.byref(beta))
+    return st, w.value, beta.value
+
+
+def nufft2_kernel_correction(K, nf, w, beta):
+    import numpy as np
+    out = np.zeros(int(K), dtype=np.float64)
+    st = _lib.nufft2_kernel_correction(int(K), int(nf), int(w), float(beta), out.ctypes.data)
+    return st, out
+
+
+def nufft2_debug_buffer(handle, which):
+    ptr = ctypes.c_void_p()
+    nbytes = ctypes.c_uint64()
+    st = _lib.nufft2_debug_buffer(handle, int(which), ctypes.byref(ptr), ctypes.byref(nbytes))
+    return st, (ptr.value or 0), nbytes.value
+
+
+# ---- torch convenience -----------------------------------------------------
+class Plan:
+    """A plan bound to torch tensors on the current device and stream.
+
+    >>> p = Plan("fp32", K, K, n_fields=3, eps=1e-6)
+    >>> p.setpts(phi, theta)            # float64 device tensors
+    >>> out = p.exec(coeffs)            # complex64 device tensor (F, K, K)
+    """
+
+    def __init__(self, prec, n_modes_theta, n_modes_phi, n_fields=1, eps=1e-6, *, w=0,
+                 beta_over_w=0.0, tile_theta=0, tile_phi=0, real_output=False, stream=None):
+        import torch
+        self._torch = torch
+        self.prec = {"fp32": NUFFT2_FP32, "fp64": NUFFT2_FP64,
+                     NUFFT2_FP32: NUFFT2_FP32, NUFFT2_FP64: NUFFT2_FP64}[prec]
+        self.cdtype = torch.complex64 if self.prec == NUFFT2_FP32 else torch.complex128
+        self.rdtype = torch.float32 if self.prec == NUFFT2_FP32 else torch.float64
+        self.shape = (int(n_fields), int(n_modes_theta), int(n_modes_phi))
+        self.real_output = bool(real_output)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        opts = nufft2_opts(int(w), float(beta_over_w), int(tile_theta), int(tile_phi),
+                           int(bool(real_output)), 0)
+        st, h = nufft2_plan(self.prec, n_modes_theta, n_modes_phi, n_fields, eps, opts,
+                            self.stream.cuda_stream)
+        _check(st, "nufft2_plan")
+        self.handle = h
+        self._pts = None
+        self.n_pts = -1
+
+    def info(self):
+        st, info = nufft2_get_info(self.handle)
+        _check(st, "nufft2_get_info")
+        return info.as_dict()
+
+    def setpts(self, phi, theta):
+        t = self._torch
+        for x in (phi, theta):
+            if x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous():
+                raise TypeError("points must be contiguous float64 device tensors")
+        if phi.numel() != theta.numel():
+            raise ValueError("phi and theta differ in length")
+        n = phi.numel()
+        _check(nufft2_setpts(self.handle, n, phi.data_ptr() if n else 0,
+                             theta.data_ptr() if n else 0), "nufft2_setpts")
+        self._pts = (phi, theta)   # keep alive until the stream has consumed them
+        self.n_pts = n
+
+    def exec(self, coeffs, out=None):
+        t = self._torch
+        if coeffs.dtype != self.cdtype or not coeffs.is_cuda or not coeffs.is_contiguous():
+            raise TypeError(f"coeffs must be a contiguous {self.cdtype} device tensor")
+        if tuple(coeffs.shape) != self.shape and tuple(coeffs.shape) != self.shape[1:]:
+            raise ValueError(f"coeffs shape {tuple(coeffs.shape)} != {self.shape}")
+        F = self.shape[0]
+        if out is None:
+            dt = self.rdtype if self.real_output else self.cdtype
+            out = t.empty((F, max(self.n_pts, 0)), dtype=dt, device=coeffs.device)
+        _check(nufft2_exec(self.handle, coeffs.data_ptr(), out.data_ptr() if out.numel() else 0),
+               "nufft2_exec")
+        return out
+
+    def check(self):
+        st = nufft2_check(self.handle)
+        return st
+
+    def debug_buffer(self, which):
+        st, ptr, nbytes = nufft2_debug_buffer(self.handle, which)
+        _check(st, "nufft2_debug_buffer")
+        return ptr, nbytes
+
+    def debug_tensor(self, which, dtype, shape):
+        """Copy a plan workspace into a new device tensor (stage tests)."""
+        t = self._torch
+        ptr, nbytes = self.debug_buffer(which)
+        out = t.empty(shape, dtype=dtype, device="cuda")
+        assert out.numel() * out.element_size() <= nbytes
+        import ctypes as _ct
+        hip = _ct.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [_ct.c_void_p, _ct.c_void_p, _ct.c_size_t, _ct.c_int]
+        self._torch.cuda.synchronize()
+        rc = hip.hipMemcpy(_ct.c_void_p(out.data_ptr()), _ct.c_void_p(ptr),
+                           out.numel() * out.element_size(), 3)
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpy failed ({rc})")
+        return out
+
+    def destroy(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            nufft2_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
