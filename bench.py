@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Throughput of the departure-point NUFFT interpolation on one MI355X.
+
+A step is one pass of the whole path over one departure-point set: setpts
+(wrap/split/sort of the points) and exec (deconvolve + pad, 2-D inverse FFT,
+ES gather) for all fields.  The workload is the 256 x 512 lat-lon grid
+(512 x 512 doubled torus), 3 fields (h, u, v) with a (1 + k^2 + l^2)^-1.5
+spectrum, 131,072 departure points of a solid-body-rotation wind; the
+headline value is the FP32 plan at eps = 1e-6 (w = 7), and the FP64 plan at
+eps = 1e-12 (w = 13) is reported beside it.  Inputs are resident in HBM
+before the timed region starts.
+
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "departure-pt interps/s (points*fields) at eps 1e-6 FP32 vs 1e-12 FP64; p99 latency"
+HBM_PEAK_GBS = 8000.0
+STAGES = ("setpts", "theta_pass", "phi_pass", "gather")
+KERNEL_SOURCES = {"setpts": "setpts.hip", "theta_pass": "fft.hip", "phi_pass": "fft.hip",
+                  "gather": "gather.hip"}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(stage):
+    path = os.path.join(ROOT, "paper_2605_01313_amd", "csrc", KERNEL_SOURCES[stage])
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def stage_bytes(stage, info, n_touched, real_output=False):
+    """Algorithmic HBM bytes of one launch of a stage (each datum moved once)."""
+    F, P = info["n_fields"], info["n_pts"]
+    Kt, Kp, nfp = info["n_modes_theta"], info["n_modes_phi"], info["nf_phi"]
+    cs = 8 if info["prec"] == 1 else 16
+    rs = cs // 2
+    rec = 16 if info["prec"] == 1 else 24
+    if stage == "setpts":
+        return P * (16 + rec + 4)
+    if stage == "theta_pass":
+        return F * Kt * Kp * cs + F * n_touched * Kp * cs
+    if stage == "phi_pass":
+        return F * n_touched * Kp * cs + F * n_touched * nfp * cs
+    if stage == "gather":
+        return F * n_touched * nfp * cs + P * (rec + 4) + F * P * (rs if real_output else cs)
+    raise KeyError(stage)
+
+
+def read_traffic(stage, workload, prec):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or None
+    if there is none or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{stage}_{workload}_{prec}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != source_hash(stage):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+class Runner:
+    def __init__(self, torch, wl, prec, eps):
+        from paper_2605_01313_amd import Plan
+        self.torch = torch
+        dev = torch.device("cuda:0")
+        F, Kt, Kp = wl.coeffs.shape
+        self.prec = prec
+        self.plan = Plan(prec, Kt, Kp, n_fields=F, eps=eps)
+        cdt = torch.complex64 if prec == "fp32" else torch.complex128
+        self.coeffs = torch.from_numpy(wl.coeffs).to(dev).to(cdt).contiguous()
+        self.phi = torch.from_numpy(wl.phi).to(dev).contiguous()
+        self.theta = torch.from_numpy(wl.theta).to(dev).contiguous()
+        self.out = torch.empty((F, wl.n_pts), dtype=cdt, device=dev)
+        self.n_pf = F * wl.n_pts
+        self.step()
+        torch.cuda.synchronize()
+        self.info = self.plan.info()
+        touched = self.plan.debug_tensor(4, torch.uint8, (self.info["nf_theta"],))
+        self.n_touched = int(touched.sum().item())
+
+    def step(self):
+        self.plan.setpts(self.phi, self.theta)
+        self.plan.exec(self.coeffs, self.out)
+
+    def timed(self, steps, warmup):
+        torch = self.torch
+        # warmup with every stage bracketed, to find the dominant kernel
+        self.plan.profile(0b1111)
+        for _ in range(max(warmup, 1)):
+            self.step()
+        prof = self.plan.profile_read()
+        avg = {k: (ms / n if n else 0.0) for k, (ms, n) in prof.items()}
+        dominant = max(avg, key=avg.get)
+        # timed region: only the dominant kernel is bracketed
+        self.plan.profile(1 << STAGES.index(dominant))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        live = self.plan.profile_read()[dominant]
+        self.plan.profile(0)
+        ms_step = (t1 - t0) * 1e3 / steps
+        dom_ms = live[0] / max(live[1], 1)
+        # per-step latency distribution (separate loop, events around each step)
+        lat = []
+        s = torch.cuda.current_stream()
+        for _ in range(min(steps, 200)):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            self.step()
+            b.record(s)
+            b.synchronize()
+            lat.append(a.elapsed_time(b))
+        lat.sort()
+        pct = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]
+        return {"ms_per_step": ms_step, "stage_avg_ms": avg, "dominant": dominant,
+                "dominant_ms": dom_ms, "p50_ms": pct(0.50), "p99_ms": pct(0.99)}
+
+
+def cpu_baseline(wl, gpu_out, target_s):
+    """The oracle (FP64 direct sum) on host cores, on a bounded sample of points."""
+    import numpy as np
+
+    import oracle
+    import synth
+    cores = oracle.num_threads()
+    F = wl.coeffs.shape[0]
+    calib = synth.sample_indices(wl.n_pts, 64, seed=99)
+    t0 = time.perf_counter()
+    oracle.dfs_eval(wl.coeffs, wl.phi[calib], wl.theta[calib])
+    per_pt = (time.perf_counter() - t0) / calib.size
+    n = int(min(wl.n_pts, max(256, target_s / max(per_pt, 1e-9))))
+    idx = synth.sample_indices(wl.n_pts, n, seed=15)
+    t0 = time.perf_counter()
+    ref = oracle.dfs_eval(wl.coeffs, wl.phi[idx], wl.theta[idx])
+    dt = time.perf_counter() - t0
+    errs = {}
+    for name, out in gpu_out.items():
+        e = [float(np.linalg.norm(out[f, idx] - ref[f]) / np.linalg.norm(ref[f])) for f in range(F)]
+        errs[name] = max(e)
+    return {"value": n * F / dt, "unit": "points*fields/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} of {wl.n_pts} points x {F} fields ({wl.name}), FP64 direct sum, "
+                      f"{dt:.1f} s", "gpu_rel_l2_on_sample": errs}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("sbr256", "wind1024"), default="sbr256",
+                    help="sbr256: 256x512 grid, solid-body rotation (default); "
+                         "wind1024: 1024x2048 grid, 8-mode wind, Courant 8")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter scale for rocprofv3 --pmc)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "sbr256":
+        log("bench: building the 256x512 solid-body-rotation workload")
+        wl = synth.workload_sbr()
+        workload = "grid256x512_sbr"
+    else:
+        log("bench: building the 1024x2048 8-mode-wind workload")
+        wl = synth.workload_large()
+        workload = "grid1024x2048_wind"
+    log(f"bench: {wl.n_pts} points x {wl.n_fields} fields; FP32 eps 1e-6")
+    r32 = Runner(torch, wl, "fp32", 1e-6)
+    res32 = r32.timed(args.steps, args.warmup)
+    log(f"bench: fp32 {res32['ms_per_step']:.4f} ms/step; stages {res32['stage_avg_ms']}")
+    r64 = Runner(torch, wl, "fp64", 1e-12)
+    res64 = r64.timed(args.steps, args.warmup)
+    log(f"bench: fp64 {res64['ms_per_step']:.4f} ms/step; stages {res64['stage_avg_ms']}")
+
+    if args.copy_probe:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copy probe 256 MiB x 5 done")
+
+    n_pf = r32.n_pf
+    value = n_pf / (res32["ms_per_step"] * 1e-3)
+    dom = res32["dominant"]
+    alg = stage_bytes(dom, r32.info, r32.n_touched)
+    achieved = alg / (res32["dominant_ms"] * 1e-3) / 1e9
+    traffic = read_traffic(dom, workload, "fp32")
+    J = wl.J
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "points*fields/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res32["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{workload}_{wl.n_fields}fields", "grid": f"{J}x{2*J} ({2*J}x{2*J} torus)",
+                   "n_points": wl.n_pts, "n_fields": wl.n_fields, "modes": f"{2*J-1}x{2*J-1}", "eps": 1e-6,
+                   "w": r32.info["w"], "nf": r32.info["nf_theta"],
+                   "step": "setpts + exec (all fields)"},
+        "latency_ms": {"p50": res32["p50_ms"], "p99": res32["p99_ms"]},
+        "stages_ms": res32["stage_avg_ms"],
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "alg_bytes_per_launch": alg,
+                     "avg_launch_ms": res32["dominant_ms"], "rows_reached": r32.n_touched},
+        "fp64": {"value": r64.n_pf / (res64["ms_per_step"] * 1e-3), "unit": "points*fields/s",
+                 "ms_per_step": res64["ms_per_step"], "eps": 1e-12, "w": r64.info["w"],
+                 "latency_ms": {"p50": res64["p50_ms"], "p99": res64["p99_ms"]},
+                 "stages_ms": res64["stage_avg_ms"]},
+    }
+    if not args.no_cpu_baseline:
+        torch.cuda.synchronize()
+        outs = {"fp32": r32.out.cpu().numpy().astype(np.complex128),
+                "fp64": r64.out.cpu().numpy()}
+        log("bench: timing the oracle on host cores")
+        line["cpu_baseline"] = cpu_baseline(wl, outs, args.cpu_seconds)
+    else:
+        line["cpu_baseline"] = None
+    r32.plan.destroy()
+    r64.plan.destroy()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

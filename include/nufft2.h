@@ -51,7 +51,7 @@ typedef enum { NUFFT2_FP32 = 1, NUFFT2_FP64 = 2 } nufft2_prec;
 typedef struct {
     int32_t w;            /* kernel width in fine-grid cells, 2..16; default from eps */
     double beta_over_w;   /* kernel shape beta / w; default 2.30 */
-    int32_t tile_theta;   /* gather tile rows (power of two, 4..128); default 32 */
+    int32_t tile_theta;   /* gather tile rows (power of two, 4..128); default 16 */
     int32_t tile_phi;     /* gather tile columns (power of two, 4..128); default 32 */
     int32_t real_output;  /* 1: write only the real part (fields known to be real) */
     int32_t reserved;     /* must be 0 */
@@ -137,6 +137,23 @@ nufft2_status nufft2_check(nufft2_handle p);
 nufft2_status nufft2_set_stream(nufft2_handle p, void *stream);
 
 /*
+ * Stage timing with HIP events on the plan's stream.
+ *   stage 0  setpts (wrap/split, bin count, scan, scatter)
+ *         1  theta pass (deconvolution, padding, FFT over n)
+ *         2  phi pass (FFT over m of the reached rows)
+ *         3  gather (kernel interpolation at the points)
+ * nufft2_profile_enable -- from now on bracket the stages whose bit is set in
+ *   stage_mask with a pair of events (0 stops).  Events cost a few
+ *   microseconds of queue time each; leave profiling off when not measuring.
+ * nufft2_profile_read -- synchronise the stream, add up the elapsed time of
+ *   every bracketed launch since the last read into total_ms[4] (host array,
+ *   milliseconds) and their number into count[4], and reset.
+ */
+#define NUFFT2_N_STAGES 4
+nufft2_status nufft2_profile_enable(nufft2_handle p, uint32_t stage_mask);
+nufft2_status nufft2_profile_read(nufft2_handle p, double *total_ms, int64_t *count);
+
+/*
  * Host-only helpers (no device work; usable without a GPU).
  *
  * nufft2_kernel_params -- the width and shape the plan would choose for eps
@@ -158,10 +175,10 @@ nufft2_status nufft2_kernel_correction(int64_t K, int64_t nf, int32_t w, double 
  *         1: point records in bin order (struct {int32 i0_theta, i0_phi;
  *            real v_theta, v_phi}; real = plan precision)
  *         2: permutation, int32 [n_pts]: record r belongs to point perm[r]
- *         3: bin counts, int32 [n_bins]
- *         4: bin starts, int32 [n_bins]
- *         5: touched theta rows, uint8 [nf_theta]
- *         6: theta-pass output [n_fields][nf_theta][n_modes_phi] complex
+ *         3: bin starts, int32 [n_bins + 1] (bin b holds records
+ *            start[b] .. start[b+1]-1)
+ *         4: theta rows reached by the current points' taps, uint8 [nf_theta]
+ *         5: theta-pass output [n_fields][nf_theta][n_modes_phi] complex
  * *dev_ptr and *bytes describe device memory the plan owns; valid until the
  * next setpts or destroy.  Errors: ERR_ARG, ERR_NO_POINTS (points-derived
  * buffers before setpts).

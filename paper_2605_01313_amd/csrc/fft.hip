@@ -5,21 +5,27 @@
 //     b[l_t, l_p] = sum_n sum_m c[n,m] corr_t[n] corr_p[m] e^{+2 pi i (n l_t / nft + m l_p / nfp)}
 // (unnormalised inverse DFT of the deconvolved, zero-padded coefficients).
 //
-//   theta pass: for each phi mode m (a batch of columns per workgroup) the
-//     length-nft transform over n of the K_theta deconvolved coefficients;
-//     only the theta rows some point's taps reach are written, to
+//   theta pass: for each phi mode m (a batch of columns per workgroup), the
+//     transform over n of the K_theta deconvolved coefficients.  Because
+//     K_theta <= nft / 2 (upsampling factor 2), the even and odd output rows
+//     are two independent half-length transforms:
+//         b[2q + r] = sum_n (x_n e^{2 pi i n r / nft}) e^{2 pi i n q / (nft/2)},
+//     with n taken modulo nft/2 (no two modes collide).  Each workgroup does
+//     one parity, so there are twice as many workgroups, each with half the
+//     LDS.  Only the theta rows some point's taps reach are written, to
 //     S[l_t][m] (modes along the row, K_phi long).
 //   phi pass: for each reached theta row, the length-nfp transform over m of
 //     S[l_t][:], written to the fine grid b[l_t][:].
 // Doing theta first keeps the intermediate at nft x K_phi (half the size of
-// the other order's K_theta x nfp), and only reached rows are transformed
-// in the phi pass.
+// the other order's K_theta x nfp), and only reached rows enter the phi pass.
 //
-// Each transform is a radix-8/4/2 Stockham sequence: the first stage reads
-// straight from global memory into registers, the middle stages go through
-// LDS, the last stage writes straight to global memory (both contiguous in
-// the index the threads step through).  Twiddles e^{2 pi i t / N} come from
-// a table the host fills in FP64 (long double) and rounds once.
+// Each transform is a radix-8 Stockham sequence (a radix-2 or -4 stage first
+// when log2 N is not a multiple of 3) with the length fixed at compile time.
+// The first stage reads straight from global memory into registers, the
+// middle stages go through LDS (one padding slot every 32 elements against
+// bank conflicts), the last stage writes straight to global memory; both are
+// contiguous in the index consecutive threads step through.  Twiddles come
+// from two short tables staged in LDS at kernel start.
 #include "nufft2_internal.hpp"
 
 namespace nufft2 {
@@ -75,168 +81,213 @@ template <typename C> __device__ inline void dft8(C *x)
     x[7] = csub(e3, w3);
 }
 
-template <typename T, int R> __device__ inline void dft(cplx<T> *x)
+template <int R, typename C> __device__ inline void dft(C *x)
 {
     if constexpr (R == 2) dft2(x);
     else if constexpr (R == 4) dft4(x);
     else dft8(x);
 }
 
-// One Stockham stage of radix R over B sequences of length N held in LDS at
-// s[i * IS + b * BS].  Each thread owns E / R butterflies; butterfly (j, b)
-// reads elements j + r N/R, applies twiddles W_{Ns R}^{r k} with k = j mod Ns,
-// transforms, and writes element ((j - k) R + k) + r Ns.
-// BFAST: consecutive threads step through b (else through j).
-template <typename T, int R, int E, bool BFAST, bool FIRST, bool LAST, class Loader, class Storer>
-__device__ inline void stockham_stage(cplx<T> *s, int N, int logB, int B, int Ns, int IS, int BS,
-                                      const cplx<T> *__restrict__ tw, const Loader &ld,
+// Stage plan for N = 2^LOGN.
+template <int LOGN> struct StagePlan {
+    static constexpr int REM = LOGN % 3;
+    static constexpr int NST = LOGN / 3 + (REM ? 1 : 0);
+    static constexpr int radix(int s) { return (s == 0 && REM) ? (1 << REM) : 8; }
+    static constexpr int ns(int s)
+    {
+        int v = 1;
+        for (int i = 0; i < s; ++i) v *= radix(i);
+        return v;
+    }
+};
+
+// Twiddles e^{2 pi i t / N} as a product of two short tables held in LDS:
+// lo[t mod 64] * hi[t / 64] (N/64 + 64 entries instead of N), so that a
+// stage's twiddle reads go out with its data reads instead of waiting on
+// the L2.  The host fills both tables from long double and rounds once; the
+// product adds at most about one rounding of the plan precision.
+constexpr int kTwLoBits = 6;
+constexpr int kTwLo = 1 << kTwLoBits;
+constexpr int tw_hi_len(int n) { return n > kTwLo ? n / kTwLo : 1; }
+constexpr int tw_lds_len(int n) { return kTwLo + tw_hi_len(n); }
+
+template <typename C>
+__device__ inline C twiddle(const C *tw, int t)
+{
+    return cmul(tw[t & (kTwLo - 1)], tw[kTwLo + (t >> kTwLoBits)]);
+}
+
+// Cooperative copy of the two tables (global layout = LDS layout) into LDS.
+template <typename C>
+__device__ inline void load_twiddles(C *dst, const C *__restrict__ src, int n)
+{
+    for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
+}
+
+// LDS slot of element i of a sequence: one padding slot every 32 elements.
+__device__ constexpr int lds_slot(int i) { return i + (i >> 5); }
+constexpr int lds_seq_len(int n) { return n + (n >> 5); }
+
+// Element (i, b) of the batch lives at lds_slot(i) * IS + b * BS.
+// BFAST: consecutive threads step through the batch index b (IS = B, BS = 1);
+// otherwise through i (IS = 1, BS = padded sequence length).
+
+// Job q of this thread in a stage of radix R over B sequences of length N.
+template <int N, int R, bool BFAST>
+__device__ inline void job_of(int q, int logB, int &j, int &b)
+{
+    constexpr int NBF = N / R;
+    const int job = threadIdx.x + q * blockDim.x;
+    if constexpr (BFAST) {
+        b = job & ((1 << logB) - 1);
+        j = job >> logB;
+    } else {
+        j = job & (NBF - 1);
+        b = job / NBF;
+    }
+}
+
+// One Stockham stage: butterfly (j, b) takes elements j + r N/R, applies
+// W_{NS R}^{r k} (k = j mod NS), transforms, and writes element
+// ((j - k) R + k) + r NS.  The first stage takes element i of sequence b
+// from ld(i, b) (global memory), the last hands element o to st(o, b, v).
+template <typename T, int LOGN, int S, int E, bool BFAST, class Loader, class Storer>
+__device__ inline void stockham_stage(cplx<T> *s, int logB, int IS, int BS,
+                                      const cplx<T> *__restrict__ tws, const Loader &ld,
                                       const Storer &st)
 {
+    using P = StagePlan<LOGN>;
+    constexpr int N = 1 << LOGN;
+    constexpr int R = P::radix(S), NS = P::ns(S);
+    constexpr bool FIRST = S == 0, LAST = S == P::NST - 1;
     constexpr int Q = E / R;
-    const int nbf = N / R;
+    constexpr int NBF = N / R;
     cplx<T> v[E];
     int jj[Q], bb[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int job = threadIdx.x + q * blockDim.x;
         int j, b;
-        if (BFAST) {
-            b = job & (B - 1);
-            j = job >> logB;
-        } else {
-            j = job & (nbf - 1);
-            b = job / nbf;
-        }
+        job_of<N, R, BFAST>(q, logB, j, b);
         jj[q] = j;
         bb[q] = b;
-        const int k = j & (Ns - 1);
+        if constexpr (FIRST) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int i = j + r * nbf;
-            if (FIRST) v[q * R + r] = ld(i, b);
-            else v[q * R + r] = s[i * IS + b * BS];
-        }
-        if (!FIRST) {
-            const int stride = N / (Ns * R);
+            for (int r = 0; r < R; ++r) v[q * R + r] = ld(j + r * NBF, b);
+        } else {
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], tw[r * k * stride]);
+            for (int r = 0; r < R; ++r) v[q * R + r] = s[lds_slot(j + r * NBF) * IS + b * BS];
+            const int k = j & (NS - 1);
+            constexpr int STRIDE = N / (NS * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], twiddle(tws, r * k * STRIDE));
         }
     }
-    if (!FIRST) __syncthreads();
+    if constexpr (!FIRST) __syncthreads();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        dft<T, R>(&v[q * R]);
+        dft<R>(&v[q * R]);
         const int j = jj[q], b = bb[q];
-        const int k = j & (Ns - 1);
+        const int k = j & (NS - 1);
         const int base = (j - k) * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int o = base + r * Ns;
-            if (LAST) st(o, b, v[q * R + r]);
-            else s[o * IS + b * BS] = v[q * R + r];
+            const int o = base + r * NS;
+            if constexpr (LAST) st(o, b, v[q * R + r]);
+            else s[lds_slot(o) * IS + b * BS] = v[q * R + r];
         }
     }
-    if (!LAST) __syncthreads();
+    if constexpr (!LAST) __syncthreads();
 }
 
-template <typename T, int R, int E, bool BFAST, class Loader, class Storer>
-__device__ inline void stockham_dispatch(bool first, bool last, cplx<T> *s, int N, int logB, int B,
-                                         int Ns, int IS, int BS, const cplx<T> *tw,
-                                         const Loader &ld, const Storer &st)
+template <typename T, int LOGN, int S, int E, bool BFAST, class Loader, class Storer>
+__device__ inline void fft_stages(cplx<T> *s, int logB, int IS, int BS, const cplx<T> *tws,
+                                  const Loader &ld, const Storer &st)
 {
-    if (first && last)
-        stockham_stage<T, R, E, BFAST, true, true>(s, N, logB, B, Ns, IS, BS, tw, ld, st);
-    else if (first)
-        stockham_stage<T, R, E, BFAST, true, false>(s, N, logB, B, Ns, IS, BS, tw, ld, st);
-    else if (last)
-        stockham_stage<T, R, E, BFAST, false, true>(s, N, logB, B, Ns, IS, BS, tw, ld, st);
-    else
-        stockham_stage<T, R, E, BFAST, false, false>(s, N, logB, B, Ns, IS, BS, tw, ld, st);
-}
-
-// Full length-N transform (N = 2^logN >= 8) of B sequences: a radix 2 or 4
-// stage first if logN is not a multiple of 3, then radix-8 stages.
-template <typename T, int E, bool BFAST, class Loader, class Storer>
-__device__ inline void fft_batch(cplx<T> *s, int logN, int logB, int IS, int BS,
-                                 const cplx<T> *tw, const Loader &ld, const Storer &st)
-{
-    const int N = 1 << logN, B = 1 << logB;
-    int rem = logN % 3;
-    int nst = logN / 3 + (rem ? 1 : 0);
-    int Ns = 1;
-    for (int si = 0; si < nst; ++si) {
-        const bool first = si == 0, last = si == nst - 1;
-        const int R = (si == 0 && rem) ? (1 << rem) : 8;
-        if (R == 8) stockham_dispatch<T, 8, E, BFAST>(first, last, s, N, logB, B, Ns, IS, BS, tw, ld, st);
-        else if (R == 4) stockham_dispatch<T, 4, E, BFAST>(first, last, s, N, logB, B, Ns, IS, BS, tw, ld, st);
-        else stockham_dispatch<T, 2, E, BFAST>(first, last, s, N, logB, B, Ns, IS, BS, tw, ld, st);
-        Ns *= R;
+    if constexpr (S < StagePlan<LOGN>::NST) {
+        stockham_stage<T, LOGN, S, E, BFAST>(s, logB, IS, BS, tws, ld, st);
+        fft_stages<T, LOGN, S + 1, E, BFAST>(s, logB, IS, BS, tws, ld, st);
     }
 }
 
-// FFT index i -> centred mode index a in [0, K), or -1 for zero padding.
-__device__ inline int mode_of(int i, int K, int N)
+// Workgroup id -> work item, so that each XCD (workgroups are dealt to the 8
+// XCDs round-robin) takes a contiguous run of work items and neighbouring
+// items share that XCD's L2.
+__device__ inline int xcd_remap(int id, int total)
+{
+    const int q = total >> 3, rem = total & 7;
+    const int x = id & 7, k = id >> 3;
+    return x * q + (x < rem ? x : rem) + k;
+}
+
+// Centred mode index of FFT slot i in a length-L transform (-1: zero padding).
+__device__ inline int mode_of(int i, int K, int L)
 {
     const int half = K >> 1, kmax = K - 1 - half;
     if (i <= kmax) return i + half;
-    if (i >= N - half) return i - N + half;
+    if (i >= L - half) return i - L + half;
     return -1;
 }
 
+// Even rows (parity 0): x_n = c[n][m] corr_t[n] corr_p[m];
+// odd rows (parity 1): x_n e^{2 pi i n / nft}.
 template <typename T> struct ThetaLoad {
     const cplx<T> *coef;  // this field
     const T *ct, *cp;
-    int Kt, Kp, nft, m0;
+    const cplx<T> *twist;  // e^{2 pi i n / nft}
+    int Kt, Kp, L, m0, parity;
     __device__ cplx<T> operator()(int i, int b) const
     {
         const int m = m0 + b;
-        const int a = mode_of(i, Kt, nft);
+        const int a = mode_of(i, Kt, L);
         if (a < 0 || m >= Kp) return {(T)0, (T)0};
         const cplx<T> c = coef[(int64_t)a * Kp + m];
         const T sc = ct[a] * cp[m];
-        return {c.x * sc, c.y * sc};
+        cplx<T> x = {c.x * sc, c.y * sc};
+        if (parity) x = cmul(x, twist[a]);
+        return x;
     }
 };
 
 template <typename T> struct ThetaStore {
     cplx<T> *S;  // this field, [nft][Kp]
     const uint8_t *touched;
-    int Kp, m0;
-    __device__ void operator()(int l, int b, cplx<T> v) const
+    int Kp, m0, parity;
+    __device__ void operator()(int q, int b, cplx<T> v) const
     {
         const int m = m0 + b;
+        const int l = 2 * q + parity;
         if (m < Kp && touched[l]) S[(int64_t)l * Kp + m] = v;
     }
 };
 
-template <typename T, int E>
-__global__ __launch_bounds__(1024) void k_theta_pass(const cplx<T> *__restrict__ coeffs,
-                                                     const T *__restrict__ corr_t,
-                                                     const T *__restrict__ corr_p,
-                                                     const cplx<T> *__restrict__ tw,
-                                                     const uint8_t *__restrict__ touched,
-                                                     cplx<T> *__restrict__ S, FFTParams fp)
+template <typename T> constexpr int theta_max_threads() { return sizeof(T) == 4 ? 1024 : 512; }
+
+// One workgroup per (field, batch of B phi modes, output parity).  The work
+// item order puts the two parities of a batch next to each other, so that
+// the XCD-aware mapping runs them on the same XCD and the second read of the
+// coefficient batch hits its L2.
+template <typename T, int LOGL, int E>
+__global__ __launch_bounds__(theta_max_threads<T>()) void k_theta_pass(
+    const cplx<T> *__restrict__ coeffs, const T *__restrict__ corr_t,
+    const cplx<T> *__restrict__ twist_t /* e^{2 pi i n / nft} */, const T *__restrict__ corr_p,
+    const cplx<T> *__restrict__ tws, const uint8_t *__restrict__ touched, cplx<T> *__restrict__ S,
+    FFTParams fp)
 {
     extern __shared__ unsigned char smem_raw[];
-    cplx<T> *s = reinterpret_cast<cplx<T> *>(smem_raw);
-    const int f = blockIdx.y;
-    const int m0 = blockIdx.x * fp.theta_batch;
-    ThetaLoad<T> ld{coeffs + (int64_t)f * fp.Kt * fp.Kp, corr_t, corr_p, fp.Kt, fp.Kp, fp.nft, m0};
-    ThetaStore<T> st{S + (int64_t)f * fp.nft * fp.Kp, touched, fp.Kp, m0};
-    // layout [i][b]: consecutive threads take consecutive columns
-    fft_batch<T, E, true>(s, fp.log_nft, fp.log_theta_batch, fp.theta_batch, 1, tw, ld, st);
+    cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
+    cplx<T> *s = tw + tw_lds_len(1 << LOGL);
+    load_twiddles(tw, tws, tw_lds_len(1 << LOGL));
+    const int ntiles = (fp.Kp + fp.theta_batch - 1) / fp.theta_batch;
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int parity = item & 1;
+    const int tile = item >> 1;
+    const int f = tile / ntiles;
+    const int m0 = (tile - f * ntiles) * fp.theta_batch;
+    ThetaLoad<T> ld{coeffs + (int64_t)f * fp.Kt * fp.Kp, corr_t, corr_p, twist_t,
+                    fp.Kt, fp.Kp, 1 << LOGL, m0, parity};
+    ThetaStore<T> st{S + (int64_t)f * fp.nft * fp.Kp, touched, fp.Kp, m0, parity};
+    fft_stages<T, LOGL, 0, E, true>(s, fp.log_theta_batch, fp.theta_batch, 1, tw, ld, st);
 }
-
-template <typename T> struct PhiLoad {
-    const cplx<T> *S;  // this field, [nft][Kp]
-    int Kp, nfp, l0;
-    __device__ cplx<T> operator()(int i, int b) const
-    {
-        const int a = mode_of(i, Kp, nfp);
-        if (a < 0) return {(T)0, (T)0};
-        return S[(int64_t)(l0 + b) * Kp + a];
-    }
-};
 
 template <typename T> struct PhiStore {
     cplx<T> *grid;  // this field, [nft][nfp]
@@ -249,78 +300,118 @@ template <typename T> struct PhiStore {
     }
 };
 
-template <typename T, int E>
-__global__ __launch_bounds__(1024) void k_phi_pass(const cplx<T> *__restrict__ S,
-                                                   const cplx<T> *__restrict__ tw,
-                                                   const uint8_t *__restrict__ touched,
-                                                   cplx<T> *__restrict__ grid, FFTParams fp)
+template <typename T> struct PhiLoad {
+    const cplx<T> *S;  // this field, [nft][Kp]
+    int Kp, nfp, l0;
+    __device__ cplx<T> operator()(int i, int b) const
+    {
+        const int a = mode_of(i, Kp, nfp);
+        if (a < 0) return {(T)0, (T)0};
+        return S[(int64_t)(l0 + b) * Kp + a];
+    }
+};
+
+// One workgroup per (field, batch of B reached theta rows).
+template <typename T, int LOGN, int E>
+__global__ __launch_bounds__(256) void k_phi_pass(const cplx<T> *__restrict__ S,
+                                                  const cplx<T> *__restrict__ tws,
+                                                  const uint8_t *__restrict__ touched,
+                                                  cplx<T> *__restrict__ grid, FFTParams fp)
 {
     extern __shared__ unsigned char smem_raw[];
-    cplx<T> *s = reinterpret_cast<cplx<T> *>(smem_raw);
-    const int f = blockIdx.y;
-    const int l0 = blockIdx.x * fp.phi_batch;
+    cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
+    cplx<T> *s = tw + tw_lds_len(1 << LOGN);
+    const int nrb = fp.nft / fp.phi_batch;
+    const int f = blockIdx.x / nrb;
+    const int l0 = (blockIdx.x - f * nrb) * fp.phi_batch;
     // skip the workgroup when none of its rows is reached by any point
-    __shared__ int any;
-    if (threadIdx.x == 0) {
-        int a = 0;
-        for (int b = 0; b < fp.phi_batch; ++b) a |= touched[l0 + b];
-        any = a;
-    }
-    __syncthreads();
+    int any = 0;
+    for (int b = 0; b < fp.phi_batch; ++b) any |= touched[l0 + b];
     if (!any) return;
+    load_twiddles(tw, tws, tw_lds_len(1 << LOGN));
     PhiLoad<T> ld{S + (int64_t)f * fp.nft * fp.Kp, fp.Kp, fp.nfp, l0};
     PhiStore<T> st{grid + (int64_t)f * fp.nft * fp.nfp, touched, fp.nfp, l0};
-    // layout [b][i]: consecutive threads take consecutive elements of a row
-    fft_batch<T, E, false>(s, fp.log_nfp, fp.log_phi_batch, 1, 1 << fp.log_nfp, tw, ld, st);
+    fft_stages<T, LOGN, 0, E, false>(s, fp.log_phi_batch, 1, lds_seq_len(1 << LOGN), tw, ld, st);
 }
 
 constexpr int kElemsPerThread = 16;
 
-hipError_t launch_theta_pass(int prec, const FFTParams &fp, const void *coeffs, const void *corr_t,
-                             const void *corr_p, const void *tw_t, const uint8_t *rowtouched,
-                             void *S, hipStream_t s)
+template <typename T, int LOGL>
+static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const void *corr_t,
+                                 const void *twist_t, const void *corr_p, const void *tws_t,
+                                 const uint8_t *touched, void *S, hipStream_t s)
 {
-    const int NB = fp.nft * fp.theta_batch;
-    const int threads = NB / kElemsPerThread;
-    const dim3 grid((fp.Kp + fp.theta_batch - 1) / fp.theta_batch, fp.n_fields);
-    if (prec == 1) {
-        const size_t lds = sizeof(float2) * (size_t)NB;
-        auto kern = k_theta_pass<float, kElemsPerThread>;
-        if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(kern, grid, dim3(threads), lds, s, (const float2 *)coeffs,
-                           (const float *)corr_t, (const float *)corr_p, (const float2 *)tw_t,
-                           rowtouched, (float2 *)S, fp);
-    } else {
-        const size_t lds = sizeof(double2) * (size_t)NB;
-        auto kern = k_theta_pass<double, kElemsPerThread>;
-        if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(kern, grid, dim3(threads), lds, s, (const double2 *)coeffs,
-                           (const double *)corr_t, (const double *)corr_p, (const double2 *)tw_t,
-                           rowtouched, (double2 *)S, fp);
-    }
+    const int L = 1 << LOGL;
+    const int threads = L * fp.theta_batch / kElemsPerThread;
+    if (threads < 1 || threads > theta_max_threads<T>()) return hipErrorInvalidConfiguration;
+    const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(L) * fp.theta_batch + tw_lds_len(L));
+    auto kern = k_theta_pass<T, LOGL, kElemsPerThread>;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int ntiles = (fp.Kp + fp.theta_batch - 1) / fp.theta_batch;
+    hipLaunchKernelGGL(kern, dim3(2 * ntiles * fp.n_fields), dim3(threads), lds, s,
+                       (const cplx<T> *)coeffs, (const T *)corr_t, (const cplx<T> *)twist_t,
+                       (const T *)corr_p, (const cplx<T> *)tws_t, touched, (cplx<T> *)S, fp);
     return hipGetLastError();
+}
+
+template <typename T, int LOGN>
+static hipError_t launch_phi_t(const FFTParams &fp, const void *S, const void *tw_p,
+                               const uint8_t *touched, void *grid, hipStream_t s)
+{
+    const int N = 1 << LOGN;
+    const int threads = N * fp.phi_batch / kElemsPerThread;
+    if (threads < 1 || threads > 256) return hipErrorInvalidConfiguration;
+    const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * fp.phi_batch + tw_lds_len(N));
+    auto kern = k_phi_pass<T, LOGN, kElemsPerThread>;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3((fp.nft / fp.phi_batch) * fp.n_fields), dim3(threads), lds, s,
+                       (const cplx<T> *)S, (const cplx<T> *)tw_p, touched, (cplx<T> *)grid, fp);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t theta_dispatch(const FFTParams &fp, const void *coeffs, const void *corr_t,
+                                 const void *twist_t, const void *corr_p, const void *tws_t,
+                                 const uint8_t *touched, void *S, hipStream_t s)
+{
+    switch (fp.log_nft - 1) {
+#define NUFFT2_L(X) case X: return launch_theta_t<T, X>(fp, coeffs, corr_t, twist_t, corr_p, tws_t, touched, S, s);
+        NUFFT2_L(3) NUFFT2_L(4) NUFFT2_L(5) NUFFT2_L(6) NUFFT2_L(7) NUFFT2_L(8) NUFFT2_L(9)
+        NUFFT2_L(10) NUFFT2_L(11)
+#undef NUFFT2_L
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t phi_dispatch(const FFTParams &fp, const void *S, const void *tw_p,
+                               const uint8_t *touched, void *grid, hipStream_t s)
+{
+    switch (fp.log_nfp) {
+#define NUFFT2_N(X) case X: return launch_phi_t<T, X>(fp, S, tw_p, touched, grid, s);
+        NUFFT2_N(4) NUFFT2_N(5) NUFFT2_N(6) NUFFT2_N(7) NUFFT2_N(8) NUFFT2_N(9) NUFFT2_N(10)
+        NUFFT2_N(11) NUFFT2_N(12)
+#undef NUFFT2_N
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_theta_pass(int prec, const FFTParams &fp, const void *coeffs, const void *corr_t,
+                             const void *twist_t, const void *corr_p, const void *tws_t,
+                             const uint8_t *rowtouched, void *S, hipStream_t s)
+{
+    if (prec == 1)
+        return theta_dispatch<float>(fp, coeffs, corr_t, twist_t, corr_p, tws_t, rowtouched, S, s);
+    return theta_dispatch<double>(fp, coeffs, corr_t, twist_t, corr_p, tws_t, rowtouched, S, s);
 }
 
 hipError_t launch_phi_pass(int prec, const FFTParams &fp, const void *S, const void *tw_p,
                            const uint8_t *rowtouched, void *grid, hipStream_t s)
 {
-    const int NB = fp.nfp * fp.phi_batch;
-    const int threads = NB / kElemsPerThread;
-    const dim3 g(fp.nft / fp.phi_batch, fp.n_fields);
-    if (prec == 1) {
-        const size_t lds = sizeof(float2) * (size_t)NB;
-        auto kern = k_phi_pass<float, kElemsPerThread>;
-        if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(kern, g, dim3(threads), lds, s, (const float2 *)S, (const float2 *)tw_p,
-                           rowtouched, (float2 *)grid, fp);
-    } else {
-        const size_t lds = sizeof(double2) * (size_t)NB;
-        auto kern = k_phi_pass<double, kElemsPerThread>;
-        if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(kern, g, dim3(threads), lds, s, (const double2 *)S, (const double2 *)tw_p,
-                           rowtouched, (double2 *)grid, fp);
-    }
-    return hipGetLastError();
+    if (prec == 1) return phi_dispatch<float>(fp, S, tw_p, rowtouched, grid, s);
+    return phi_dispatch<double>(fp, S, tw_p, rowtouched, grid, s);
 }
 
 }  // namespace nufft2

@@ -47,10 +47,13 @@ struct FFTParams {
     int32_t phi_batch, log_phi_batch;       // rows per phi-pass workgroup
 };
 
+// corr_t: real [Kt]; twist_t: complex [Kt], e^{2 pi i n / nft} (n = a - Kt/2);
+// corr_p: real [Kp]; tws_t / tws_p: twiddle tables of the nft/2- and
+// nfp-point transforms (64 low entries, then the high entries; see fft.hip).
 hipError_t launch_theta_pass(int prec, const FFTParams &fp, const void *coeffs, const void *corr_t,
-                             const void *corr_p, const void *tw_t, const uint8_t *rowtouched,
-                             void *S, hipStream_t s);
-hipError_t launch_phi_pass(int prec, const FFTParams &fp, const void *S, const void *tw_p,
+                             const void *twist_t, const void *corr_p, const void *tws_t,
+                             const uint8_t *rowtouched, void *S, hipStream_t s);
+hipError_t launch_phi_pass(int prec, const FFTParams &fp, const void *S, const void *tws_p,
                            const uint8_t *rowtouched, void *grid, hipStream_t s);
 
 struct GatherParams {
@@ -61,14 +64,13 @@ struct GatherParams {
     int32_t w;
     double beta;
     int32_t n_fields;
+    int32_t fields_per_pass;   // fields staged in LDS together (1..4)
     int64_t n_pts;
     int32_t real_output;
 };
 
+// binstart has nbins + 1 entries; bin b holds records binstart[b] .. binstart[b+1]-1.
 hipError_t launch_gather(int prec, const GatherParams &gp, const void *grid, const void *rec,
-                         const int32_t *perm, const int32_t *bincount, const int32_t *binstart,
-                         void *out, hipStream_t s);
-
-hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+                         const int32_t *perm, const int32_t *binstart, void *out, hipStream_t s);
 
 }  // namespace nufft2

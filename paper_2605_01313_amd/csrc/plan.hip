@@ -21,9 +21,10 @@ namespace {
 constexpr int kMaxNf = 4096;
 constexpr int kMaxW = 16;
 constexpr double kDefaultBetaOverW = 2.30;
-constexpr int kDefaultTile = 32;
-constexpr size_t kThetaPassLdsBudget = 65536;
-constexpr size_t kGatherLdsLimit = 65536;
+constexpr int kDefaultTileTheta = 16;
+constexpr int kDefaultTilePhi = 32;
+constexpr size_t kGatherLdsLimit = 65536;  // per staged field group
+constexpr int kGatherMaxFieldsPerPass = 4;
 
 }  // namespace
 
@@ -38,6 +39,7 @@ struct nufft2_plan_s {
     int nbins_t = 0, nbins_p = 0;
     int64_t nbins = 0;
     int real_output = 0;
+    int fields_per_pass = 1;
     hipStream_t stream = nullptr;
     int device = 0;
     size_t csize = 0;  // bytes per complex
@@ -46,7 +48,8 @@ struct nufft2_plan_s {
 
     // device workspaces
     void *corr_t = nullptr, *corr_p = nullptr;
-    void *tw_t = nullptr, *tw_p = nullptr;
+    void *tw_t = nullptr, *tw_p = nullptr;  // two-level twiddle tables
+    void *twist_t = nullptr;                // e^{2 pi i n / nft} per theta mode
     void *S = nullptr, *grid = nullptr;
     int32_t *bincount = nullptr, *binstart = nullptr;
     uint8_t *rowmark = nullptr, *rowtouched = nullptr;
@@ -60,6 +63,12 @@ struct nufft2_plan_s {
     int64_t n_pts = -1;
     size_t ws_bytes = 0;
     hipError_t last_err = hipSuccess;
+
+    // stage timing
+    uint32_t prof_mask = 0;
+    struct Bracket { int stage; hipEvent_t a, b; };
+    std::vector<Bracket> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
 };
 
 namespace {
@@ -154,25 +163,34 @@ nufft2_status kernel_correction(int64_t K, int64_t nf, int w, double beta, doubl
     return NUFFT2_OK;
 }
 
-template <typename T> void fill_twiddles(std::vector<T> &buf, int N)
+// Twiddle tables of an N-point transform in the kernels' layout:
+// lo[u] = e^{2 pi i u / N} for u < 64, then hi[v] = e^{2 pi i 64 v / N} for
+// v < max(N / 64, 1); the kernels form e^{2 pi i t / N} = lo[t % 64] hi[t / 64].
+template <typename T> void fill_twiddle_tables(std::vector<T> &buf, int N)
 {
     const long double two_pi = 6.283185307179586476925286766559005768L;
-    buf.resize(2 * (size_t)N);
-    for (int t = 0; t < N; ++t) {
-        const long double ang = two_pi * (long double)t / (long double)N;
-        buf[2 * t] = (T)cosl(ang);
-        buf[2 * t + 1] = (T)sinl(ang);
+    const int lo = 64, hi = N > 64 ? N / 64 : 1;
+    buf.clear();
+    for (int u = 0; u < lo; ++u) {
+        const long double ang = two_pi * (long double)u / (long double)N;
+        buf.push_back((T)cosl(ang));
+        buf.push_back((T)sinl(ang));
+    }
+    for (int v = 0; v < hi; ++v) {
+        const long double ang = two_pi * (long double)(64 * v) / (long double)N;
+        buf.push_back((T)cosl(ang));
+        buf.push_back((T)sinl(ang));
     }
 }
 
 void free_all(nufft2_plan_s *p)
 {
-    void *ptrs[] = {p->corr_t, p->corr_p, p->tw_t,  p->tw_p,     p->S,     p->grid,
+    void *ptrs[] = {p->corr_t, p->corr_p, p->tw_t,  p->tw_p,  p->twist_t,   p->S,     p->grid,
                     p->bincount, p->binstart, p->rowmark, p->rowtouched, p->flags, p->keyrank,
                     p->rec,    p->perm};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
-    p->corr_t = p->corr_p = p->tw_t = p->tw_p = p->S = p->grid = nullptr;
+    p->corr_t = p->corr_p = p->tw_t = p->tw_p = p->twist_t = p->S = p->grid = nullptr;
     p->bincount = p->binstart = p->flags = p->perm = nullptr;
     p->rowmark = p->rowtouched = nullptr;
     p->keyrank = nullptr;
@@ -205,21 +223,82 @@ template <typename T> nufft2_status upload_tables(nufft2_plan_s *p)
     st = kernel_correction(p->Kp, p->nfp, p->w, p->beta, cp.data());
     if (st != NUFFT2_OK) return st;
     std::vector<T> ctT(ct.begin(), ct.end()), cpT(cp.begin(), cp.end());
-    std::vector<T> twt, twp;
-    fill_twiddles<T>(twt, p->nft);
-    fill_twiddles<T>(twp, p->nfp);
+    std::vector<T> twt, twp, twist(2 * (size_t)p->Kt);
+    fill_twiddle_tables<T>(twt, p->nft / 2);
+    fill_twiddle_tables<T>(twp, p->nfp);
+    {
+        const long double two_pi = 6.283185307179586476925286766559005768L;
+        for (int64_t a = 0; a < p->Kt; ++a) {
+            const long double ang = two_pi * (long double)(a - p->Kt / 2) / (long double)p->nft;
+            twist[2 * a] = (T)cosl(ang);
+            twist[2 * a + 1] = (T)sinl(ang);
+        }
+    }
     hipError_t e;
     if ((e = hipMemcpy(p->corr_t, ctT.data(), sizeof(T) * ctT.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->corr_p, cpT.data(), sizeof(T) * cpT.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->tw_t, twt.data(), sizeof(T) * twt.size(), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p->tw_p, twp.data(), sizeof(T) * twp.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        (e = hipMemcpy(p->tw_p, twp.data(), sizeof(T) * twp.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->twist_t, twist.data(), sizeof(T) * twist.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return fail_hip(p, e);
     return NUFFT2_OK;
 }
 
-int choose_tile(int32_t requested, int nf, bool *bad)
+hipEvent_t prof_event(nufft2_plan_s *p)
 {
-    int t = requested > 0 ? requested : kDefaultTile;
+    if (!p->prof_pool.empty()) {
+        hipEvent_t e = p->prof_pool.back();
+        p->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Open a bracket for `stage` if it is being timed; returns its slot or -1.
+int prof_begin(nufft2_plan_s *p, int stage)
+{
+    if (!(p->prof_mask & (1u << stage))) return -1;
+    hipEvent_t a = prof_event(p), b = prof_event(p);
+    if (!a || !b || hipEventRecord(a, p->stream) != hipSuccess) {
+        if (a) p->prof_pool.push_back(a);
+        if (b) p->prof_pool.push_back(b);
+        (void)hipGetLastError();
+        return -1;
+    }
+    p->prof_pending.push_back({stage, a, b});
+    return (int)p->prof_pending.size() - 1;
+}
+
+void prof_end(nufft2_plan_s *p, int slot)
+{
+    if (slot < 0) return;
+    if (hipEventRecord(p->prof_pending[slot].b, p->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        p->prof_pool.push_back(p->prof_pending[slot].a);
+        p->prof_pool.push_back(p->prof_pending[slot].b);
+        p->prof_pending.erase(p->prof_pending.begin() + slot);
+    }
+}
+
+void prof_release_all(nufft2_plan_s *p)
+{
+    for (auto &br : p->prof_pending) {
+        (void)hipEventDestroy(br.a);
+        (void)hipEventDestroy(br.b);
+    }
+    for (hipEvent_t e : p->prof_pool) (void)hipEventDestroy(e);
+    p->prof_pending.clear();
+    p->prof_pool.clear();
+}
+
+int choose_tile(int32_t requested, int dflt, int nf, bool *bad)
+{
+    int t = requested > 0 ? requested : dflt;
     if (requested > 0 && (!is_pow2(requested) || requested < 4 || requested > 128)) *bad = true;
     if (t > nf) t = nf;
     return t;
@@ -285,8 +364,8 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     if ((int64_t)n_fields * nft * nfp > (int64_t(1) << 34)) return NUFFT2_ERR_ARG;
 
     bool bad_tile = false;
-    const int tt = choose_tile(o.tile_theta, (int)nft, &bad_tile);
-    const int tp = choose_tile(o.tile_phi, (int)nfp, &bad_tile);
+    const int tt = choose_tile(o.tile_theta, kDefaultTileTheta, (int)nft, &bad_tile);
+    const int tp = choose_tile(o.tile_phi, kDefaultTilePhi, (int)nfp, &bad_tile);
     if (bad_tile) return NUFFT2_ERR_ARG;
     {
         // the gather stages a (tile + w - 1)^2 patch of one field in LDS
@@ -329,30 +408,41 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     fp.log_nfp = ilog2(p->nfp);
     fp.n_fields = p->F;
     {
-        int64_t b = (int64_t)(kThetaPassLdsBudget / (p->csize * (size_t)p->nft));
-        if (b > 64) b = 64;
-        if (b < 1) b = 1;
-        while ((int64_t)p->nft * b < 1024) b *= 2;
-        while ((int64_t)p->nft * b > 16384) b /= 2;
-        b = int64_t(1) << (ilog2(b + 1) - 1);  // power of two not above b
+        // theta pass: columns per workgroup so that a row segment is >= 64 bytes,
+        // at least 64 threads, at most 1024 (FP32) / 512 (FP64) threads
+        const int64_t L = p->nft / 2;
+        const int64_t max_threads = prec == NUFFT2_FP32 ? 1024 : 512;
+        int64_t b = prec == NUFFT2_FP32 ? 8 : 4;
+        while (L * b < 1024) b *= 2;
+        while (L * b / 16 > max_threads) b /= 2;
         fp.theta_batch = (int)b;
         fp.log_theta_batch = ilog2(b);
     }
     {
+        // phi pass: rows per workgroup so that a workgroup transforms 4096 elements
         int64_t b = 4096 / p->nfp;
         if (b < 1) b = 1;
         if (b > p->nft) b = p->nft;
         fp.phi_batch = (int)b;
         fp.log_phi_batch = ilog2(b);
     }
+    {
+        const size_t tile = p->csize * (size_t)(tt + w - 1) * (size_t)(tp + w - 1);
+        int g = (int)(kGatherLdsLimit / tile);
+        if (g > kGatherMaxFieldsPerPass) g = kGatherMaxFieldsPerPass;
+        if (g > p->F) g = p->F;
+        if (g < 1) g = 1;
+        p->fields_per_pass = g;
+    }
 
     const size_t rs = p->rsize, cs = p->csize;
     bool ok = dev_alloc(p, &p->corr_t, rs * p->Kt) && dev_alloc(p, &p->corr_p, rs * p->Kp) &&
-              dev_alloc(p, &p->tw_t, cs * p->nft) && dev_alloc(p, &p->tw_p, cs * p->nfp) &&
+              dev_alloc(p, &p->tw_t, cs * (64 + p->nft)) && dev_alloc(p, &p->tw_p, cs * (64 + p->nfp)) &&
+              dev_alloc(p, &p->twist_t, cs * p->Kt) &&
               dev_alloc(p, &p->S, cs * (size_t)p->F * p->nft * p->Kp) &&
               dev_alloc(p, &p->grid, cs * (size_t)p->F * p->nft * p->nfp) &&
               dev_alloc(p, (void **)&p->bincount, sizeof(int32_t) * (size_t)p->nbins) &&
-              dev_alloc(p, (void **)&p->binstart, sizeof(int32_t) * (size_t)p->nbins) &&
+              dev_alloc(p, (void **)&p->binstart, sizeof(int32_t) * (size_t)(p->nbins + 1)) &&
               dev_alloc(p, (void **)&p->rowmark, (size_t)p->nft) &&
               dev_alloc(p, (void **)&p->rowtouched, (size_t)p->nft) &&
               dev_alloc(p, (void **)&p->flags, sizeof(int32_t) * 4);
@@ -367,6 +457,9 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
         if ((e = hipMemset(p->S, 0, cs * (size_t)p->F * p->nft * p->Kp)) != hipSuccess ||
             (e = hipMemset(p->grid, 0, cs * (size_t)p->F * p->nft * p->nfp)) != hipSuccess ||
             (e = hipMemset(p->rowtouched, 0, (size_t)p->nft)) != hipSuccess ||
+            (e = hipMemset(p->rowmark, 0, (size_t)p->nft)) != hipSuccess ||
+            (e = hipMemset(p->bincount, 0, sizeof(int32_t) * (size_t)p->nbins)) != hipSuccess ||
+            (e = hipMemset(p->binstart, 0, sizeof(int32_t) * (size_t)(p->nbins + 1))) != hipSuccess ||
             (e = hipMemset(p->flags, 0, sizeof(int32_t) * 4)) != hipSuccess ||
             (e = hipDeviceSynchronize()) != hipSuccess)
             st = NUFFT2_ERR_HIP;
@@ -426,9 +519,11 @@ NUFFT2_API nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const dou
     sp.w = p->w;
     sp.nbins_phi = p->nbins_p;
     sp.n = n_pts;
+    const int slot = prof_begin(p, 0);
     hipError_t e = launch_setpts(p->prec, sp, phi_dev, theta_dev, p->bincount, p->binstart, p->nbins,
                                  p->keyrank, p->rowmark, p->rowtouched, p->rec, p->perm, p->flags,
                                  p->stream);
+    prof_end(p, slot);
     if (e != hipSuccess) return fail_hip(p, e);
     p->n_pts = n_pts;
     return NUFFT2_OK;
@@ -440,10 +535,14 @@ NUFFT2_API nufft2_status nufft2_exec(nufft2_handle p, const void *coeffs_dev, vo
     if (p->n_pts < 0) return NUFFT2_ERR_NO_POINTS;
     if (p->n_pts == 0) return NUFFT2_OK;
     if (!coeffs_dev || !out_dev) return NUFFT2_ERR_ARG;
-    hipError_t e = launch_theta_pass(p->prec, p->fp, coeffs_dev, p->corr_t, p->corr_p, p->tw_t,
-                                     p->rowtouched, p->S, p->stream);
+    int slot = prof_begin(p, 1);
+    hipError_t e = launch_theta_pass(p->prec, p->fp, coeffs_dev, p->corr_t, p->twist_t, p->corr_p,
+                                     p->tw_t, p->rowtouched, p->S, p->stream);
+    prof_end(p, slot);
     if (e != hipSuccess) return fail_hip(p, e);
+    slot = prof_begin(p, 2);
     e = launch_phi_pass(p->prec, p->fp, p->S, p->tw_p, p->rowtouched, p->grid, p->stream);
+    prof_end(p, slot);
     if (e != hipSuccess) return fail_hip(p, e);
     GatherParams gp{};
     gp.nft = p->nft;
@@ -455,10 +554,12 @@ NUFFT2_API nufft2_status nufft2_exec(nufft2_handle p, const void *coeffs_dev, vo
     gp.w = p->w;
     gp.beta = p->beta;
     gp.n_fields = p->F;
+    gp.fields_per_pass = p->fields_per_pass;
     gp.n_pts = p->n_pts;
     gp.real_output = p->real_output;
-    e = launch_gather(p->prec, gp, p->grid, p->rec, p->perm, p->bincount, p->binstart, out_dev,
-                      p->stream);
+    slot = prof_begin(p, 3);
+    e = launch_gather(p->prec, gp, p->grid, p->rec, p->perm, p->binstart, out_dev, p->stream);
+    prof_end(p, slot);
     if (e != hipSuccess) return fail_hip(p, e);
     return NUFFT2_OK;
 }
@@ -469,8 +570,8 @@ NUFFT2_API nufft2_status nufft2_check(nufft2_handle p)
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return fail_hip(p, e);
     if (p->last_err != hipSuccess) return NUFFT2_ERR_HIP;
-    int32_t flags = 0;
-    e = hipMemcpy(&flags, p->flags, sizeof(int32_t), hipMemcpyDeviceToHost);
+    int32_t flags = 0;  // flags[1]: published by the last setpts
+    e = hipMemcpy(&flags, p->flags + 1, sizeof(int32_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail_hip(p, e);
     if (p->n_pts > 0 && (flags & 1)) return NUFFT2_ERR_NONFINITE;
     return NUFFT2_OK;
@@ -489,8 +590,40 @@ NUFFT2_API nufft2_status nufft2_destroy(nufft2_handle p)
 {
     if (!p) return NUFFT2_OK;
     (void)hipStreamSynchronize(p->stream);
+    prof_release_all(p);
     free_all(p);
     delete p;
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_profile_enable(nufft2_handle p, uint32_t stage_mask)
+{
+    if (!p || (stage_mask >> NUFFT2_N_STAGES) != 0) return NUFFT2_ERR_ARG;
+    p->prof_mask = stage_mask;
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_profile_read(nufft2_handle p, double *total_ms, int64_t *count)
+{
+    if (!p || !total_ms || !count) return NUFFT2_ERR_ARG;
+    for (int i = 0; i < NUFFT2_N_STAGES; ++i) {
+        total_ms[i] = 0.0;
+        count[i] = 0;
+    }
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return fail_hip(p, e);
+    for (auto &br : p->prof_pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, br.a, br.b) == hipSuccess) {
+            total_ms[br.stage] += ms;
+            count[br.stage] += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        p->prof_pool.push_back(br.a);
+        p->prof_pool.push_back(br.b);
+    }
+    p->prof_pending.clear();
     return NUFFT2_OK;
 }
 
@@ -521,17 +654,16 @@ NUFFT2_API nufft2_status nufft2_debug_buffer(nufft2_handle p, int32_t which, voi
                                              uint64_t *bytes)
 {
     if (!p || !dev_ptr || !bytes) return NUFFT2_ERR_ARG;
-    const bool needs_pts = which == 1 || which == 2;
+    const bool needs_pts = which == 1 || which == 2 || which == 3 || which == 4;
     if (needs_pts && p->n_pts < 0) return NUFFT2_ERR_NO_POINTS;
     const size_t recsz = p->prec == NUFFT2_FP32 ? sizeof(PointRec<float>) : sizeof(PointRec<double>);
     switch (which) {
     case 0: *dev_ptr = p->grid; *bytes = p->csize * (size_t)p->F * p->nft * p->nfp; break;
     case 1: *dev_ptr = p->rec; *bytes = recsz * (size_t)p->n_pts; break;
     case 2: *dev_ptr = p->perm; *bytes = sizeof(int32_t) * (size_t)p->n_pts; break;
-    case 3: *dev_ptr = p->bincount; *bytes = sizeof(int32_t) * (size_t)p->nbins; break;
-    case 4: *dev_ptr = p->binstart; *bytes = sizeof(int32_t) * (size_t)p->nbins; break;
-    case 5: *dev_ptr = p->rowtouched; *bytes = (size_t)p->nft; break;
-    case 6: *dev_ptr = p->S; *bytes = p->csize * (size_t)p->F * p->nft * p->Kp; break;
+    case 3: *dev_ptr = p->binstart; *bytes = sizeof(int32_t) * (size_t)(p->nbins + 1); break;
+    case 4: *dev_ptr = p->rowtouched; *bytes = (size_t)p->nft; break;
+    case 5: *dev_ptr = p->S; *bytes = p->csize * (size_t)p->F * p->nft * p->Kp; break;
     default: return NUFFT2_ERR_ARG;
     }
     return NUFFT2_OK;

@@ -3,11 +3,12 @@
 // by gather tile ("bin").
 //
 // Pipeline (all on the plan's stream):
-//   k_fill_zero        clear bin counts and the theta-row marks
 //   k_setpts_bin       per point: wrap/split, bin id, rank within the bin
-//                      (atomic), mark the first-tap theta row
-//   k_bin_scan         one workgroup: exclusive scan of the bin counts, and
-//                      the set of theta rows any point's taps reach
+//                      (one atomic per bin and wave), mark the first-tap
+//                      theta row
+//   k_bin_scan         one workgroup: exclusive scan of the bin counts, the
+//                      set of theta rows any point's taps reach; clears the
+//                      counters and marks for the next call
 //   k_setpts_scatter   per point: recompute the split, write the packed
 //                      record at binstart[bin] + rank, and the permutation
 //
@@ -17,23 +18,6 @@
 #include "nufft2_internal.hpp"
 
 namespace nufft2 {
-
-__global__ void k_fill_zero(uint32_t *p, int64_t n_words)
-{
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += stride)
-        p[i] = 0u;
-}
-
-hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
-{
-    const int64_t words = (int64_t)((bytes + 3) / 4);
-    if (words == 0) return hipSuccess;
-    int64_t blocks = (words + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)p, words);
-    return hipGetLastError();
-}
 
 // Split one FP64 coordinate x (radians, any real) into (i0 mod nf, v).
 // t = x * nf / 2pi is reduced into [0, nf) exactly (nf is a power of two, so
@@ -56,30 +40,52 @@ __device__ inline void split_axis(double x, const AxisParams &ax, int w, int32_t
     v = (T)(u - (double)(w >> 1));
 }
 
-template <typename T>
-__global__ void k_setpts_bin(const double *__restrict__ phi, const double *__restrict__ theta,
-                             SetptsParams sp, int32_t *__restrict__ bincount,
-                             int2 *__restrict__ keyrank, uint8_t *__restrict__ rowmark,
-                             int32_t *__restrict__ flags)
+// Rank of this lane's point among the points of its bin: lanes of a wave
+// that share a bin are grouped with ballots and take one atomic per group
+// (departure points arrive in grid order, so a wave touches only a few bins).
+__device__ inline int32_t wave_aggregated_rank(int32_t *__restrict__ bincount, int32_t bin)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < sp.n; j += stride) {
-        const double ph = phi[j], th = theta[j];
-        int32_t bin;
-        if (!isfinite(ph) || !isfinite(th)) {
-            atomicOr(flags, 1);
-            bin = 0;
-        } else {
-            int32_t it, ip;
-            T vt, vp;
-            split_axis<T>(th, sp.th, sp.w, it, vt);
-            split_axis<T>(ph, sp.ph, sp.w, ip, vp);
-            bin = (it / sp.th.tile) * sp.nbins_phi + ip / sp.ph.tile;
-            rowmark[it] = 1;
-        }
-        const int32_t rank = atomicAdd(&bincount[bin], 1);
-        keyrank[j] = make_int2(bin, rank);
+    const int lane = (int)__lane_id();
+    uint64_t pending = __ballot(1);
+    int32_t rank = 0;
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int32_t lbin = __shfl(bin, leader, 64);
+        const uint64_t grp = pending & __ballot(bin == lbin);
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(&bincount[lbin], (int32_t)__popcll(grp));
+        base = __shfl(base, leader, 64);
+        if ((grp >> lane) & 1ull) rank = base + (int32_t)__popcll(grp & ((1ull << lane) - 1ull));
+        pending &= ~grp;
     }
+    return rank;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_setpts_bin(const double *__restrict__ phi,
+                                                    const double *__restrict__ theta, SetptsParams sp,
+                                                    int32_t *__restrict__ bincount,
+                                                    int2 *__restrict__ keyrank,
+                                                    uint8_t *__restrict__ rowmark,
+                                                    int32_t *__restrict__ flags)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= sp.n) return;
+    const double ph = phi[j], th = theta[j];
+    int32_t bin;
+    if (!isfinite(ph) || !isfinite(th)) {
+        atomicOr(&flags[0], 1);
+        bin = 0;
+    } else {
+        int32_t it, ip;
+        T vt, vp;
+        split_axis<T>(th, sp.th, sp.w, it, vt);
+        split_axis<T>(ph, sp.ph, sp.w, ip, vp);
+        bin = (it / sp.th.tile) * sp.nbins_phi + ip / sp.ph.tile;
+        rowmark[it] = 1;
+    }
+    const int32_t rank = wave_aggregated_rank(bincount, bin);
+    keyrank[j] = make_int2(bin, rank);
 }
 
 // Block-wide exclusive scan of one int per thread (blockDim.x a multiple of 64).
@@ -113,51 +119,87 @@ __device__ inline int block_exclusive_scan(int x, int *lds, int &total)
     return res;
 }
 
-// One workgroup of 1024 threads.  Each pass scans CHUNK * 1024 bins, every
-// thread owning CHUNK consecutive bins.
-__global__ __launch_bounds__(1024) void k_bin_scan(const int32_t *__restrict__ bincount,
-                                                   int32_t *__restrict__ binstart, int64_t nbins,
-                                                   const uint8_t *__restrict__ rowmark,
-                                                   uint8_t *__restrict__ rowtouched, int nft, int w)
+// One workgroup of 1024 threads.  Each pass stages CHUNK * 1024 bin counts
+// in LDS with coalesced loads, every thread scans CHUNK consecutive counts,
+// and the starts go back out through LDS with coalesced stores.  binstart
+// gets nbins + 1 entries (the last is the number of points).  The kernel
+// also leaves the counters, the row marks and the non-finite accumulator
+// cleared for the next setpts, and publishes the non-finite flag in flags[1].
+constexpr int kScanThreads = 1024;
+constexpr int kScanChunk = 8;
+// one padding slot after every kScanChunk counts keeps a thread's chunk in
+// its own LDS banks
+__device__ constexpr int scan_slot(int e) { return e + e / kScanChunk; }
+
+__global__ __launch_bounds__(kScanThreads) void k_bin_scan(int32_t *__restrict__ bincount,
+                                                           int32_t *__restrict__ binstart,
+                                                           int64_t nbins,
+                                                           uint8_t *__restrict__ rowmark,
+                                                           uint8_t *__restrict__ rowtouched,
+                                                           int nft, int w,
+                                                           int32_t *__restrict__ flags)
 {
-    constexpr int CHUNK = 16;
     __shared__ int lds[33];
+    __shared__ int stage[kScanChunk * kScanThreads + kScanThreads];
+    constexpr int PASS = kScanChunk * kScanThreads;
     int carry = 0;
-    for (int64_t base = 0; base < nbins; base += (int64_t)CHUNK * blockDim.x) {
-        const int64_t mine = base + (int64_t)threadIdx.x * CHUNK;
-        int vals[CHUNK];
+    for (int64_t base = 0; base < nbins; base += PASS) {
+        const int n = (int)((nbins - base) < PASS ? (nbins - base) : PASS);
+        for (int e = threadIdx.x; e < PASS; e += kScanThreads) {
+            int v = 0;
+            if (e < n) {
+                v = bincount[base + e];
+                bincount[base + e] = 0;
+            }
+            stage[scan_slot(e)] = v;
+        }
+        __syncthreads();
+        int vals[kScanChunk];
         int sum = 0;
 #pragma unroll
-        for (int c = 0; c < CHUNK; ++c) {
-            vals[c] = (mine + c < nbins) ? bincount[mine + c] : 0;
+        for (int c = 0; c < kScanChunk; ++c) {
+            vals[c] = stage[scan_slot(threadIdx.x * kScanChunk + c)];
             sum += vals[c];
         }
         int total;
         int run = carry + block_exclusive_scan(sum, lds, total);
 #pragma unroll
-        for (int c = 0; c < CHUNK; ++c) {
-            if (mine + c < nbins) binstart[mine + c] = run;
+        for (int c = 0; c < kScanChunk; ++c) {
+            stage[scan_slot(threadIdx.x * kScanChunk + c)] = run;
             run += vals[c];
         }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n; e += kScanThreads) binstart[base + e] = stage[scan_slot(e)];
+        __syncthreads();
         carry += total;
+    }
+    if (threadIdx.x == 0) {
+        binstart[nbins] = carry;
+        flags[1] = flags[0];
+        flags[0] = 0;
     }
     // A theta row l is read by the gather iff some point's first tap row is
     // within w - 1 rows below it (cyclically).
-    for (int l = threadIdx.x; l < nft; l += blockDim.x) {
+    for (int l = threadIdx.x; l < nft; l += kScanThreads) {
         uint8_t t = 0;
         for (int a = 0; a < w; ++a) t |= rowmark[(l - a + nft) & (nft - 1)];
         rowtouched[l] = t;
     }
+    __syncthreads();
+    for (int l = threadIdx.x; l < nft; l += kScanThreads) rowmark[l] = 0;
 }
 
 template <typename T>
-__global__ void k_setpts_scatter(const double *__restrict__ phi, const double *__restrict__ theta,
-                                 SetptsParams sp, const int2 *__restrict__ keyrank,
-                                 const int32_t *__restrict__ binstart,
-                                 PointRec<T> *__restrict__ rec, int32_t *__restrict__ perm)
+__global__ __launch_bounds__(256) void k_setpts_scatter(const double *__restrict__ phi,
+                                                        const double *__restrict__ theta,
+                                                        SetptsParams sp,
+                                                        const int2 *__restrict__ keyrank,
+                                                        const int32_t *__restrict__ binstart,
+                                                        PointRec<T> *__restrict__ rec,
+                                                        int32_t *__restrict__ perm)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < sp.n; j += stride) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < sp.n) {
         const double ph = phi[j], th = theta[j];
         PointRec<T> r;
         if (!isfinite(ph) || !isfinite(th)) {
@@ -181,14 +223,11 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
                          uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
                          int32_t *flags, hipStream_t s)
 {
+    // bincount, rowmark and flags[0] are zero on entry: the plan clears them
+    // once and every k_bin_scan leaves them cleared.
     hipError_t e;
-    if ((e = launch_fill_zero(bincount, sizeof(int32_t) * (size_t)nbins, s)) != hipSuccess) return e;
-    if ((e = launch_fill_zero(rowmark, (size_t)sp.th.nf, s)) != hipSuccess) return e;
-    if ((e = launch_fill_zero(flags, sizeof(int32_t), s)) != hipSuccess) return e;
     const int threads = 256;
-    int64_t blocks = (sp.n + threads - 1) / threads;
-    if (blocks > 65536) blocks = 65536;
-    if (blocks < 1) blocks = 1;
+    const int64_t blocks = (sp.n + threads - 1) / threads;
     if (sp.n > 0) {
         if (prec == 1)
             hipLaunchKernelGGL(k_setpts_bin<float>, dim3((unsigned)blocks), dim3(threads), 0, s, phi,
@@ -198,8 +237,8 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
                                theta, sp, bincount, keyrank, rowmark, flags);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, bincount, binstart, nbins, rowmark,
-                       rowtouched, sp.th.nf, sp.w);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kScanThreads), 0, s, bincount, binstart, nbins, rowmark,
+                       rowtouched, sp.th.nf, sp.w, flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (sp.n > 0) {
         if (prec == 1)

@@ -30,8 +30,11 @@ NUFFT2_FP64 = 2
 EXPORTED = (
     "nufft2_plan", "nufft2_setpts", "nufft2_exec", "nufft2_destroy", "nufft2_strerror",
     "nufft2_get_info", "nufft2_check", "nufft2_set_stream", "nufft2_kernel_params",
-    "nufft2_kernel_correction", "nufft2_debug_buffer",
+    "nufft2_kernel_correction", "nufft2_debug_buffer", "nufft2_profile_enable",
+    "nufft2_profile_read",
 )
+NUFFT2_N_STAGES = 4
+STAGE_NAMES = ("setpts", "theta_pass", "phi_pass", "gather")
 
 
 class nufft2_opts(ctypes.Structure):
@@ -73,6 +76,8 @@ def _load():
         "nufft2_kernel_params": [i32, dbl, ctypes.POINTER(i32), ctypes.POINTER(dbl)],
         "nufft2_kernel_correction": [i64, i64, i32, dbl, vp],
         "nufft2_debug_buffer": [H, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_uint64)],
+        "nufft2_profile_enable": [H, ctypes.c_uint32],
+        "nufft2_profile_read": [H, vp, vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -160,6 +165,19 @@ def nufft2_debug_buffer(handle, which):
     return st, (ptr.value or 0), nbytes.value
 
 
+def nufft2_profile_enable(handle, stage_mask):
+    return _lib.nufft2_profile_enable(handle, int(stage_mask))
+
+
+def nufft2_profile_read(handle):
+    """Returns (status, total_ms[4], count[4])."""
+    import numpy as np
+    ms = np.zeros(NUFFT2_N_STAGES, dtype=np.float64)
+    cnt = np.zeros(NUFFT2_N_STAGES, dtype=np.int64)
+    st = _lib.nufft2_profile_read(handle, ms.ctypes.data, cnt.ctypes.data)
+    return st, ms, cnt
+
+
 # ---- torch convenience -----------------------------------------------------
 class Plan:
     """A plan bound to torch tensors on the current device and stream.
@@ -224,6 +242,14 @@ class Plan:
     def check(self):
         st = nufft2_check(self.handle)
         return st
+
+    def profile(self, stage_mask):
+        _check(nufft2_profile_enable(self.handle, stage_mask), "nufft2_profile_enable")
+
+    def profile_read(self):
+        st, ms, cnt = nufft2_profile_read(self.handle)
+        _check(st, "nufft2_profile_read")
+        return {STAGE_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(NUFFT2_N_STAGES)}
 
     def debug_buffer(self, which):
         st, ptr, nbytes = nufft2_debug_buffer(self.handle, which)
