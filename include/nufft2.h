@@ -82,7 +82,7 @@ typedef struct {
  *           NUFFT2_FP64: everything in FP64.  eps >= 1e-15.
  *   The kernel width is w = ceil(log10(1/eps)) + 1 (13 at 1e-12, 7 at 1e-6)
  *   unless opts->w is set.  The fine grid is the smallest power of two
- *   >= max(2 * modes, 2 * w, 16) per dimension and must not exceed 4096.
+ *   >= max(2 * modes, 2 * w, 32) per dimension and must not exceed 4096.
  *   opts may be NULL.  stream is a hipStream_t (NULL: the null stream).
  *   The plan owns every device workspace; it allocates on the current device.
  *   Errors: ERR_ARG, ERR_EPS_RANGE, ERR_ALLOC, ERR_HIP.  *out is set only on

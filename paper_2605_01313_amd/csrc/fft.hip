@@ -6,7 +6,7 @@
 // (unnormalised inverse DFT of the deconvolved, zero-padded coefficients).
 //
 //   theta pass: for each phi mode m (a batch of columns per workgroup), the
-//     transform over n of the K_theta deconvolved coefficients.  Because
+//     transform over n of the deconvolved coefficients c[n][m] corr_t[n] corr_p[m].  Because
 //     K_theta <= nft / 2 (upsampling factor 2), the even and odd output rows
 //     are two independent half-length transforms:
 //         b[2q + r] = sum_n (x_n e^{2 pi i n r / nft}) e^{2 pi i n q / (nft/2)},
@@ -150,11 +150,12 @@ __device__ inline void job_of(int q, int logB, int &j, int &b)
 // One Stockham stage: butterfly (j, b) takes elements j + r N/R, applies
 // W_{NS R}^{r k} (k = j mod NS), transforms, and writes element
 // ((j - k) R + k) + r NS.  The first stage takes element i of sequence b
-// from ld(i, b) (global memory), the last hands element o to st(o, b, v).
-template <typename T, int LOGN, int S, int E, bool BFAST, class Loader, class Storer>
+// from ld(i, b) (global memory) and then runs pro() (work that may share the
+// loads' memory round trip); the last hands element o to st(o, b, v).
+template <typename T, int LOGN, int S, int E, bool BFAST, class Loader, class Storer, class Pro>
 __device__ inline void stockham_stage(cplx<T> *s, int logB, int IS, int BS,
                                       const cplx<T> *__restrict__ tws, const Loader &ld,
-                                      const Storer &st)
+                                      const Storer &st, const Pro &pro)
 {
     using P = StagePlan<LOGN>;
     constexpr int N = 1 << LOGN;
@@ -182,7 +183,8 @@ __device__ inline void stockham_stage(cplx<T> *s, int logB, int IS, int BS,
             for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], twiddle(tws, r * k * STRIDE));
         }
     }
-    if constexpr (!FIRST) __syncthreads();
+    if constexpr (FIRST) pro();
+    else __syncthreads();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         dft<R>(&v[q * R]);
@@ -199,15 +201,23 @@ __device__ inline void stockham_stage(cplx<T> *s, int logB, int IS, int BS,
     if constexpr (!LAST) __syncthreads();
 }
 
-template <typename T, int LOGN, int S, int E, bool BFAST, class Loader, class Storer>
+template <typename T, int LOGN, int S, int E, bool BFAST, class Loader, class Storer, class Pro>
 __device__ inline void fft_stages(cplx<T> *s, int logB, int IS, int BS, const cplx<T> *tws,
-                                  const Loader &ld, const Storer &st)
+                                  const Loader &ld, const Storer &st, const Pro &pro)
 {
     if constexpr (S < StagePlan<LOGN>::NST) {
-        stockham_stage<T, LOGN, S, E, BFAST>(s, logB, IS, BS, tws, ld, st);
-        fft_stages<T, LOGN, S + 1, E, BFAST>(s, logB, IS, BS, tws, ld, st);
+        stockham_stage<T, LOGN, S, E, BFAST>(s, logB, IS, BS, tws, ld, st, pro);
+        fft_stages<T, LOGN, S + 1, E, BFAST>(s, logB, IS, BS, tws, ld, st, pro);
     }
 }
+
+// Prologue that copies the twiddle tables into LDS (needed from stage 1 on).
+template <typename C> struct TwiddleCopy {
+    C *dst;
+    const C *src;
+    int n;
+    __device__ void operator()() const { load_twiddles(dst, src, n); }
+};
 
 // Workgroup id -> work item, so that each XCD (workgroups are dealt to the 8
 // XCDs round-robin) takes a contiguous run of work items and neighbouring
@@ -229,22 +239,26 @@ __device__ inline int mode_of(int i, int K, int L)
 }
 
 // Even rows (parity 0): x_n = c[n][m] corr_t[n] corr_p[m];
-// odd rows (parity 1): x_n e^{2 pi i n / nft}.
+// odd rows (parity 1):   x_n = c[n][m] corr_t[n] corr_p[m] e^{2 pi i n / nft}.
+// fac holds the two theta factor tables ([2][Kt] complex); cpm is corr_p of
+// the thread's column, which is the same for all its jobs (the block size is
+// a multiple of the column batch).
 template <typename T> struct ThetaLoad {
     const cplx<T> *coef;  // this field
-    const T *ct, *cp;
-    const cplx<T> *twist;  // e^{2 pi i n / nft}
-    int Kt, Kp, L, m0, parity;
+    const cplx<T> *fac;   // this parity's factors
+    T cpm;
+    int Kt, Kp, L, m0;
+    // Loads are unconditional (clamped indices) so that the compiler issues
+    // every element's loads before the first wait; padding slots select 0.
     __device__ cplx<T> operator()(int i, int b) const
     {
         const int m = m0 + b;
         const int a = mode_of(i, Kt, L);
-        if (a < 0 || m >= Kp) return {(T)0, (T)0};
-        const cplx<T> c = coef[(int64_t)a * Kp + m];
-        const T sc = ct[a] * cp[m];
-        cplx<T> x = {c.x * sc, c.y * sc};
-        if (parity) x = cmul(x, twist[a]);
-        return x;
+        const bool live = a >= 0 && m < Kp;
+        const int ac = live ? a : 0, mc = live ? m : 0;
+        const cplx<T> f = fac[ac];
+        const cplx<T> x = cmul(coef[(int64_t)ac * Kp + mc], cplx<T>{f.x * cpm, f.y * cpm});
+        return live ? x : cplx<T>{(T)0, (T)0};
     }
 };
 
@@ -268,25 +282,26 @@ template <typename T> constexpr int theta_max_threads() { return sizeof(T) == 4 
 // coefficient batch hits its L2.
 template <typename T, int LOGL, int E>
 __global__ __launch_bounds__(theta_max_threads<T>()) void k_theta_pass(
-    const cplx<T> *__restrict__ coeffs, const T *__restrict__ corr_t,
-    const cplx<T> *__restrict__ twist_t /* e^{2 pi i n / nft} */, const T *__restrict__ corr_p,
-    const cplx<T> *__restrict__ tws, const uint8_t *__restrict__ touched, cplx<T> *__restrict__ S,
-    FFTParams fp)
+    const cplx<T> *__restrict__ coeffs, const cplx<T> *__restrict__ fac_t,
+    const T *__restrict__ corr_p, const cplx<T> *__restrict__ tws,
+    const uint8_t *__restrict__ touched, cplx<T> *__restrict__ S, FFTParams fp)
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
     cplx<T> *s = tw + tw_lds_len(1 << LOGL);
-    load_twiddles(tw, tws, tw_lds_len(1 << LOGL));
     const int ntiles = (fp.Kp + fp.theta_batch - 1) / fp.theta_batch;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int parity = item & 1;
     const int tile = item >> 1;
     const int f = tile / ntiles;
     const int m0 = (tile - f * ntiles) * fp.theta_batch;
-    ThetaLoad<T> ld{coeffs + (int64_t)f * fp.Kt * fp.Kp, corr_t, corr_p, twist_t,
-                    fp.Kt, fp.Kp, 1 << LOGL, m0, parity};
+    const int mt = m0 + ((int)threadIdx.x & (fp.theta_batch - 1));
+    const T cpm = corr_p[mt < fp.Kp ? mt : 0];
+    ThetaLoad<T> ld{coeffs + (int64_t)f * fp.Kt * fp.Kp, fac_t + parity * fp.Kt, cpm, fp.Kt, fp.Kp,
+                    1 << LOGL, m0};
     ThetaStore<T> st{S + (int64_t)f * fp.nft * fp.Kp, touched, fp.Kp, m0, parity};
-    fft_stages<T, LOGL, 0, E, true>(s, fp.log_theta_batch, fp.theta_batch, 1, tw, ld, st);
+    TwiddleCopy<cplx<T>> pro{tw, tws, tw_lds_len(1 << LOGL)};
+    fft_stages<T, LOGL, 0, E, true>(s, fp.log_theta_batch, fp.theta_batch, 1, tw, ld, st, pro);
 }
 
 template <typename T> struct PhiStore {
@@ -306,8 +321,8 @@ template <typename T> struct PhiLoad {
     __device__ cplx<T> operator()(int i, int b) const
     {
         const int a = mode_of(i, Kp, nfp);
-        if (a < 0) return {(T)0, (T)0};
-        return S[(int64_t)(l0 + b) * Kp + a];
+        const cplx<T> v = S[(int64_t)(l0 + b) * Kp + (a < 0 ? 0 : a)];
+        return a < 0 ? cplx<T>{(T)0, (T)0} : v;
     }
 };
 
@@ -328,30 +343,31 @@ __global__ __launch_bounds__(256) void k_phi_pass(const cplx<T> *__restrict__ S,
     int any = 0;
     for (int b = 0; b < fp.phi_batch; ++b) any |= touched[l0 + b];
     if (!any) return;
-    load_twiddles(tw, tws, tw_lds_len(1 << LOGN));
     PhiLoad<T> ld{S + (int64_t)f * fp.nft * fp.Kp, fp.Kp, fp.nfp, l0};
     PhiStore<T> st{grid + (int64_t)f * fp.nft * fp.nfp, touched, fp.nfp, l0};
-    fft_stages<T, LOGN, 0, E, false>(s, fp.log_phi_batch, 1, lds_seq_len(1 << LOGN), tw, ld, st);
+    TwiddleCopy<cplx<T>> pro{tw, tws, tw_lds_len(1 << LOGN)};
+    fft_stages<T, LOGN, 0, E, false>(s, fp.log_phi_batch, 1, lds_seq_len(1 << LOGN), tw, ld, st, pro);
 }
 
 constexpr int kElemsPerThread = 16;
 
 template <typename T, int LOGL>
-static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const void *corr_t,
-                                 const void *twist_t, const void *corr_p, const void *tws_t,
-                                 const uint8_t *touched, void *S, hipStream_t s)
+static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const void *fac_t,
+                                 const void *corr_p, const void *tws_t, const uint8_t *touched,
+                                 void *S, hipStream_t s)
 {
     const int L = 1 << LOGL;
     const int threads = L * fp.theta_batch / kElemsPerThread;
-    if (threads < 1 || threads > theta_max_threads<T>()) return hipErrorInvalidConfiguration;
+    if (threads < 1 || threads > theta_max_threads<T>() || threads % fp.theta_batch != 0)
+        return hipErrorInvalidConfiguration;
     const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(L) * fp.theta_batch + tw_lds_len(L));
     auto kern = k_theta_pass<T, LOGL, kElemsPerThread>;
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int ntiles = (fp.Kp + fp.theta_batch - 1) / fp.theta_batch;
     hipLaunchKernelGGL(kern, dim3(2 * ntiles * fp.n_fields), dim3(threads), lds, s,
-                       (const cplx<T> *)coeffs, (const T *)corr_t, (const cplx<T> *)twist_t,
-                       (const T *)corr_p, (const cplx<T> *)tws_t, touched, (cplx<T> *)S, fp);
+                       (const cplx<T> *)coeffs, (const cplx<T> *)fac_t, (const T *)corr_p,
+                       (const cplx<T> *)tws_t, touched, (cplx<T> *)S, fp);
     return hipGetLastError();
 }
 
@@ -372,13 +388,13 @@ static hipError_t launch_phi_t(const FFTParams &fp, const void *S, const void *t
 }
 
 template <typename T>
-static hipError_t theta_dispatch(const FFTParams &fp, const void *coeffs, const void *corr_t,
-                                 const void *twist_t, const void *corr_p, const void *tws_t,
-                                 const uint8_t *touched, void *S, hipStream_t s)
+static hipError_t theta_dispatch(const FFTParams &fp, const void *coeffs, const void *fac_t,
+                                 const void *corr_p, const void *tws_t, const uint8_t *touched,
+                                 void *S, hipStream_t s)
 {
     switch (fp.log_nft - 1) {
-#define NUFFT2_L(X) case X: return launch_theta_t<T, X>(fp, coeffs, corr_t, twist_t, corr_p, tws_t, touched, S, s);
-        NUFFT2_L(3) NUFFT2_L(4) NUFFT2_L(5) NUFFT2_L(6) NUFFT2_L(7) NUFFT2_L(8) NUFFT2_L(9)
+#define NUFFT2_L(X) case X: return launch_theta_t<T, X>(fp, coeffs, fac_t, corr_p, tws_t, touched, S, s);
+        NUFFT2_L(4) NUFFT2_L(5) NUFFT2_L(6) NUFFT2_L(7) NUFFT2_L(8) NUFFT2_L(9)
         NUFFT2_L(10) NUFFT2_L(11)
 #undef NUFFT2_L
     default: return hipErrorInvalidValue;
@@ -391,20 +407,19 @@ static hipError_t phi_dispatch(const FFTParams &fp, const void *S, const void *t
 {
     switch (fp.log_nfp) {
 #define NUFFT2_N(X) case X: return launch_phi_t<T, X>(fp, S, tw_p, touched, grid, s);
-        NUFFT2_N(4) NUFFT2_N(5) NUFFT2_N(6) NUFFT2_N(7) NUFFT2_N(8) NUFFT2_N(9) NUFFT2_N(10)
+        NUFFT2_N(5) NUFFT2_N(6) NUFFT2_N(7) NUFFT2_N(8) NUFFT2_N(9) NUFFT2_N(10)
         NUFFT2_N(11) NUFFT2_N(12)
 #undef NUFFT2_N
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_theta_pass(int prec, const FFTParams &fp, const void *coeffs, const void *corr_t,
-                             const void *twist_t, const void *corr_p, const void *tws_t,
-                             const uint8_t *rowtouched, void *S, hipStream_t s)
+hipError_t launch_theta_pass(int prec, const FFTParams &fp, const void *coeffs, const void *fac_t,
+                             const void *corr_p, const void *tws_t, const uint8_t *rowtouched,
+                             void *S, hipStream_t s)
 {
-    if (prec == 1)
-        return theta_dispatch<float>(fp, coeffs, corr_t, twist_t, corr_p, tws_t, rowtouched, S, s);
-    return theta_dispatch<double>(fp, coeffs, corr_t, twist_t, corr_p, tws_t, rowtouched, S, s);
+    if (prec == 1) return theta_dispatch<float>(fp, coeffs, fac_t, corr_p, tws_t, rowtouched, S, s);
+    return theta_dispatch<double>(fp, coeffs, fac_t, corr_p, tws_t, rowtouched, S, s);
 }
 
 hipError_t launch_phi_pass(int prec, const FFTParams &fp, const void *S, const void *tw_p,

@@ -33,6 +33,7 @@ template <> __device__ inline double es_kernel<double>(double z, double beta)
 constexpr int kGatherMaxFields = 4;
 
 constexpr int kGatherThreads = 256;
+constexpr int kLoadBatch = 4;
 
 template <typename T, int W, int FG>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(const cplx<T> *__restrict__ grid,
@@ -62,12 +63,32 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const cplx<T> *__rest
     for (int f0 = 0; f0 < gp.n_fields; f0 += FG) {
         const int fg = min(FG, gp.n_fields - f0);
         __syncthreads();
-        for (int e = threadIdx.x; e < tile_elems; e += blockDim.x) {
-            const int rr = e / TC, cc = e - rr * TC;
-            const int64_t off = (int64_t)((r0 + rr) & (gp.nft - 1)) * gp.nfp + ((c0 + cc) & (gp.nfp - 1));
+        // Stage the patch: each thread issues the loads of up to kLoadBatch
+        // elements (all fields) before it stores any of them, so that one
+        // memory round trip serves the batch.
+        for (int e0 = 0; e0 < tile_elems; e0 += kLoadBatch * kGatherThreads) {
+            cplx<T> buf[kLoadBatch][FG];
 #pragma unroll
-            for (int f = 0; f < FG; ++f)
-                if (f < fg) tiles[f * tile_elems + e] = grid[(int64_t)(f0 + f) * field_stride + off];
+            for (int u = 0; u < kLoadBatch; ++u) {
+                const int e = e0 + u * kGatherThreads + (int)threadIdx.x;
+                const int ec = e < tile_elems ? e : 0;
+                const int rr = ec / TC, cc = ec - rr * TC;
+                const int64_t off =
+                    (int64_t)((r0 + rr) & (gp.nft - 1)) * gp.nfp + ((c0 + cc) & (gp.nfp - 1));
+#pragma unroll
+                for (int f = 0; f < FG; ++f) {
+                    const int ff = f0 + (f < fg ? f : 0);
+                    buf[u][f] = grid[(int64_t)ff * field_stride + off];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u) {
+                const int e = e0 + u * kGatherThreads + (int)threadIdx.x;
+                if (e < tile_elems) {
+#pragma unroll
+                    for (int f = 0; f < FG; ++f) tiles[f * tile_elems + e] = buf[u][f];
+                }
+            }
         }
         __syncthreads();
         for (int base = 0; base < cnt; base += blockDim.x) {

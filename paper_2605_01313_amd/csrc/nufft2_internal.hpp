@@ -47,12 +47,12 @@ struct FFTParams {
     int32_t phi_batch, log_phi_batch;       // rows per phi-pass workgroup
 };
 
-// corr_t: real [Kt]; twist_t: complex [Kt], e^{2 pi i n / nft} (n = a - Kt/2);
-// corr_p: real [Kp]; tws_t / tws_p: twiddle tables of the nft/2- and
-// nfp-point transforms (64 low entries, then the high entries; see fft.hip).
-hipError_t launch_theta_pass(int prec, const FFTParams &fp, const void *coeffs, const void *corr_t,
-                             const void *twist_t, const void *corr_p, const void *tws_t,
-                             const uint8_t *rowtouched, void *S, hipStream_t s);
+// fac_t: complex [2][Kt]: corr_t[a], then corr_t[a] e^{2 pi i n / nft}
+// (n = a - Kt/2); corr_p: real [Kp]; tws_t / tws_p: twiddle tables of the
+// nft/2- and nfp-point transforms (64 low entries, then the high entries).
+hipError_t launch_theta_pass(int prec, const FFTParams &fp, const void *coeffs, const void *fac_t,
+                             const void *corr_p, const void *tws_t, const uint8_t *rowtouched,
+                             void *S, hipStream_t s);
 hipError_t launch_phi_pass(int prec, const FFTParams &fp, const void *S, const void *tws_p,
                            const uint8_t *rowtouched, void *grid, hipStream_t s);
 

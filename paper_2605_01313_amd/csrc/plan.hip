@@ -49,7 +49,7 @@ struct nufft2_plan_s {
     // device workspaces
     void *corr_t = nullptr, *corr_p = nullptr;
     void *tw_t = nullptr, *tw_p = nullptr;  // two-level twiddle tables
-    void *twist_t = nullptr;                // e^{2 pi i n / nft} per theta mode
+    void *twist_t = nullptr;                // [2][Kt]: corr_t[a], corr_t[a] e^{2 pi i n / nft}
     void *S = nullptr, *grid = nullptr;
     int32_t *bincount = nullptr, *binstart = nullptr;
     uint8_t *rowmark = nullptr, *rowtouched = nullptr;
@@ -223,15 +223,17 @@ template <typename T> nufft2_status upload_tables(nufft2_plan_s *p)
     st = kernel_correction(p->Kp, p->nfp, p->w, p->beta, cp.data());
     if (st != NUFFT2_OK) return st;
     std::vector<T> ctT(ct.begin(), ct.end()), cpT(cp.begin(), cp.end());
-    std::vector<T> twt, twp, twist(2 * (size_t)p->Kt);
+    std::vector<T> twt, twp, twist(4 * (size_t)p->Kt);
     fill_twiddle_tables<T>(twt, p->nft / 2);
     fill_twiddle_tables<T>(twp, p->nfp);
     {
         const long double two_pi = 6.283185307179586476925286766559005768L;
         for (int64_t a = 0; a < p->Kt; ++a) {
             const long double ang = two_pi * (long double)(a - p->Kt / 2) / (long double)p->nft;
-            twist[2 * a] = (T)cosl(ang);
-            twist[2 * a + 1] = (T)sinl(ang);
+            twist[2 * a] = (T)ct[a];
+            twist[2 * a + 1] = (T)0;
+            twist[2 * (p->Kt + a)] = (T)((long double)ct[a] * cosl(ang));
+            twist[2 * (p->Kt + a) + 1] = (T)((long double)ct[a] * sinl(ang));
         }
     }
     hipError_t e;
@@ -356,7 +358,7 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     auto fine = [&](int64_t K) {
         int64_t n = 2 * K;
         if (n < 2 * w) n = 2 * w;
-        if (n < 16) n = 16;
+        if (n < 32) n = 32;
         return int64_t(1) << ilog2(n);
     };
     const int64_t nft = fine(n_modes_theta), nfp = fine(n_modes_phi);
@@ -438,7 +440,7 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     const size_t rs = p->rsize, cs = p->csize;
     bool ok = dev_alloc(p, &p->corr_t, rs * p->Kt) && dev_alloc(p, &p->corr_p, rs * p->Kp) &&
               dev_alloc(p, &p->tw_t, cs * (64 + p->nft)) && dev_alloc(p, &p->tw_p, cs * (64 + p->nfp)) &&
-              dev_alloc(p, &p->twist_t, cs * p->Kt) &&
+              dev_alloc(p, &p->twist_t, 2 * cs * p->Kt) &&
               dev_alloc(p, &p->S, cs * (size_t)p->F * p->nft * p->Kp) &&
               dev_alloc(p, &p->grid, cs * (size_t)p->F * p->nft * p->nfp) &&
               dev_alloc(p, (void **)&p->bincount, sizeof(int32_t) * (size_t)p->nbins) &&
@@ -536,8 +538,8 @@ NUFFT2_API nufft2_status nufft2_exec(nufft2_handle p, const void *coeffs_dev, vo
     if (p->n_pts == 0) return NUFFT2_OK;
     if (!coeffs_dev || !out_dev) return NUFFT2_ERR_ARG;
     int slot = prof_begin(p, 1);
-    hipError_t e = launch_theta_pass(p->prec, p->fp, coeffs_dev, p->corr_t, p->twist_t, p->corr_p,
-                                     p->tw_t, p->rowtouched, p->S, p->stream);
+    hipError_t e = launch_theta_pass(p->prec, p->fp, coeffs_dev, p->twist_t, p->corr_p, p->tw_t,
+                                     p->rowtouched, p->S, p->stream);
     prof_end(p, slot);
     if (e != hipSuccess) return fail_hip(p, e);
     slot = prof_begin(p, 2);
