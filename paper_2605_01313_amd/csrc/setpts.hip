@@ -40,25 +40,31 @@ __device__ inline void split_axis(double x, const AxisParams &ax, int w, int32_t
     v = (T)(u - (double)(w >> 1));
 }
 
-// Rank of this lane's point among the points of its bin: lanes of a wave
-// that share a bin are grouped with ballots and take one atomic per group
-// (departure points arrive in grid order, so a wave touches only a few bins).
+// Rank of this lane's point among the points of its bin.  Lanes of a wave
+// that share a bin are grouped with ballots first (no memory traffic); then
+// every group leader adds its group's size with one atomic, all leaders in
+// the same instruction, so the wave pays one atomic round trip.  Departure
+// points arrive in grid order, so a wave touches only a few bins.
 __device__ inline int32_t wave_aggregated_rank(int32_t *__restrict__ bincount, int32_t bin)
 {
     const int lane = (int)__lane_id();
     uint64_t pending = __ballot(1);
-    int32_t rank = 0;
+    int leader_of_mine = lane;
+    int32_t offset = 0, count = 0;
     while (pending) {
         const int leader = __ffsll((unsigned long long)pending) - 1;
         const int32_t lbin = __shfl(bin, leader, 64);
         const uint64_t grp = pending & __ballot(bin == lbin);
-        int32_t base = 0;
-        if (lane == leader) base = atomicAdd(&bincount[lbin], (int32_t)__popcll(grp));
-        base = __shfl(base, leader, 64);
-        if ((grp >> lane) & 1ull) rank = base + (int32_t)__popcll(grp & ((1ull << lane) - 1ull));
+        if ((grp >> lane) & 1ull) {
+            leader_of_mine = leader;
+            offset = (int32_t)__popcll(grp & ((1ull << lane) - 1ull));
+        }
+        if (lane == leader) count = (int32_t)__popcll(grp);
         pending &= ~grp;
     }
-    return rank;
+    int32_t base = 0;
+    if (count > 0) base = atomicAdd(&bincount[bin], count);
+    return __shfl(base, leader_of_mine, 64) + offset;
 }
 
 template <typename T>
@@ -179,14 +185,20 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_scan(int32_t *__restrict__
         flags[0] = 0;
     }
     // A theta row l is read by the gather iff some point's first tap row is
-    // within w - 1 rows below it (cyclically).
+    // within w - 1 rows below it (cyclically).  The marks are staged in LDS
+    // (coalesced) so the w-wide window reads hit LDS, not global memory.
+    uint8_t *marks = reinterpret_cast<uint8_t *>(stage);
+    __syncthreads();
     for (int l = threadIdx.x; l < nft; l += kScanThreads) {
-        uint8_t t = 0;
-        for (int a = 0; a < w; ++a) t |= rowmark[(l - a + nft) & (nft - 1)];
-        rowtouched[l] = t;
+        marks[l] = rowmark[l];
+        rowmark[l] = 0;
     }
     __syncthreads();
-    for (int l = threadIdx.x; l < nft; l += kScanThreads) rowmark[l] = 0;
+    for (int l = threadIdx.x; l < nft; l += kScanThreads) {
+        uint8_t t = 0;
+        for (int a = 0; a < w; ++a) t |= marks[(l - a + nft) & (nft - 1)];
+        rowtouched[l] = t;
+    }
 }
 
 template <typename T>
