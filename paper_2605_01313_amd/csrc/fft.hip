@@ -128,9 +128,17 @@ __device__ inline void load_twiddles(C *dst, const C *__restrict__ src, int n)
 __device__ constexpr int lds_slot(int i) { return i + (i >> 5); }
 constexpr int lds_seq_len(int n) { return n + (n >> 5); }
 
-// Element (i, b) of the batch lives at lds_slot(i) * IS + b * BS.
-// BFAST: consecutive threads step through the batch index b (IS = B, BS = 1);
-// otherwise through i (IS = 1, BS = padded sequence length).
+// LDS address of element i of sequence b.
+// BFAST (consecutive threads step through b): lds_slot(i) * IS + b, IS = B.
+// Otherwise (threads step through i): lds_slot(i) + b * BS with BS the padded
+// sequence length.  (An odd pitch B + 1 for BFAST was measured no faster and
+// costs LDS that lowers the number of workgroups per CU.)
+template <bool BFAST>
+__device__ inline int lds_addr(int i, int b, int IS, int BS)
+{
+    if constexpr (BFAST) return lds_slot(i) * IS + b;
+    else return lds_slot(i) + b * BS;
+}
 
 // Job q of this thread in a stage of radix R over B sequences of length N.
 template <int N, int R, bool BFAST>
@@ -176,7 +184,7 @@ __device__ inline void stockham_stage(cplx<T> *s, int logB, int IS, int BS,
             for (int r = 0; r < R; ++r) v[q * R + r] = ld(j + r * NBF, b);
         } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q * R + r] = s[lds_slot(j + r * NBF) * IS + b * BS];
+            for (int r = 0; r < R; ++r) v[q * R + r] = s[lds_addr<BFAST>(j + r * NBF, b, IS, BS)];
             const int k = j & (NS - 1);
             constexpr int STRIDE = N / (NS * R);
 #pragma unroll
@@ -195,7 +203,7 @@ __device__ inline void stockham_stage(cplx<T> *s, int logB, int IS, int BS,
         for (int r = 0; r < R; ++r) {
             const int o = base + r * NS;
             if constexpr (LAST) st(o, b, v[q * R + r]);
-            else s[lds_slot(o) * IS + b * BS] = v[q * R + r];
+            else s[lds_addr<BFAST>(o, b, IS, BS)] = v[q * R + r];
         }
     }
     if constexpr (!LAST) __syncthreads();
@@ -263,18 +271,36 @@ template <typename T> struct ThetaLoad {
 };
 
 template <typename T> struct ThetaStore {
-    cplx<T> *S;  // this field, [nft][Kp]
-    const uint8_t *touched;
+    cplx<T> *S;              // this field, [nft][Kp]
+    const uint8_t *reached;  // LDS copy: reached[q] for output row 2q + parity
     int Kp, m0, parity;
     __device__ void operator()(int q, int b, cplx<T> v) const
     {
         const int m = m0 + b;
         const int l = 2 * q + parity;
-        if (m < Kp && touched[l]) S[(int64_t)l * Kp + m] = v;
+        if (m < Kp && reached[q]) S[(int64_t)l * Kp + m] = v;
+    }
+};
+
+// Prologue of the theta pass: the twiddle tables and this parity's row flags
+// go to LDS while the first stage's loads are in flight.
+template <typename C> struct ThetaPro {
+    C *tw_dst;
+    const C *tw_src;
+    int tw_n;
+    uint8_t *flags_dst;
+    const uint8_t *touched;
+    int L, parity;
+    __device__ void operator()() const
+    {
+        load_twiddles(tw_dst, tw_src, tw_n);
+        for (int q = threadIdx.x; q < L; q += blockDim.x) flags_dst[q] = touched[2 * q + parity];
     }
 };
 
 template <typename T> constexpr int theta_max_threads() { return sizeof(T) == 4 ? 1024 : 512; }
+// row flags of one parity, rounded up to 16 bytes to keep the data aligned
+constexpr int theta_flag_bytes(int L) { return (L + 15) & ~15; }
 
 // One workgroup per (field, batch of B phi modes, output parity).  The work
 // item order puts the two parities of a batch next to each other, so that
@@ -287,8 +313,10 @@ __global__ __launch_bounds__(theta_max_threads<T>()) void k_theta_pass(
     const uint8_t *__restrict__ touched, cplx<T> *__restrict__ S, FFTParams fp)
 {
     extern __shared__ unsigned char smem_raw[];
+    constexpr int L = 1 << LOGL;
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *s = tw + tw_lds_len(1 << LOGL);
+    uint8_t *flags = reinterpret_cast<uint8_t *>(tw + tw_lds_len(L));
+    cplx<T> *s = reinterpret_cast<cplx<T> *>(flags + theta_flag_bytes(L));
     const int ntiles = (fp.Kp + fp.theta_batch - 1) / fp.theta_batch;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int parity = item & 1;
@@ -298,9 +326,9 @@ __global__ __launch_bounds__(theta_max_threads<T>()) void k_theta_pass(
     const int mt = m0 + ((int)threadIdx.x & (fp.theta_batch - 1));
     const T cpm = corr_p[mt < fp.Kp ? mt : 0];
     ThetaLoad<T> ld{coeffs + (int64_t)f * fp.Kt * fp.Kp, fac_t + parity * fp.Kt, cpm, fp.Kt, fp.Kp,
-                    1 << LOGL, m0};
-    ThetaStore<T> st{S + (int64_t)f * fp.nft * fp.Kp, touched, fp.Kp, m0, parity};
-    TwiddleCopy<cplx<T>> pro{tw, tws, tw_lds_len(1 << LOGL)};
+                    L, m0};
+    ThetaStore<T> st{S + (int64_t)f * fp.nft * fp.Kp, flags, fp.Kp, m0, parity};
+    ThetaPro<cplx<T>> pro{tw, tws, tw_lds_len(L), flags, touched, L, parity};
     fft_stages<T, LOGL, 0, E, true>(s, fp.log_theta_batch, fp.theta_batch, 1, tw, ld, st, pro);
 }
 
@@ -360,7 +388,8 @@ static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const 
     const int threads = L * fp.theta_batch / kElemsPerThread;
     if (threads < 1 || threads > theta_max_threads<T>() || threads % fp.theta_batch != 0)
         return hipErrorInvalidConfiguration;
-    const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(L) * fp.theta_batch + tw_lds_len(L));
+    const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(L) * fp.theta_batch + tw_lds_len(L)) +
+                       theta_flag_bytes(L);
     auto kern = k_theta_pass<T, LOGL, kElemsPerThread>;
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -24,6 +24,7 @@ constexpr double kDefaultBetaOverW = 2.30;
 constexpr int kDefaultTileTheta = 16;
 constexpr int kDefaultTilePhi = 32;
 constexpr size_t kGatherLdsLimit = 65536;  // per staged field group
+constexpr size_t kFftLdsLimit = 155648;    // 152 KiB of the 160 KiB per workgroup
 constexpr int kGatherMaxFieldsPerPass = 4;
 
 }  // namespace
@@ -410,13 +411,23 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     fp.log_nfp = ilog2(p->nfp);
     fp.n_fields = p->F;
     {
-        // theta pass: columns per workgroup so that a row segment is >= 64 bytes,
-        // at least 64 threads, at most 1024 (FP32) / 512 (FP64) threads
+        // theta pass: columns per workgroup so that a row segment is >= 64 bytes
+        // where possible, at least 64 threads, at most 1024 (FP32) or 512 (FP64)
+        // threads, and within the per-workgroup LDS limit (data, twiddle
+        // tables, row flags).  Fewer, larger workgroups measured faster than
+        // smaller ones that share a CU.
         const int64_t L = p->nft / 2;
         const int64_t max_threads = prec == NUFFT2_FP32 ? 1024 : 512;
+        auto lds_bytes = [&](int64_t b) {
+            return (int64_t)p->csize * ((L + L / 32) * b + 64 + (L > 64 ? L / 64 : 1)) + ((L + 15) & ~15);
+        };
         int64_t b = prec == NUFFT2_FP32 ? 8 : 4;
         while (L * b < 1024) b *= 2;
-        while (L * b / 16 > max_threads) b /= 2;
+        while (b > 1 && (L * b / 16 > max_threads || lds_bytes(b) > (int64_t)kFftLdsLimit)) b /= 2;
+        if (lds_bytes(b) > (int64_t)kFftLdsLimit || L * b / 16 > max_threads) {
+            delete p;
+            return NUFFT2_ERR_ARG;
+        }
         fp.theta_batch = (int)b;
         fp.log_theta_batch = ilog2(b);
     }

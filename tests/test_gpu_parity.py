@@ -210,6 +210,22 @@ def test_white_spectrum_meets_1e12_one_width_up(torch_dev, oracle_mod):
     assert max(errs) <= 1e-12
 
 
+@pytest.mark.parametrize("prec,eps,tol", [("fp64", 1e-12, 3e-12), ("fp32", 1e-6, 3e-6)])
+def test_largest_grid(torch_dev, oracle_mod, prec, eps, tol):
+    """The 4096 x 4096 fine grid (K = 2047): plan limits hold in both precisions."""
+    rng = np.random.default_rng(4096)
+    K = 2047
+    coeffs = synth.random_complex(rng, (2, K, K)) * synth.envelope_algebraic(K, K, 1.0)[None]
+    phi = rng.uniform(0, 2 * np.pi, 600)
+    theta = rng.uniform(-0.2, np.pi + 0.2, 600)
+    say(f"case largest_grid prec={prec}")
+    plan, got = run_plan(torch_dev, prec, coeffs, phi, theta, eps)
+    assert plan.info()["nf_theta"] == 4096 and plan.check() == 0
+    errs = field_errors(got, oracle_mod.dfs_eval(coeffs, phi, theta))
+    say(f"  rel l2 {errs}")
+    assert max(errs) <= tol
+
+
 def test_zero_points_and_exec_before_setpts(torch_dev):
     torch, dev = torch_dev
     from paper_2605_01313_amd import Plan, nufft2
