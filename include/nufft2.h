@@ -179,6 +179,9 @@ nufft2_status nufft2_kernel_correction(int64_t K, int64_t nf, int32_t w, double 
  *            start[b] .. start[b+1]-1)
  *         4: theta rows reached by the current points' taps, uint8 [nf_theta]
  *         5: theta-pass output [n_fields][nf_theta][n_modes_phi] complex
+ *         6: non-empty bins, int32 [n_bins + 1]: the first k entries are the
+ *            bins holding at least one record in increasing order, entry
+ *            n_bins is k
  * *dev_ptr and *bytes describe device memory the plan owns; valid until the
  * next setpts or destroy.  Errors: ERR_ARG, ERR_NO_POINTS (points-derived
  * buffers before setpts).

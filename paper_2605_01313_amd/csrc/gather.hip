@@ -7,27 +7,39 @@
 // One workgroup per bin (a tile_t x tile_p block of first-tap cells).  The
 // workgroup stages the (tile_t + w - 1) x (tile_p + w - 1) patch of up to
 // FG fields at once in LDS, then each thread sums the w x w taps of one
-// point for all staged fields (independent accumulators per field).  The
-// column weights are computed once per point and field group, the row
-// weights on the fly.  The tap
-// order (rows a outer, columns b inner) is fixed, so a point's value does not
-// depend on where in its bin the sort placed it.
+// point for all staged fields (independent accumulators per field).  Points
+// are dealt to lanes so that the lanes the LDS serves together read different
+// banks (the chunk loop and column_rotation).  The column weights are
+// computed once per point and field group, the row weights on the fly.  The
+// tap order (rows a outer, columns inner in one of two orders fixed by the
+// point's own cell) does not depend on which lane or where in its bin the sort
+// placed the point.
 #include "nufft2_internal.hpp"
 
 namespace nufft2 {
 
-template <typename T> __device__ inline T es_kernel(T z, T beta);
-template <> __device__ inline float es_kernel<float>(float z, float beta)
+// ES kernel exp(beta (sqrt(1 - z^2) - 1)), clamped to e^{-beta} outside |z| <= 1.
+// The second argument is es_constant(beta).  FP32 uses the hardware square
+// root and base-2 exponential (about 1 ulp each, far inside a 1e-6 tolerance)
+// with beta log2(e) folded in; FP64 uses the correctly rounded library calls.
+template <typename T> __host__ __device__ inline T es_constant(double beta);
+template <> __host__ __device__ inline float es_constant<float>(double beta)
 {
-    float t = 1.0f - z * z;
-    t = t > 0.0f ? t : 0.0f;
-    return __expf(beta * (__fsqrt_rn(t) - 1.0f));
+    return (float)(beta * 1.4426950408889634);
 }
-template <> __device__ inline double es_kernel<double>(double z, double beta)
+template <> __host__ __device__ inline double es_constant<double>(double beta) { return beta; }
+
+template <typename T> __device__ inline T es_kernel(T z, T k);
+template <> __device__ inline float es_kernel<float>(float z, float k)
+{
+    const float t = fmaxf(1.0f - z * z, 0.0f);
+    return __builtin_amdgcn_exp2f(__builtin_amdgcn_sqrtf(t) * k - k);
+}
+template <> __device__ inline double es_kernel<double>(double z, double k)
 {
     double t = 1.0 - z * z;
     t = t > 0.0 ? t : 0.0;
-    return exp(beta * (sqrt(t) - 1.0));
+    return exp(k * (sqrt(t) - 1.0));
 }
 
 constexpr int kGatherMaxFields = 4;
@@ -35,18 +47,44 @@ constexpr int kGatherMaxFields = 4;
 constexpr int kGatherThreads = 256;
 constexpr int kLoadBatch = 4;
 
+// Lanes the LDS serves in one cycle for reads of one complex element (128
+// bytes per cycle over 32 four-byte banks, measured on gfx950 with the
+// SQ_LDS_BANK_CONFLICT counter): 16 for FP32, 8 for FP64.  Lanes of such a
+// group whose patch offsets differ modulo this number never collide on a
+// bank, whatever tap they read.
+template <typename T> constexpr int lds_lane_group() { return 128 / (int)sizeof(cplx<T>); }
+
+// Departure points sit near a lattice of spacing 2 fine cells (the grid nodes
+// at upsampling factor 2), so the patch offsets of the points of a bin share
+// their parity and a plain layout leaves half of the banks idle.  Points on
+// the two colours of a checkerboard over that lattice read their columns in
+// two orders (0 .. w-1, or 1 .. w-1 then 0), which moves half of them to the
+// other parity.  The order depends only on the point's own cell.
+__device__ inline int column_rotation(int it, int ip) { return ((it >> 1) ^ (ip >> 1)) & 1; }
+
 template <typename T, int W, int FG>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(const cplx<T> *__restrict__ grid,
                                                            const PointRec<T> *__restrict__ rec,
                                                            const int32_t *__restrict__ perm,
                                                            const int32_t *__restrict__ binstart,
+                                                           const int32_t *__restrict__ binlist,
                                                            void *__restrict__ out, GatherParams gp)
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *tiles = reinterpret_cast<cplx<T> *>(smem_raw);
-    // Plain order: consecutive bins go to different XCDs, which spreads the
-    // non-empty bins (points cover only half of the doubled torus) evenly.
-    const int bin = (int)blockIdx.x;
+    // Workgroups are dealt to the 8 XCDs round-robin.  XCD x (= blockIdx & 7)
+    // takes the x-th eighth of the non-empty bins in bin order, so that the
+    // bins running together on one XCD are neighbours and the halo rows and
+    // columns their patches share come from that XCD's L2 (about 30% less
+    // HBM traffic than plain bin order).  Only non-empty bins are dealt (the
+    // points cover about half of the doubled torus), so the XCDs get equal
+    // shares.  The grid has 8 * ceil(nbins / 8) workgroups.
+    const int n_ne = binlist[gp.nbins];
+    const int per = (n_ne + 7) >> 3;
+    const int k = (int)(blockIdx.x >> 3);
+    const int item = (int)(blockIdx.x & 7) * per + k;
+    if (k >= per || item >= n_ne) return;
+    const int bin = binlist[item];
     const int start = binstart[bin];
     const int cnt = binstart[bin + 1] - start;
     if (cnt == 0) return;
@@ -55,8 +93,12 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const cplx<T> *__rest
     const int TR = gp.tile_t + W - 1, TC = gp.tile_p + W - 1;
     const int tile_elems = TR * TC;
     const T inv_hw = (T)2 / (T)W;
-    const T beta = (T)gp.beta;
+    const T kc = es_constant<T>(gp.beta);
     constexpr int H = W / 2;
+    constexpr int RU = sizeof(T) == 8 ? 2 : 1;
+    constexpr int NK = lds_lane_group<T>();
+    __shared__ int bucket[NK];  // per bank key: count, then start
+    __shared__ short slot[kGatherThreads];  // lane -> point of the chunk (-1: none)
     const int64_t field_stride = (int64_t)gp.nft * gp.nfp;
 
     // FG fields per pass; the last pass may hold fewer (fg)
@@ -91,26 +133,71 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const cplx<T> *__rest
             }
         }
         __syncthreads();
-        for (int base = 0; base < cnt; base += blockDim.x) {
-            const int r = base + (int)threadIdx.x;
-            if (r >= cnt) continue;
+        for (int base = 0; base < cnt; base += kGatherThreads) {
+            // Deal this chunk's points to lanes: counting-sort them by bank
+            // key (patch offset of the first tap plus the column rotation,
+            // modulo NK), then give sorted position k to lane
+            // (k mod R) * NK + k / R.  Points R apart in key order share a
+            // lane group, so a group holds distinct keys unless one key has
+            // more than R points.  The order inside a key (atomic ranks) does
+            // not matter: a point's sum does not depend on its lane.
+            const int n = min(kGatherThreads, cnt - base);
+            const int R = (n + NK - 1) / NK;
+            const int t = (int)threadIdx.x;
+            if (t < NK) bucket[t] = 0;
+            slot[t] = -1;
+            __syncthreads();
+            int key = 0, rank = 0;
+            if (t < n) {
+                const PointRec<T> q = rec[start + base + t];
+                const bool qbad = !(q.vt == q.vt) || !(q.vp == q.vp);
+                key = qbad ? 0 : ((q.it - r0) * TC + (q.ip - c0) + column_rotation(q.it, q.ip)) & (NK - 1);
+                rank = atomicAdd(&bucket[key], 1);
+            }
+            __syncthreads();
+            if (t < NK) {
+                // exclusive scan of the NK bucket counts within wave 0
+                const int c = bucket[t];
+                int incl = c;
+#pragma unroll
+                for (int d = 1; d < NK; d <<= 1) {
+                    const int y = __shfl_up(incl, d, 64);
+                    if (t >= d) incl += y;
+                }
+                bucket[t] = incl - c;
+            }
+            __syncthreads();
+            if (t < n) {
+                const int k = bucket[key] + rank;
+                slot[(k % R) * NK + k / R] = (short)t;
+            }
+            __syncthreads();
+            const int mine = slot[t];
+            if (mine < 0) continue;
+            const int r = base + mine;
             const PointRec<T> pr = rec[start + r];
             const int dst = perm[start + r];
             const bool bad = !(pr.vt == pr.vt) || !(pr.vp == pr.vp);
             const int lr = bad ? 0 : pr.it - r0;
             const int lc = bad ? 0 : pr.ip - c0;
+            // step b reads column (b + rot) mod w; wp[b] is that column's weight
+            const int rot = bad ? 0 : column_rotation(pr.it, pr.ip);
+            const int last = rot ? 0 : W - 1;  // column of the final step
             T wp[W];
 #pragma unroll
-            for (int b = 0; b < W; ++b) wp[b] = es_kernel<T>(((T)(b - H) - pr.vp) * inv_hw, beta);
+            for (int b = 0; b < W - 1; ++b) wp[b] = es_kernel<T>(((T)(b + rot - H) - pr.vp) * inv_hw, kc);
+            wp[W - 1] = es_kernel<T>(((T)(last - H) - pr.vp) * inv_hw, kc);
             T ax[FG], ay[FG];
 #pragma unroll
             for (int f = 0; f < FG; ++f) ax[f] = ay[f] = (T)0;
-            // rows stay a loop: unrolling it lets the compiler hoist all w*w*FG
-            // LDS loads and run out of registers
-#pragma unroll 1
+            // rows stay a loop (two per iteration in FP64): unrolling it fully
+            // lets the compiler hoist all w*w*FG LDS loads and run out of
+            // registers
+#pragma unroll RU
             for (int a = 0; a < W; ++a) {
-                const T wt = es_kernel<T>(((T)(a - H) - pr.vt) * inv_hw, beta);
+                const T wt = es_kernel<T>(((T)(a - H) - pr.vt) * inv_hw, kc);
                 const cplx<T> *row = tiles + (lr + a) * TC + lc;
+                const cplx<T> *rrow = row + rot;
                 T rx[FG], ry[FG];
 #pragma unroll
                 for (int f = 0; f < FG; ++f) rx[f] = ry[f] = (T)0;
@@ -119,7 +206,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const cplx<T> *__rest
 #pragma unroll
                     for (int f = 0; f < FG; ++f) {
                         // fields past fg read stale LDS; their sums are never stored
-                        const cplx<T> v = row[f * tile_elems + b];
+                        const cplx<T> v = b < W - 1 ? rrow[f * tile_elems + b] : row[f * tile_elems + last];
                         rx[f] += wp[b] * v.x;
                         ry[f] += wp[b] * v.y;
                     }
@@ -145,36 +232,37 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const cplx<T> *__rest
 
 template <typename T, int W, int FG>
 static hipError_t launch_wf(const GatherParams &gp, const void *grid, const void *rec,
-                            const int32_t *perm, const int32_t *binstart, void *out, hipStream_t s)
+                            const int32_t *perm, const int32_t *binstart, const int32_t *binlist,
+                            void *out, hipStream_t s)
 {
     const size_t lds = sizeof(cplx<T>) * (size_t)(gp.tile_t + W - 1) * (gp.tile_p + W - 1) * FG;
     auto kern = k_gather<T, W, FG>;
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, dim3((unsigned)gp.nbins), dim3(kGatherThreads), lds, s,
-                       (const cplx<T> *)grid, (const PointRec<T> *)rec, perm, binstart, out, gp);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(8 * ((gp.nbins + 7) / 8))), dim3(kGatherThreads), lds, s,
+                       (const cplx<T> *)grid, (const PointRec<T> *)rec, perm, binstart, binlist, out, gp);
     return hipGetLastError();
 }
 
 template <typename T, int W>
 static hipError_t launch_w(const GatherParams &gp, const void *grid, const void *rec, const int32_t *perm,
-                           const int32_t *binstart, void *out, hipStream_t s)
+                           const int32_t *binstart, const int32_t *binlist, void *out, hipStream_t s)
 {
     switch (gp.fields_per_pass) {
-    case 1: return launch_wf<T, W, 1>(gp, grid, rec, perm, binstart, out, s);
-    case 2: return launch_wf<T, W, 2>(gp, grid, rec, perm, binstart, out, s);
-    case 3: return launch_wf<T, W, 3>(gp, grid, rec, perm, binstart, out, s);
-    case 4: return launch_wf<T, W, 4>(gp, grid, rec, perm, binstart, out, s);
+    case 1: return launch_wf<T, W, 1>(gp, grid, rec, perm, binstart, binlist, out, s);
+    case 2: return launch_wf<T, W, 2>(gp, grid, rec, perm, binstart, binlist, out, s);
+    case 3: return launch_wf<T, W, 3>(gp, grid, rec, perm, binstart, binlist, out, s);
+    case 4: return launch_wf<T, W, 4>(gp, grid, rec, perm, binstart, binlist, out, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
 static hipError_t launch_t(const GatherParams &gp, const void *grid, const void *rec, const int32_t *perm,
-                           const int32_t *binstart, void *out, hipStream_t s)
+                           const int32_t *binstart, const int32_t *binlist, void *out, hipStream_t s)
 {
     switch (gp.w) {
-#define NUFFT2_W(X) case X: return launch_w<T, X>(gp, grid, rec, perm, binstart, out, s);
+#define NUFFT2_W(X) case X: return launch_w<T, X>(gp, grid, rec, perm, binstart, binlist, out, s);
         NUFFT2_W(2) NUFFT2_W(3) NUFFT2_W(4) NUFFT2_W(5) NUFFT2_W(6) NUFFT2_W(7) NUFFT2_W(8)
         NUFFT2_W(9) NUFFT2_W(10) NUFFT2_W(11) NUFFT2_W(12) NUFFT2_W(13) NUFFT2_W(14)
         NUFFT2_W(15) NUFFT2_W(16)
@@ -184,11 +272,12 @@ static hipError_t launch_t(const GatherParams &gp, const void *grid, const void 
 }
 
 hipError_t launch_gather(int prec, const GatherParams &gp, const void *grid, const void *rec,
-                         const int32_t *perm, const int32_t *binstart, void *out, hipStream_t s)
+                         const int32_t *perm, const int32_t *binstart, const int32_t *binlist,
+                         void *out, hipStream_t s)
 {
     if (gp.n_pts == 0) return hipSuccess;
-    if (prec == 1) return launch_t<float>(gp, grid, rec, perm, binstart, out, s);
-    return launch_t<double>(gp, grid, rec, perm, binstart, out, s);
+    if (prec == 1) return launch_t<float>(gp, grid, rec, perm, binstart, binlist, out, s);
+    return launch_t<double>(gp, grid, rec, perm, binstart, binlist, out, s);
 }
 
 }  // namespace nufft2

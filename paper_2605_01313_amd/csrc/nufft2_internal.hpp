@@ -34,7 +34,8 @@ struct SetptsParams {
 
 // ---- launchers (each returns the hipError_t of its launch) ----
 hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, const double *theta,
-                         int32_t *bincount, int32_t *binstart, int64_t nbins, int2 *keyrank,
+                         int32_t *bincount, int32_t *binstart, int32_t *binlist, int64_t nbins,
+                         int2 *keyrank,
                          uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
                          int32_t *flags, hipStream_t s);
 
@@ -70,7 +71,9 @@ struct GatherParams {
 };
 
 // binstart has nbins + 1 entries; bin b holds records binstart[b] .. binstart[b+1]-1.
+// binlist holds the non-empty bins in increasing order, their number in entry nbins.
 hipError_t launch_gather(int prec, const GatherParams &gp, const void *grid, const void *rec,
-                         const int32_t *perm, const int32_t *binstart, void *out, hipStream_t s);
+                         const int32_t *perm, const int32_t *binstart, const int32_t *binlist,
+                         void *out, hipStream_t s);
 
 }  // namespace nufft2

@@ -53,6 +53,7 @@ struct nufft2_plan_s {
     void *twist_t = nullptr;                // [2][Kt]: corr_t[a], corr_t[a] e^{2 pi i n / nft}
     void *S = nullptr, *grid = nullptr;
     int32_t *bincount = nullptr, *binstart = nullptr;
+    int32_t *binlist = nullptr;  // non-empty bins in order, their number last
     uint8_t *rowmark = nullptr, *rowtouched = nullptr;
     int32_t *flags = nullptr;
     // point workspaces (grown by setpts)
@@ -187,12 +188,12 @@ template <typename T> void fill_twiddle_tables(std::vector<T> &buf, int N)
 void free_all(nufft2_plan_s *p)
 {
     void *ptrs[] = {p->corr_t, p->corr_p, p->tw_t,  p->tw_p,  p->twist_t,   p->S,     p->grid,
-                    p->bincount, p->binstart, p->rowmark, p->rowtouched, p->flags, p->keyrank,
+                    p->bincount, p->binstart, p->binlist, p->rowmark, p->rowtouched, p->flags, p->keyrank,
                     p->rec,    p->perm};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     p->corr_t = p->corr_p = p->tw_t = p->tw_p = p->twist_t = p->S = p->grid = nullptr;
-    p->bincount = p->binstart = p->flags = p->perm = nullptr;
+    p->bincount = p->binstart = p->binlist = p->flags = p->perm = nullptr;
     p->rowmark = p->rowtouched = nullptr;
     p->keyrank = nullptr;
     p->rec = nullptr;
@@ -456,6 +457,7 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
               dev_alloc(p, &p->grid, cs * (size_t)p->F * p->nft * p->nfp) &&
               dev_alloc(p, (void **)&p->bincount, sizeof(int32_t) * (size_t)p->nbins) &&
               dev_alloc(p, (void **)&p->binstart, sizeof(int32_t) * (size_t)(p->nbins + 1)) &&
+              dev_alloc(p, (void **)&p->binlist, sizeof(int32_t) * (size_t)(p->nbins + 1)) &&
               dev_alloc(p, (void **)&p->rowmark, (size_t)p->nft) &&
               dev_alloc(p, (void **)&p->rowtouched, (size_t)p->nft) &&
               dev_alloc(p, (void **)&p->flags, sizeof(int32_t) * 4);
@@ -473,6 +475,7 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
             (e = hipMemset(p->rowmark, 0, (size_t)p->nft)) != hipSuccess ||
             (e = hipMemset(p->bincount, 0, sizeof(int32_t) * (size_t)p->nbins)) != hipSuccess ||
             (e = hipMemset(p->binstart, 0, sizeof(int32_t) * (size_t)(p->nbins + 1))) != hipSuccess ||
+            (e = hipMemset(p->binlist, 0, sizeof(int32_t) * (size_t)(p->nbins + 1))) != hipSuccess ||
             (e = hipMemset(p->flags, 0, sizeof(int32_t) * 4)) != hipSuccess ||
             (e = hipDeviceSynchronize()) != hipSuccess)
             st = NUFFT2_ERR_HIP;
@@ -533,7 +536,7 @@ NUFFT2_API nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const dou
     sp.nbins_phi = p->nbins_p;
     sp.n = n_pts;
     const int slot = prof_begin(p, 0);
-    hipError_t e = launch_setpts(p->prec, sp, phi_dev, theta_dev, p->bincount, p->binstart, p->nbins,
+    hipError_t e = launch_setpts(p->prec, sp, phi_dev, theta_dev, p->bincount, p->binstart, p->binlist, p->nbins,
                                  p->keyrank, p->rowmark, p->rowtouched, p->rec, p->perm, p->flags,
                                  p->stream);
     prof_end(p, slot);
@@ -571,7 +574,8 @@ NUFFT2_API nufft2_status nufft2_exec(nufft2_handle p, const void *coeffs_dev, vo
     gp.n_pts = p->n_pts;
     gp.real_output = p->real_output;
     slot = prof_begin(p, 3);
-    e = launch_gather(p->prec, gp, p->grid, p->rec, p->perm, p->binstart, out_dev, p->stream);
+    e = launch_gather(p->prec, gp, p->grid, p->rec, p->perm, p->binstart, p->binlist, out_dev,
+                      p->stream);
     prof_end(p, slot);
     if (e != hipSuccess) return fail_hip(p, e);
     return NUFFT2_OK;
@@ -667,7 +671,7 @@ NUFFT2_API nufft2_status nufft2_debug_buffer(nufft2_handle p, int32_t which, voi
                                              uint64_t *bytes)
 {
     if (!p || !dev_ptr || !bytes) return NUFFT2_ERR_ARG;
-    const bool needs_pts = which == 1 || which == 2 || which == 3 || which == 4;
+    const bool needs_pts = (which >= 1 && which <= 4) || which == 6;
     if (needs_pts && p->n_pts < 0) return NUFFT2_ERR_NO_POINTS;
     const size_t recsz = p->prec == NUFFT2_FP32 ? sizeof(PointRec<float>) : sizeof(PointRec<double>);
     switch (which) {
@@ -677,6 +681,7 @@ NUFFT2_API nufft2_status nufft2_debug_buffer(nufft2_handle p, int32_t which, voi
     case 3: *dev_ptr = p->binstart; *bytes = sizeof(int32_t) * (size_t)(p->nbins + 1); break;
     case 4: *dev_ptr = p->rowtouched; *bytes = (size_t)p->nft; break;
     case 5: *dev_ptr = p->S; *bytes = p->csize * (size_t)p->F * p->nft * p->Kp; break;
+    case 6: *dev_ptr = p->binlist; *bytes = sizeof(int32_t) * (size_t)(p->nbins + 1); break;
     default: return NUFFT2_ERR_ARG;
     }
     return NUFFT2_OK;

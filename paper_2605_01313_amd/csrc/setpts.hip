@@ -7,8 +7,9 @@
 //                      (one atomic per bin and wave), mark the first-tap
 //                      theta row
 //   k_bin_scan         one workgroup: exclusive scan of the bin counts, the
-//                      set of theta rows any point's taps reach; clears the
-//                      counters and marks for the next call
+//                      list of non-empty bins, the set of theta rows any
+//                      point's taps reach; clears the counters and marks for
+//                      the next call
 //   k_setpts_scatter   per point: recompute the split, write the packed
 //                      record at binstart[bin] + rank, and the permutation
 //
@@ -94,41 +95,60 @@ __global__ __launch_bounds__(256) void k_setpts_bin(const double *__restrict__ p
     keyrank[j] = make_int2(bin, rank);
 }
 
-// Block-wide exclusive scan of one int per thread (blockDim.x a multiple of 64).
-__device__ inline int block_exclusive_scan(int x, int *lds, int &total)
+// Block-wide exclusive scans of two ints per thread at once (one set of
+// barriers for both; blockDim.x a multiple of 64, at most 32 waves).
+// Returns the exclusive prefixes in x, y and the block totals in tx, ty.
+__device__ inline void block_exclusive_scan2(int &x, int &y, int (*lds)[33], int &tx, int &ty)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
-    int incl = x;
+    int ix = x, iy = y;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += y;
+        const int ux = __shfl_up(ix, d, 64), uy = __shfl_up(iy, d, 64);
+        if (lane >= d) {
+            ix += ux;
+            iy += uy;
+        }
     }
-    if (lane == 63) lds[wid] = incl;
+    if (lane == 63) {
+        lds[0][wid] = ix;
+        lds[1][wid] = iy;
+    }
     __syncthreads();
     if (wid == 0) {
-        const int wv = lane < nwaves ? lds[lane] : 0;
-        int wi = wv;
+        const int vx = lane < nwaves ? lds[0][lane] : 0, vy = lane < nwaves ? lds[1][lane] : 0;
+        int wx = vx, wy = vy;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(wi, d, 64);
-            if (lane >= d) wi += y;
+            const int ux = __shfl_up(wx, d, 64), uy = __shfl_up(wy, d, 64);
+            if (lane >= d) {
+                wx += ux;
+                wy += uy;
+            }
         }
-        if (lane < nwaves) lds[lane] = wi - wv;
-        if (lane == nwaves - 1) lds[32] = wi;
+        if (lane < nwaves) {
+            lds[0][lane] = wx - vx;
+            lds[1][lane] = wy - vy;
+        }
+        if (lane == nwaves - 1) {
+            lds[0][32] = wx;
+            lds[1][32] = wy;
+        }
     }
     __syncthreads();
-    const int res = incl - x + lds[wid];
-    total = lds[32];
+    x = ix - x + lds[0][wid];
+    y = iy - y + lds[1][wid];
+    tx = lds[0][32];
+    ty = lds[1][32];
     __syncthreads();
-    return res;
 }
 
 // One workgroup of 1024 threads.  Each pass stages CHUNK * 1024 bin counts
 // in LDS with coalesced loads, every thread scans CHUNK consecutive counts,
 // and the starts go back out through LDS with coalesced stores.  binstart
-// gets nbins + 1 entries (the last is the number of points).  The kernel
+// gets nbins + 1 entries (the last is the number of points); binlist gets the
+// non-empty bins in increasing order and their number in entry nbins.  The kernel
 // also leaves the counters, the row marks and the non-finite accumulator
 // cleared for the next setpts, and publishes the non-finite flag in flags[1].
 constexpr int kScanThreads = 1024;
@@ -139,16 +159,17 @@ __device__ constexpr int scan_slot(int e) { return e + e / kScanChunk; }
 
 __global__ __launch_bounds__(kScanThreads) void k_bin_scan(int32_t *__restrict__ bincount,
                                                            int32_t *__restrict__ binstart,
+                                                           int32_t *__restrict__ binlist,
                                                            int64_t nbins,
                                                            uint8_t *__restrict__ rowmark,
                                                            uint8_t *__restrict__ rowtouched,
                                                            int nft, int w,
                                                            int32_t *__restrict__ flags)
 {
-    __shared__ int lds[33];
+    __shared__ int lds[2][33];
     __shared__ int stage[kScanChunk * kScanThreads + kScanThreads];
     constexpr int PASS = kScanChunk * kScanThreads;
-    int carry = 0;
+    int carry = 0, carry_ne = 0;
     for (int64_t base = 0; base < nbins; base += PASS) {
         const int n = (int)((nbins - base) < PASS ? (nbins - base) : PASS);
         for (int e = threadIdx.x; e < PASS; e += kScanThreads) {
@@ -167,20 +188,30 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_scan(int32_t *__restrict__
             vals[c] = stage[scan_slot(threadIdx.x * kScanChunk + c)];
             sum += vals[c];
         }
-        int total;
-        int run = carry + block_exclusive_scan(sum, lds, total);
+        int ne = 0;
+#pragma unroll
+        for (int c = 0; c < kScanChunk; ++c) ne += vals[c] > 0 ? 1 : 0;
+        int total, ne_total;
+        int run = sum, pos = ne;
+        block_exclusive_scan2(run, pos, lds, total, ne_total);
+        run += carry;
+        pos += carry_ne;
+        const int first = (int)base + (int)threadIdx.x * kScanChunk;
 #pragma unroll
         for (int c = 0; c < kScanChunk; ++c) {
             stage[scan_slot(threadIdx.x * kScanChunk + c)] = run;
             run += vals[c];
+            if (vals[c] > 0) binlist[pos++] = first + c;
         }
         __syncthreads();
         for (int e = threadIdx.x; e < n; e += kScanThreads) binstart[base + e] = stage[scan_slot(e)];
         __syncthreads();
         carry += total;
+        carry_ne += ne_total;
     }
     if (threadIdx.x == 0) {
         binstart[nbins] = carry;
+        binlist[nbins] = carry_ne;
         flags[1] = flags[0];
         flags[0] = 0;
     }
@@ -231,7 +262,8 @@ __global__ __launch_bounds__(256) void k_setpts_scatter(const double *__restrict
 }
 
 hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, const double *theta,
-                         int32_t *bincount, int32_t *binstart, int64_t nbins, int2 *keyrank,
+                         int32_t *bincount, int32_t *binstart, int32_t *binlist, int64_t nbins,
+                         int2 *keyrank,
                          uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
                          int32_t *flags, hipStream_t s)
 {
@@ -249,8 +281,8 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
                                theta, sp, bincount, keyrank, rowmark, flags);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kScanThreads), 0, s, bincount, binstart, nbins, rowmark,
-                       rowtouched, sp.th.nf, sp.w, flags);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kScanThreads), 0, s, bincount, binstart, binlist, nbins,
+                       rowmark, rowtouched, sp.th.nf, sp.w, flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (sp.n > 0) {
         if (prec == 1)

@@ -115,6 +115,16 @@ def test_setpts_records_and_sort(torch_dev):
     for a in range(w):
         want[(it + a) % nft] = 1
     assert np.array_equal(touched, want)
+    check_binlist(plan, torch, starts_all)
+
+
+def check_binlist(plan, torch, starts_all):
+    """The compacted list of non-empty bins equals the bins with a record."""
+    nb = starts_all.size - 1
+    binlist = plan.debug_tensor(6, torch.int32, (nb + 1,)).cpu().numpy()
+    nonempty = np.flatnonzero(np.diff(starts_all) > 0)
+    assert binlist[nb] == nonempty.size
+    assert np.array_equal(binlist[:nonempty.size], nonempty)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -220,7 +230,12 @@ def test_largest_grid(torch_dev, oracle_mod, prec, eps, tol):
     theta = rng.uniform(-0.2, np.pi + 0.2, 600)
     say(f"case largest_grid prec={prec}")
     plan, got = run_plan(torch_dev, prec, coeffs, phi, theta, eps)
-    assert plan.info()["nf_theta"] == 4096 and plan.check() == 0
+    info = plan.info()
+    assert info["nf_theta"] == 4096 and plan.check() == 0
+    torch = torch_dev[0]
+    # more bins than one pass of the scan workgroup
+    assert info["n_bins"] > 8192
+    check_binlist(plan, torch, plan.debug_tensor(3, torch.int32, (info["n_bins"] + 1,)).cpu().numpy())
     errs = field_errors(got, oracle_mod.dfs_eval(coeffs, phi, theta))
     say(f"  rel l2 {errs}")
     assert max(errs) <= tol
