@@ -154,6 +154,53 @@ nufft2_status nufft2_profile_enable(nufft2_handle p, uint32_t stage_mask);
 nufft2_status nufft2_profile_read(nufft2_handle p, double *total_ms, int64_t *count);
 
 /*
+ * Groups: many plans run as one unit, for ensembles whose members have
+ * uneven grid sizes (section 5's evaluation repeated for every member and
+ * field).  Members whose plans share precision, mode counts, field count,
+ * kernel width and shape, tiles and output kind form a class; a group runs
+ * each setpts kernel once per precision over all members' points, and each
+ * exec stage once per class over all of the class's members, as
+ * segmented launches captured in one HIP graph per call type.  Results are
+ * bit-identical to running every plan on its own.
+ *
+ * nufft2_group_create -- group the n distinct plans (host array of handles).
+ *   All plans must use the same stream and device; the group keeps pointers
+ *   to them, and they must outlive the group.  The group owns a stream of
+ *   its own (ordered after and before the plans' stream with events, so
+ *   calls keep the plans' stream order) and small device tables.
+ *   Errors: ERR_ARG (n < 1, null or repeated plan, mixed streams or
+ *   devices), ERR_ALLOC, ERR_HIP.
+ * nufft2_group_setpts -- nufft2_setpts for every member: n_pts[i] points at
+ *   phi_dev[i], theta_dev[i] (host arrays of n entries).  Same argument
+ *   rules and device-side behaviour as nufft2_setpts.
+ * nufft2_group_exec -- nufft2_exec for every member: coeffs_dev[i],
+ *   out_dev[i] (host arrays of n device pointers, none null, also for
+ *   members with zero points).  Errors: ERR_ARG, ERR_NO_POINTS (a member
+ *   without points set), ERR_HIP.
+ *   A change of any device pointer or point count since the previous call
+ *   of the same kind rewrites the group's tables (it first waits for the
+ *   group's earlier work); a change of the total point count also
+ *   re-captures the setpts graph.
+ * nufft2_group_destroy -- synchronise and free the group (not the plans).
+ * nufft2_group_get_info -- members, classes and the kernels per graph.
+ */
+typedef struct nufft2_group_s *nufft2_group;
+typedef struct {
+    int32_t n_members;
+    int32_t n_classes;          /* exec classes */
+    int32_t setpts_kernels;     /* kernels in the setpts graph */
+    int32_t exec_kernels;       /* kernels in the exec graph */
+    uint64_t table_bytes;       /* device memory of the group's tables */
+} nufft2_group_info;
+
+nufft2_status nufft2_group_create(const nufft2_handle *plans, int32_t n, nufft2_group *out);
+nufft2_status nufft2_group_setpts(nufft2_group g, const int64_t *n_pts, const double *const *phi_dev,
+                                  const double *const *theta_dev);
+nufft2_status nufft2_group_exec(nufft2_group g, const void *const *coeffs_dev, void *const *out_dev);
+nufft2_status nufft2_group_destroy(nufft2_group g);
+nufft2_status nufft2_group_get_info(nufft2_group g, nufft2_group_info *info);
+
+/*
  * Host-only helpers (no device work; usable without a GPU).
  *
  * nufft2_kernel_params -- the width and shape the plan would choose for eps

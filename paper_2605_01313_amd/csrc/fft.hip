@@ -302,15 +302,16 @@ template <typename T> constexpr int theta_max_threads() { return sizeof(T) == 4 
 // row flags of one parity, rounded up to 16 bytes to keep the data aligned
 constexpr int theta_flag_bytes(int L) { return (L + 15) & ~15; }
 
-// One workgroup per (field, batch of B phi modes, output parity).  The work
-// item order puts the two parities of a batch next to each other, so that
-// the XCD-aware mapping runs them on the same XCD and the second read of the
-// coefficient batch hits its L2.
+// One workgroup per (field, batch of B phi modes, output parity); item is
+// the work item of this workgroup.  The work item order puts the two
+// parities of a batch next to each other, so that the XCD-aware mapping runs
+// them on the same XCD and the second read of the coefficient batch hits its
+// L2.
 template <typename T, int LOGL, int E>
-__global__ __launch_bounds__(theta_max_threads<T>()) void k_theta_pass(
-    const cplx<T> *__restrict__ coeffs, const cplx<T> *__restrict__ fac_t,
-    const T *__restrict__ corr_p, const cplx<T> *__restrict__ tws,
-    const uint8_t *__restrict__ touched, cplx<T> *__restrict__ S, FFTParams fp)
+__device__ inline void theta_body(int item, const cplx<T> *__restrict__ coeffs, const cplx<T> *__restrict__ fac_t,
+                                  const T *__restrict__ corr_p, const cplx<T> *__restrict__ tws,
+                                  const uint8_t *__restrict__ touched, cplx<T> *__restrict__ S,
+                                  const FFTParams &fp)
 {
     extern __shared__ unsigned char smem_raw[];
     constexpr int L = 1 << LOGL;
@@ -318,7 +319,6 @@ __global__ __launch_bounds__(theta_max_threads<T>()) void k_theta_pass(
     uint8_t *flags = reinterpret_cast<uint8_t *>(tw + tw_lds_len(L));
     cplx<T> *s = reinterpret_cast<cplx<T> *>(flags + theta_flag_bytes(L));
     const int ntiles = (fp.Kp + fp.theta_batch - 1) / fp.theta_batch;
-    const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int parity = item & 1;
     const int tile = item >> 1;
     const int f = tile / ntiles;
@@ -330,6 +330,29 @@ __global__ __launch_bounds__(theta_max_threads<T>()) void k_theta_pass(
     ThetaStore<T> st{S + (int64_t)f * fp.nft * fp.Kp, flags, fp.Kp, m0, parity};
     ThetaPro<cplx<T>> pro{tw, tws, tw_lds_len(L), flags, touched, L, parity};
     fft_stages<T, LOGL, 0, E, true>(s, fp.log_theta_batch, fp.theta_batch, 1, tw, ld, st, pro);
+}
+
+template <typename T, int LOGL, int E>
+__global__ __launch_bounds__(theta_max_threads<T>()) void k_theta_pass(
+    const cplx<T> *__restrict__ coeffs, const cplx<T> *__restrict__ fac_t,
+    const T *__restrict__ corr_p, const cplx<T> *__restrict__ tws,
+    const uint8_t *__restrict__ touched, cplx<T> *__restrict__ S, FFTParams fp)
+{
+    theta_body<T, LOGL, E>(xcd_remap(blockIdx.x, gridDim.x), coeffs, fac_t, corr_p, tws, touched, S, fp);
+}
+
+// Members of a group class share every shape parameter, so member j owns
+// work items [j * per, (j + 1) * per) of the class grid (per even: the two
+// parities of a batch stay with one member and one XCD).
+template <typename T, int LOGL, int E>
+__global__ __launch_bounds__(theta_max_threads<T>()) void k_theta_group(const ThetaJob *__restrict__ jobs,
+                                                                        int per)
+{
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int j = item / per;
+    const ThetaJob J = jobs[j];
+    theta_body<T, LOGL, E>(item - j * per, (const cplx<T> *)J.coeffs, (const cplx<T> *)J.fac_t,
+                           (const T *)J.corr_p, (const cplx<T> *)J.tws, J.touched, (cplx<T> *)J.S, J.fp);
 }
 
 template <typename T> struct PhiStore {
@@ -354,19 +377,19 @@ template <typename T> struct PhiLoad {
     }
 };
 
-// One workgroup per (field, batch of B reached theta rows).
+// One workgroup per (field, batch of B reached theta rows); blk is the
+// workgroup's index in the stage.
 template <typename T, int LOGN, int E>
-__global__ __launch_bounds__(256) void k_phi_pass(const cplx<T> *__restrict__ S,
-                                                  const cplx<T> *__restrict__ tws,
-                                                  const uint8_t *__restrict__ touched,
-                                                  cplx<T> *__restrict__ grid, FFTParams fp)
+__device__ inline void phi_body(int blk, const cplx<T> *__restrict__ S, const cplx<T> *__restrict__ tws,
+                                const uint8_t *__restrict__ touched, cplx<T> *__restrict__ grid,
+                                const FFTParams &fp)
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
     cplx<T> *s = tw + tw_lds_len(1 << LOGN);
     const int nrb = fp.nft / fp.phi_batch;
-    const int f = blockIdx.x / nrb;
-    const int l0 = (blockIdx.x - f * nrb) * fp.phi_batch;
+    const int f = blk / nrb;
+    const int l0 = (blk - f * nrb) * fp.phi_batch;
     // skip the workgroup when none of its rows is reached by any point
     int any = 0;
     for (int b = 0; b < fp.phi_batch; ++b) any |= touched[l0 + b];
@@ -377,12 +400,33 @@ __global__ __launch_bounds__(256) void k_phi_pass(const cplx<T> *__restrict__ S,
     fft_stages<T, LOGN, 0, E, false>(s, fp.log_phi_batch, 1, lds_seq_len(1 << LOGN), tw, ld, st, pro);
 }
 
+template <typename T, int LOGN, int E>
+__global__ __launch_bounds__(256) void k_phi_pass(const cplx<T> *__restrict__ S,
+                                                  const cplx<T> *__restrict__ tws,
+                                                  const uint8_t *__restrict__ touched,
+                                                  cplx<T> *__restrict__ grid, FFTParams fp)
+{
+    phi_body<T, LOGN, E>((int)blockIdx.x, S, tws, touched, grid, fp);
+}
+
+// Member j of a group class owns workgroups [j * per, (j + 1) * per).
+template <typename T, int LOGN, int E>
+__global__ __launch_bounds__(256) void k_phi_group(const PhiJob *__restrict__ jobs, int per)
+{
+    const int j = (int)blockIdx.x / per;
+    const PhiJob J = jobs[j];
+    phi_body<T, LOGN, E>((int)blockIdx.x - j * per, (const cplx<T> *)J.S, (const cplx<T> *)J.tws, J.touched,
+                         (cplx<T> *)J.grid, J.fp);
+}
+
 constexpr int kElemsPerThread = 16;
 
+// jobs == nullptr: one plan (the pointer arguments); otherwise n_members
+// members of one group class described by jobs (device memory).
 template <typename T, int LOGL>
 static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const void *fac_t,
                                  const void *corr_p, const void *tws_t, const uint8_t *touched,
-                                 void *S, hipStream_t s)
+                                 void *S, const ThetaJob *jobs, int n_members, hipStream_t s)
 {
     const int L = 1 << LOGL;
     const int threads = L * fp.theta_batch / kElemsPerThread;
@@ -390,39 +434,57 @@ static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const 
         return hipErrorInvalidConfiguration;
     const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(L) * fp.theta_batch + tw_lds_len(L)) +
                        theta_flag_bytes(L);
-    auto kern = k_theta_pass<T, LOGL, kElemsPerThread>;
-    if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int ntiles = (fp.Kp + fp.theta_batch - 1) / fp.theta_batch;
-    hipLaunchKernelGGL(kern, dim3(2 * ntiles * fp.n_fields), dim3(threads), lds, s,
-                       (const cplx<T> *)coeffs, (const cplx<T> *)fac_t, (const T *)corr_p,
-                       (const cplx<T> *)tws_t, touched, (cplx<T> *)S, fp);
+    const int per = 2 * ntiles * fp.n_fields;
+    if (jobs) {
+        auto kern = k_theta_group<T, LOGL, kElemsPerThread>;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3(per * n_members), dim3(threads), lds, s, jobs, per);
+    } else {
+        auto kern = k_theta_pass<T, LOGL, kElemsPerThread>;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3(per), dim3(threads), lds, s, (const cplx<T> *)coeffs,
+                           (const cplx<T> *)fac_t, (const T *)corr_p, (const cplx<T> *)tws_t, touched,
+                           (cplx<T> *)S, fp);
+    }
     return hipGetLastError();
 }
 
 template <typename T, int LOGN>
 static hipError_t launch_phi_t(const FFTParams &fp, const void *S, const void *tw_p,
-                               const uint8_t *touched, void *grid, hipStream_t s)
+                               const uint8_t *touched, void *grid, const PhiJob *jobs, int n_members,
+                               hipStream_t s)
 {
     const int N = 1 << LOGN;
     const int threads = N * fp.phi_batch / kElemsPerThread;
     if (threads < 1 || threads > 256) return hipErrorInvalidConfiguration;
     const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * fp.phi_batch + tw_lds_len(N));
-    auto kern = k_phi_pass<T, LOGN, kElemsPerThread>;
-    if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, dim3((fp.nft / fp.phi_batch) * fp.n_fields), dim3(threads), lds, s,
-                       (const cplx<T> *)S, (const cplx<T> *)tw_p, touched, (cplx<T> *)grid, fp);
+    const int per = (fp.nft / fp.phi_batch) * fp.n_fields;
+    if (jobs) {
+        auto kern = k_phi_group<T, LOGN, kElemsPerThread>;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3(per * n_members), dim3(threads), lds, s, jobs, per);
+    } else {
+        auto kern = k_phi_pass<T, LOGN, kElemsPerThread>;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3(per), dim3(threads), lds, s, (const cplx<T> *)S, (const cplx<T> *)tw_p,
+                           touched, (cplx<T> *)grid, fp);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t theta_dispatch(const FFTParams &fp, const void *coeffs, const void *fac_t,
                                  const void *corr_p, const void *tws_t, const uint8_t *touched,
-                                 void *S, hipStream_t s)
+                                 void *S, const ThetaJob *jobs, int n_members, hipStream_t s)
 {
     switch (fp.log_nft - 1) {
-#define NUFFT2_L(X) case X: return launch_theta_t<T, X>(fp, coeffs, fac_t, corr_p, tws_t, touched, S, s);
+#define NUFFT2_L(X)                                                                                        \
+    case X: return launch_theta_t<T, X>(fp, coeffs, fac_t, corr_p, tws_t, touched, S, jobs, n_members, s);
         NUFFT2_L(4) NUFFT2_L(5) NUFFT2_L(6) NUFFT2_L(7) NUFFT2_L(8) NUFFT2_L(9)
         NUFFT2_L(10) NUFFT2_L(11)
 #undef NUFFT2_L
@@ -432,10 +494,11 @@ static hipError_t theta_dispatch(const FFTParams &fp, const void *coeffs, const 
 
 template <typename T>
 static hipError_t phi_dispatch(const FFTParams &fp, const void *S, const void *tw_p,
-                               const uint8_t *touched, void *grid, hipStream_t s)
+                               const uint8_t *touched, void *grid, const PhiJob *jobs, int n_members,
+                               hipStream_t s)
 {
     switch (fp.log_nfp) {
-#define NUFFT2_N(X) case X: return launch_phi_t<T, X>(fp, S, tw_p, touched, grid, s);
+#define NUFFT2_N(X) case X: return launch_phi_t<T, X>(fp, S, tw_p, touched, grid, jobs, n_members, s);
         NUFFT2_N(5) NUFFT2_N(6) NUFFT2_N(7) NUFFT2_N(8) NUFFT2_N(9) NUFFT2_N(10)
         NUFFT2_N(11) NUFFT2_N(12)
 #undef NUFFT2_N
@@ -447,15 +510,29 @@ hipError_t launch_theta_pass(int prec, const FFTParams &fp, const void *coeffs, 
                              const void *corr_p, const void *tws_t, const uint8_t *rowtouched,
                              void *S, hipStream_t s)
 {
-    if (prec == 1) return theta_dispatch<float>(fp, coeffs, fac_t, corr_p, tws_t, rowtouched, S, s);
-    return theta_dispatch<double>(fp, coeffs, fac_t, corr_p, tws_t, rowtouched, S, s);
+    if (prec == 1) return theta_dispatch<float>(fp, coeffs, fac_t, corr_p, tws_t, rowtouched, S, nullptr, 0, s);
+    return theta_dispatch<double>(fp, coeffs, fac_t, corr_p, tws_t, rowtouched, S, nullptr, 0, s);
 }
 
 hipError_t launch_phi_pass(int prec, const FFTParams &fp, const void *S, const void *tw_p,
                            const uint8_t *rowtouched, void *grid, hipStream_t s)
 {
-    if (prec == 1) return phi_dispatch<float>(fp, S, tw_p, rowtouched, grid, s);
-    return phi_dispatch<double>(fp, S, tw_p, rowtouched, grid, s);
+    if (prec == 1) return phi_dispatch<float>(fp, S, tw_p, rowtouched, grid, nullptr, 0, s);
+    return phi_dispatch<double>(fp, S, tw_p, rowtouched, grid, nullptr, 0, s);
+}
+
+hipError_t launch_theta_group(int prec, const FFTParams &fp, const ThetaJob *jobs, int n_members, hipStream_t s)
+{
+    if (n_members < 1 || !jobs) return hipErrorInvalidValue;
+    if (prec == 1) return theta_dispatch<float>(fp, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
+    return theta_dispatch<double>(fp, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
+}
+
+hipError_t launch_phi_group(int prec, const FFTParams &fp, const PhiJob *jobs, int n_members, hipStream_t s)
+{
+    if (n_members < 1 || !jobs) return hipErrorInvalidValue;
+    if (prec == 1) return phi_dispatch<float>(fp, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
+    return phi_dispatch<double>(fp, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
 }
 
 }  // namespace nufft2

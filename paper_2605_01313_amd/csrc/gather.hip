@@ -62,17 +62,16 @@ template <typename T> constexpr int lds_lane_group() { return 128 / (int)sizeof(
 // other parity.  The order depends only on the point's own cell.
 __device__ inline int column_rotation(int it, int ip) { return ((it >> 1) ^ (ip >> 1)) & 1; }
 
+// blk: this workgroup's index in the stage (8 * ceil(nbins / 8) of them).
 template <typename T, int W, int FG>
-__global__ __launch_bounds__(kGatherThreads) void k_gather(const cplx<T> *__restrict__ grid,
-                                                           const PointRec<T> *__restrict__ rec,
-                                                           const int32_t *__restrict__ perm,
-                                                           const int32_t *__restrict__ binstart,
-                                                           const int32_t *__restrict__ binlist,
-                                                           void *__restrict__ out, GatherParams gp)
+__device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, const PointRec<T> *__restrict__ rec,
+                                   const int32_t *__restrict__ perm, const int32_t *__restrict__ binstart,
+                                   const int32_t *__restrict__ binlist, void *__restrict__ out,
+                                   const GatherParams &gp)
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *tiles = reinterpret_cast<cplx<T> *>(smem_raw);
-    // Workgroups are dealt to the 8 XCDs round-robin.  XCD x (= blockIdx & 7)
+    // Workgroups are dealt to the 8 XCDs round-robin.  XCD x (= blk & 7)
     // takes the x-th eighth of the non-empty bins in bin order, so that the
     // bins running together on one XCD are neighbours and the halo rows and
     // columns their patches share come from that XCD's L2 (about 30% less
@@ -81,8 +80,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const cplx<T> *__rest
     // shares.  The grid has 8 * ceil(nbins / 8) workgroups.
     const int n_ne = binlist[gp.nbins];
     const int per = (n_ne + 7) >> 3;
-    const int k = (int)(blockIdx.x >> 3);
-    const int item = (int)(blockIdx.x & 7) * per + k;
+    const int k = blk >> 3;
+    const int item = (blk & 7) * per + k;
     if (k >= per || item >= n_ne) return;
     const int bin = binlist[item];
     const int start = binstart[bin];
@@ -231,38 +230,72 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const cplx<T> *__rest
 }
 
 template <typename T, int W, int FG>
+__global__ __launch_bounds__(kGatherThreads) void k_gather(const cplx<T> *__restrict__ grid,
+                                                           const PointRec<T> *__restrict__ rec,
+                                                           const int32_t *__restrict__ perm,
+                                                           const int32_t *__restrict__ binstart,
+                                                           const int32_t *__restrict__ binlist,
+                                                           void *__restrict__ out, GatherParams gp)
+{
+    gather_body<T, W, FG>((int)blockIdx.x, grid, rec, perm, binstart, binlist, out, gp);
+}
+
+// Member j of a group class owns workgroups [j * per, (j + 1) * per); per is
+// a multiple of 8, so a workgroup's XCD is the same as in a launch of its own.
+template <typename T, int W, int FG>
+__global__ __launch_bounds__(kGatherThreads) void k_gather_group(const GatherJob *__restrict__ jobs, int per)
+{
+    const int j = (int)blockIdx.x / per;
+    const GatherJob J = jobs[j];
+    gather_body<T, W, FG>((int)blockIdx.x - j * per, (const cplx<T> *)J.grid, (const PointRec<T> *)J.rec,
+                          J.perm, J.binstart, J.binlist, J.out, J.gp);
+}
+
+// jobs == nullptr: one plan (the pointer arguments); otherwise n_members
+// members of one group class described by jobs (device memory).
+template <typename T, int W, int FG>
 static hipError_t launch_wf(const GatherParams &gp, const void *grid, const void *rec,
                             const int32_t *perm, const int32_t *binstart, const int32_t *binlist,
-                            void *out, hipStream_t s)
+                            void *out, const GatherJob *jobs, int n_members, hipStream_t s)
 {
     const size_t lds = sizeof(cplx<T>) * (size_t)(gp.tile_t + W - 1) * (gp.tile_p + W - 1) * FG;
-    auto kern = k_gather<T, W, FG>;
-    if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, dim3((unsigned)(8 * ((gp.nbins + 7) / 8))), dim3(kGatherThreads), lds, s,
-                       (const cplx<T> *)grid, (const PointRec<T> *)rec, perm, binstart, binlist, out, gp);
+    const int per = (int)(8 * ((gp.nbins + 7) / 8));
+    if (jobs) {
+        auto kern = k_gather_group<T, W, FG>;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3((unsigned)(per * n_members)), dim3(kGatherThreads), lds, s, jobs, per);
+    } else {
+        auto kern = k_gather<T, W, FG>;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3((unsigned)per), dim3(kGatherThreads), lds, s, (const cplx<T> *)grid,
+                           (const PointRec<T> *)rec, perm, binstart, binlist, out, gp);
+    }
     return hipGetLastError();
 }
 
 template <typename T, int W>
 static hipError_t launch_w(const GatherParams &gp, const void *grid, const void *rec, const int32_t *perm,
-                           const int32_t *binstart, const int32_t *binlist, void *out, hipStream_t s)
+                           const int32_t *binstart, const int32_t *binlist, void *out, const GatherJob *jobs,
+                           int n_members, hipStream_t s)
 {
     switch (gp.fields_per_pass) {
-    case 1: return launch_wf<T, W, 1>(gp, grid, rec, perm, binstart, binlist, out, s);
-    case 2: return launch_wf<T, W, 2>(gp, grid, rec, perm, binstart, binlist, out, s);
-    case 3: return launch_wf<T, W, 3>(gp, grid, rec, perm, binstart, binlist, out, s);
-    case 4: return launch_wf<T, W, 4>(gp, grid, rec, perm, binstart, binlist, out, s);
+    case 1: return launch_wf<T, W, 1>(gp, grid, rec, perm, binstart, binlist, out, jobs, n_members, s);
+    case 2: return launch_wf<T, W, 2>(gp, grid, rec, perm, binstart, binlist, out, jobs, n_members, s);
+    case 3: return launch_wf<T, W, 3>(gp, grid, rec, perm, binstart, binlist, out, jobs, n_members, s);
+    case 4: return launch_wf<T, W, 4>(gp, grid, rec, perm, binstart, binlist, out, jobs, n_members, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
 static hipError_t launch_t(const GatherParams &gp, const void *grid, const void *rec, const int32_t *perm,
-                           const int32_t *binstart, const int32_t *binlist, void *out, hipStream_t s)
+                           const int32_t *binstart, const int32_t *binlist, void *out, const GatherJob *jobs,
+                           int n_members, hipStream_t s)
 {
     switch (gp.w) {
-#define NUFFT2_W(X) case X: return launch_w<T, X>(gp, grid, rec, perm, binstart, binlist, out, s);
+#define NUFFT2_W(X) case X: return launch_w<T, X>(gp, grid, rec, perm, binstart, binlist, out, jobs, n_members, s);
         NUFFT2_W(2) NUFFT2_W(3) NUFFT2_W(4) NUFFT2_W(5) NUFFT2_W(6) NUFFT2_W(7) NUFFT2_W(8)
         NUFFT2_W(9) NUFFT2_W(10) NUFFT2_W(11) NUFFT2_W(12) NUFFT2_W(13) NUFFT2_W(14)
         NUFFT2_W(15) NUFFT2_W(16)
@@ -276,8 +309,16 @@ hipError_t launch_gather(int prec, const GatherParams &gp, const void *grid, con
                          void *out, hipStream_t s)
 {
     if (gp.n_pts == 0) return hipSuccess;
-    if (prec == 1) return launch_t<float>(gp, grid, rec, perm, binstart, binlist, out, s);
-    return launch_t<double>(gp, grid, rec, perm, binstart, binlist, out, s);
+    if (prec == 1) return launch_t<float>(gp, grid, rec, perm, binstart, binlist, out, nullptr, 0, s);
+    return launch_t<double>(gp, grid, rec, perm, binstart, binlist, out, nullptr, 0, s);
+}
+
+hipError_t launch_gather_group(int prec, const GatherParams &gp, const GatherJob *jobs, int n_members,
+                               hipStream_t s)
+{
+    if (n_members < 1 || !jobs) return hipErrorInvalidValue;
+    if (prec == 1) return launch_t<float>(gp, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
+    return launch_t<double>(gp, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
 }
 
 }  // namespace nufft2

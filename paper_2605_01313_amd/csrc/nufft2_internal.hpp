@@ -39,6 +39,25 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
                          uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
                          int32_t *flags, hipStream_t s);
 
+// One member of a group for the setpts kernels (device memory; the
+// pointers as in launch_setpts).  Its n_pts points are point blocks
+// block_begin .. block_begin + ceil(n_pts / 256) - 1 of the group launch.
+struct SetptsJob {
+    const double *phi, *theta;
+    SetptsParams sp;
+    int32_t *bincount, *binstart, *binlist;
+    int64_t nbins;
+    int2 *keyrank;
+    uint8_t *rowmark, *rowtouched;
+    void *rec;
+    int32_t *perm, *flags;
+    int32_t block_begin, pad;
+};
+// All members of one precision: point kernels over n_blocks blocks
+// (job_of_block: member of each block), the scan one workgroup per member.
+hipError_t launch_setpts_group(int prec, const SetptsJob *jobs, int n_members, const int32_t *job_of_block,
+                               int n_blocks, hipStream_t s);
+
 struct FFTParams {
     int32_t Kt, Kp;       // modes
     int32_t nft, nfp;     // fine grid
@@ -56,6 +75,24 @@ hipError_t launch_theta_pass(int prec, const FFTParams &fp, const void *coeffs, 
                              void *S, hipStream_t s);
 hipError_t launch_phi_pass(int prec, const FFTParams &fp, const void *S, const void *tws_p,
                            const uint8_t *rowtouched, void *grid, hipStream_t s);
+
+// One member of a group class for the theta / phi passes (device memory;
+// the pointers as in launch_theta_pass / launch_phi_pass).  Members of a
+// class share every FFTParams field.
+struct ThetaJob {
+    const void *coeffs, *fac_t, *corr_p, *tws;
+    const uint8_t *touched;
+    void *S;
+    FFTParams fp;
+};
+struct PhiJob {
+    const void *S, *tws;
+    const uint8_t *touched;
+    void *grid;
+    FFTParams fp;
+};
+hipError_t launch_theta_group(int prec, const FFTParams &fp, const ThetaJob *jobs, int n_members, hipStream_t s);
+hipError_t launch_phi_group(int prec, const FFTParams &fp, const PhiJob *jobs, int n_members, hipStream_t s);
 
 struct GatherParams {
     int32_t nft, nfp;
@@ -75,5 +112,16 @@ struct GatherParams {
 hipError_t launch_gather(int prec, const GatherParams &gp, const void *grid, const void *rec,
                          const int32_t *perm, const int32_t *binstart, const int32_t *binlist,
                          void *out, hipStream_t s);
+
+// One member of a group class for the gather (device memory).  Members of a
+// class share every GatherParams field except n_pts.
+struct GatherJob {
+    const void *grid, *rec;
+    const int32_t *perm, *binstart, *binlist;
+    void *out;
+    GatherParams gp;
+};
+hipError_t launch_gather_group(int prec, const GatherParams &gp, const GatherJob *jobs, int n_members,
+                               hipStream_t s);
 
 }  // namespace nufft2

@@ -11,6 +11,7 @@
 
 #include "nufft2.h"
 #include "nufft2_internal.hpp"
+#include "plan_state.hpp"
 
 #define NUFFT2_API extern "C" __attribute__((visibility("default")))
 
@@ -28,50 +29,6 @@ constexpr size_t kFftLdsLimit = 155648;    // 152 KiB of the 160 KiB per workgro
 constexpr int kGatherMaxFieldsPerPass = 4;
 
 }  // namespace
-
-struct nufft2_plan_s {
-    int prec = 0;
-    int64_t Kt = 0, Kp = 0;
-    int F = 0;
-    int w = 0;
-    double beta = 0;
-    int nft = 0, nfp = 0;
-    int tile_t = 0, tile_p = 0;
-    int nbins_t = 0, nbins_p = 0;
-    int64_t nbins = 0;
-    int real_output = 0;
-    int fields_per_pass = 1;
-    hipStream_t stream = nullptr;
-    int device = 0;
-    size_t csize = 0;  // bytes per complex
-    size_t rsize = 0;  // bytes per real
-    FFTParams fp{};
-
-    // device workspaces
-    void *corr_t = nullptr, *corr_p = nullptr;
-    void *tw_t = nullptr, *tw_p = nullptr;  // two-level twiddle tables
-    void *twist_t = nullptr;                // [2][Kt]: corr_t[a], corr_t[a] e^{2 pi i n / nft}
-    void *S = nullptr, *grid = nullptr;
-    int32_t *bincount = nullptr, *binstart = nullptr;
-    int32_t *binlist = nullptr;  // non-empty bins in order, their number last
-    uint8_t *rowmark = nullptr, *rowtouched = nullptr;
-    int32_t *flags = nullptr;
-    // point workspaces (grown by setpts)
-    int64_t pts_cap = 0;
-    int2 *keyrank = nullptr;
-    void *rec = nullptr;
-    int32_t *perm = nullptr;
-
-    int64_t n_pts = -1;
-    size_t ws_bytes = 0;
-    hipError_t last_err = hipSuccess;
-
-    // stage timing
-    uint32_t prof_mask = 0;
-    struct Bracket { int stage; hipEvent_t a, b; };
-    std::vector<Bracket> prof_pending;
-    std::vector<hipEvent_t> prof_pool;
-};
 
 namespace {
 
@@ -489,41 +446,42 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     return NUFFT2_OK;
 }
 
-NUFFT2_API nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const double *phi_dev,
-                                       const double *theta_dev)
+nufft2_status nufft2::plan_reserve_points(nufft2_plan_s *p, int64_t n_pts)
 {
-    if (!p || n_pts < 0 || n_pts > (int64_t)0x7fffffff) return NUFFT2_ERR_ARG;
-    if (n_pts > 0 && (!phi_dev || !theta_dev)) return NUFFT2_ERR_ARG;
-    if (n_pts > p->pts_cap) {
-        // grow the point workspaces; wait for work that may still use them
-        hipError_t e = hipStreamSynchronize(p->stream);
-        if (e != hipSuccess) return fail_hip(p, e);
-        void *ptrs[] = {p->keyrank, p->rec, p->perm};
-        for (void *q : ptrs)
+    if (n_pts <= p->pts_cap) return NUFFT2_OK;
+    // grow the point workspaces; wait for work that may still use them
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return fail_hip(p, e);
+    void *ptrs[] = {p->keyrank, p->rec, p->perm};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    p->ws_bytes -= (size_t)p->pts_cap * (sizeof(int2) + 2 * p->rsize + 8 + sizeof(int32_t));
+    p->keyrank = nullptr;
+    p->rec = nullptr;
+    p->perm = nullptr;
+    p->pts_cap = 0;
+    p->n_pts = -1;
+    const size_t recsz = p->prec == NUFFT2_FP32 ? sizeof(PointRec<float>) : sizeof(PointRec<double>);
+    const size_t before = p->ws_bytes;
+    if (!dev_alloc(p, (void **)&p->keyrank, sizeof(int2) * (size_t)n_pts) ||
+        !dev_alloc(p, &p->rec, recsz * (size_t)n_pts) ||
+        !dev_alloc(p, (void **)&p->perm, sizeof(int32_t) * (size_t)n_pts)) {
+        void *q2[] = {p->keyrank, p->rec, p->perm};
+        for (void *q : q2)
             if (q) (void)hipFree(q);
-        p->ws_bytes -= (size_t)p->pts_cap * (sizeof(int2) + 2 * p->rsize + 8 + sizeof(int32_t));
         p->keyrank = nullptr;
         p->rec = nullptr;
         p->perm = nullptr;
-        p->pts_cap = 0;
-        p->n_pts = -1;
-        const size_t recsz = p->prec == NUFFT2_FP32 ? sizeof(PointRec<float>) : sizeof(PointRec<double>);
-        const size_t before = p->ws_bytes;
-        if (!dev_alloc(p, (void **)&p->keyrank, sizeof(int2) * (size_t)n_pts) ||
-            !dev_alloc(p, &p->rec, recsz * (size_t)n_pts) ||
-            !dev_alloc(p, (void **)&p->perm, sizeof(int32_t) * (size_t)n_pts)) {
-            void *q2[] = {p->keyrank, p->rec, p->perm};
-            for (void *q : q2)
-                if (q) (void)hipFree(q);
-            p->keyrank = nullptr;
-            p->rec = nullptr;
-            p->perm = nullptr;
-            p->ws_bytes = before;
-            return NUFFT2_ERR_ALLOC;
-        }
-        p->ws_bytes = before + (size_t)n_pts * (sizeof(int2) + 2 * p->rsize + 8 + sizeof(int32_t));
-        p->pts_cap = n_pts;
+        p->ws_bytes = before;
+        return NUFFT2_ERR_ALLOC;
     }
+    p->ws_bytes = before + (size_t)n_pts * (sizeof(int2) + 2 * p->rsize + 8 + sizeof(int32_t));
+    p->pts_cap = n_pts;
+    return NUFFT2_OK;
+}
+
+SetptsParams nufft2::plan_setpts_params(const nufft2_plan_s *p, int64_t n_pts)
+{
     SetptsParams sp{};
     const double inv_two_pi = 0.15915494309189533576888376337251436;
     sp.th.to_grid = (double)p->nft * inv_two_pi;
@@ -535,6 +493,35 @@ NUFFT2_API nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const dou
     sp.w = p->w;
     sp.nbins_phi = p->nbins_p;
     sp.n = n_pts;
+    return sp;
+}
+
+GatherParams nufft2::plan_gather_params(const nufft2_plan_s *p)
+{
+    GatherParams gp{};
+    gp.nft = p->nft;
+    gp.nfp = p->nfp;
+    gp.tile_t = p->tile_t;
+    gp.tile_p = p->tile_p;
+    gp.nbins_phi = p->nbins_p;
+    gp.nbins = p->nbins;
+    gp.w = p->w;
+    gp.beta = p->beta;
+    gp.n_fields = p->F;
+    gp.fields_per_pass = p->fields_per_pass;
+    gp.n_pts = p->n_pts;
+    gp.real_output = p->real_output;
+    return gp;
+}
+
+NUFFT2_API nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const double *phi_dev,
+                                       const double *theta_dev)
+{
+    if (!p || n_pts < 0 || n_pts > (int64_t)0x7fffffff) return NUFFT2_ERR_ARG;
+    if (n_pts > 0 && (!phi_dev || !theta_dev)) return NUFFT2_ERR_ARG;
+    nufft2_status st = plan_reserve_points(p, n_pts);
+    if (st != NUFFT2_OK) return st;
+    const SetptsParams sp = plan_setpts_params(p, n_pts);
     const int slot = prof_begin(p, 0);
     hipError_t e = launch_setpts(p->prec, sp, phi_dev, theta_dev, p->bincount, p->binstart, p->binlist, p->nbins,
                                  p->keyrank, p->rowmark, p->rowtouched, p->rec, p->perm, p->flags,
@@ -560,19 +547,7 @@ NUFFT2_API nufft2_status nufft2_exec(nufft2_handle p, const void *coeffs_dev, vo
     e = launch_phi_pass(p->prec, p->fp, p->S, p->tw_p, p->rowtouched, p->grid, p->stream);
     prof_end(p, slot);
     if (e != hipSuccess) return fail_hip(p, e);
-    GatherParams gp{};
-    gp.nft = p->nft;
-    gp.nfp = p->nfp;
-    gp.tile_t = p->tile_t;
-    gp.tile_p = p->tile_p;
-    gp.nbins_phi = p->nbins_p;
-    gp.nbins = p->nbins;
-    gp.w = p->w;
-    gp.beta = p->beta;
-    gp.n_fields = p->F;
-    gp.fields_per_pass = p->fields_per_pass;
-    gp.n_pts = p->n_pts;
-    gp.real_output = p->real_output;
+    const GatherParams gp = plan_gather_params(p);
     slot = prof_begin(p, 3);
     e = launch_gather(p->prec, gp, p->grid, p->rec, p->perm, p->binstart, p->binlist, out_dev,
                       p->stream);

@@ -68,15 +68,13 @@ __device__ inline int32_t wave_aggregated_rank(int32_t *__restrict__ bincount, i
     return __shfl(base, leader_of_mine, 64) + offset;
 }
 
+// Point j (a thread of a 256-thread block; j >= n: inactive).
 template <typename T>
-__global__ __launch_bounds__(256) void k_setpts_bin(const double *__restrict__ phi,
-                                                    const double *__restrict__ theta, SetptsParams sp,
-                                                    int32_t *__restrict__ bincount,
-                                                    int2 *__restrict__ keyrank,
-                                                    uint8_t *__restrict__ rowmark,
-                                                    int32_t *__restrict__ flags)
+__device__ inline void setpts_bin_point(int64_t j, const double *__restrict__ phi, const double *__restrict__ theta,
+                                        const SetptsParams &sp, int32_t *__restrict__ bincount,
+                                        int2 *__restrict__ keyrank, uint8_t *__restrict__ rowmark,
+                                        int32_t *__restrict__ flags)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= sp.n) return;
     const double ph = phi[j], th = theta[j];
     int32_t bin;
@@ -93,6 +91,29 @@ __global__ __launch_bounds__(256) void k_setpts_bin(const double *__restrict__ p
     }
     const int32_t rank = wave_aggregated_rank(bincount, bin);
     keyrank[j] = make_int2(bin, rank);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_setpts_bin(const double *__restrict__ phi,
+                                                    const double *__restrict__ theta, SetptsParams sp,
+                                                    int32_t *__restrict__ bincount,
+                                                    int2 *__restrict__ keyrank,
+                                                    uint8_t *__restrict__ rowmark,
+                                                    int32_t *__restrict__ flags)
+{
+    setpts_bin_point<T>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, phi, theta, sp, bincount, keyrank,
+                        rowmark, flags);
+}
+
+// Group launches: job_of_block[b] is the member that owns point block b;
+// the member's points start at block jobs[j].block_begin.
+template <typename T>
+__global__ __launch_bounds__(256) void k_setpts_bin_group(const SetptsJob *__restrict__ jobs,
+                                                          const int32_t *__restrict__ job_of_block)
+{
+    const SetptsJob J = jobs[job_of_block[blockIdx.x]];
+    setpts_bin_point<T>((int64_t)((int)blockIdx.x - J.block_begin) * blockDim.x + threadIdx.x, J.phi, J.theta,
+                        J.sp, J.bincount, J.keyrank, J.rowmark, J.flags);
 }
 
 // Block-wide exclusive scans of two ints per thread at once (one set of
@@ -157,14 +178,10 @@ constexpr int kScanChunk = 8;
 // its own LDS banks
 __device__ constexpr int scan_slot(int e) { return e + e / kScanChunk; }
 
-__global__ __launch_bounds__(kScanThreads) void k_bin_scan(int32_t *__restrict__ bincount,
-                                                           int32_t *__restrict__ binstart,
-                                                           int32_t *__restrict__ binlist,
-                                                           int64_t nbins,
-                                                           uint8_t *__restrict__ rowmark,
-                                                           uint8_t *__restrict__ rowtouched,
-                                                           int nft, int w,
-                                                           int32_t *__restrict__ flags)
+__device__ inline void bin_scan_body(int32_t *__restrict__ bincount, int32_t *__restrict__ binstart,
+                                     int32_t *__restrict__ binlist, int64_t nbins, uint8_t *__restrict__ rowmark,
+                                     uint8_t *__restrict__ rowtouched, int nft, int w,
+                                     int32_t *__restrict__ flags)
 {
     __shared__ int lds[2][33];
     __shared__ int stage[kScanChunk * kScanThreads + kScanThreads];
@@ -232,16 +249,32 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_scan(int32_t *__restrict__
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_setpts_scatter(const double *__restrict__ phi,
-                                                        const double *__restrict__ theta,
-                                                        SetptsParams sp,
-                                                        const int2 *__restrict__ keyrank,
-                                                        const int32_t *__restrict__ binstart,
-                                                        PointRec<T> *__restrict__ rec,
-                                                        int32_t *__restrict__ perm)
+__global__ __launch_bounds__(kScanThreads) void k_bin_scan(int32_t *__restrict__ bincount,
+                                                           int32_t *__restrict__ binstart,
+                                                           int32_t *__restrict__ binlist,
+                                                           int64_t nbins,
+                                                           uint8_t *__restrict__ rowmark,
+                                                           uint8_t *__restrict__ rowtouched,
+                                                           int nft, int w,
+                                                           int32_t *__restrict__ flags)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bin_scan_body(bincount, binstart, binlist, nbins, rowmark, rowtouched, nft, w, flags);
+}
+
+// Group launch: one workgroup per member.
+__global__ __launch_bounds__(kScanThreads) void k_bin_scan_group(const SetptsJob *__restrict__ jobs)
+{
+    const SetptsJob J = jobs[blockIdx.x];
+    bin_scan_body(J.bincount, J.binstart, J.binlist, J.nbins, J.rowmark, J.rowtouched, J.sp.th.nf, J.sp.w,
+                  J.flags);
+}
+
+template <typename T>
+__device__ inline void setpts_scatter_point(int64_t j, const double *__restrict__ phi,
+                                            const double *__restrict__ theta, const SetptsParams &sp,
+                                            const int2 *__restrict__ keyrank, const int32_t *__restrict__ binstart,
+                                            PointRec<T> *__restrict__ rec, int32_t *__restrict__ perm)
+{
     if (j < sp.n) {
         const double ph = phi[j], th = theta[j];
         PointRec<T> r;
@@ -259,6 +292,28 @@ __global__ __launch_bounds__(256) void k_setpts_scatter(const double *__restrict
         rec[pos] = r;
         perm[pos] = (int32_t)j;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_setpts_scatter(const double *__restrict__ phi,
+                                                        const double *__restrict__ theta,
+                                                        SetptsParams sp,
+                                                        const int2 *__restrict__ keyrank,
+                                                        const int32_t *__restrict__ binstart,
+                                                        PointRec<T> *__restrict__ rec,
+                                                        int32_t *__restrict__ perm)
+{
+    setpts_scatter_point<T>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, phi, theta, sp, keyrank, binstart, rec,
+                            perm);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_setpts_scatter_group(const SetptsJob *__restrict__ jobs,
+                                                              const int32_t *__restrict__ job_of_block)
+{
+    const SetptsJob J = jobs[job_of_block[blockIdx.x]];
+    setpts_scatter_point<T>((int64_t)((int)blockIdx.x - J.block_begin) * blockDim.x + threadIdx.x, J.phi,
+                            J.theta, J.sp, J.keyrank, J.binstart, (PointRec<T> *)J.rec, J.perm);
 }
 
 hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, const double *theta,
@@ -291,6 +346,30 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
         else
             hipLaunchKernelGGL(k_setpts_scatter<double>, dim3((unsigned)blocks), dim3(threads), 0, s,
                                phi, theta, sp, keyrank, binstart, (PointRec<double> *)rec, perm);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_setpts_group(int prec, const SetptsJob *jobs, int n_members, const int32_t *job_of_block,
+                               int n_blocks, hipStream_t s)
+{
+    if (n_members < 1 || !jobs || (n_blocks > 0 && !job_of_block)) return hipErrorInvalidValue;
+    hipError_t e;
+    if (n_blocks > 0) {
+        if (prec == 1)
+            hipLaunchKernelGGL(k_setpts_bin_group<float>, dim3(n_blocks), dim3(256), 0, s, jobs, job_of_block);
+        else
+            hipLaunchKernelGGL(k_setpts_bin_group<double>, dim3(n_blocks), dim3(256), 0, s, jobs, job_of_block);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_bin_scan_group, dim3(n_members), dim3(kScanThreads), 0, s, jobs);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (n_blocks > 0) {
+        if (prec == 1)
+            hipLaunchKernelGGL(k_setpts_scatter_group<float>, dim3(n_blocks), dim3(256), 0, s, jobs, job_of_block);
+        else
+            hipLaunchKernelGGL(k_setpts_scatter_group<double>, dim3(n_blocks), dim3(256), 0, s, jobs, job_of_block);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

@@ -31,7 +31,8 @@ EXPORTED = (
     "nufft2_plan", "nufft2_setpts", "nufft2_exec", "nufft2_destroy", "nufft2_strerror",
     "nufft2_get_info", "nufft2_check", "nufft2_set_stream", "nufft2_kernel_params",
     "nufft2_kernel_correction", "nufft2_debug_buffer", "nufft2_profile_enable",
-    "nufft2_profile_read",
+    "nufft2_profile_read", "nufft2_group_create", "nufft2_group_setpts", "nufft2_group_exec",
+    "nufft2_group_destroy", "nufft2_group_get_info",
 )
 NUFFT2_N_STAGES = 4
 STAGE_NAMES = ("setpts", "theta_pass", "phi_pass", "gather")
@@ -52,6 +53,15 @@ class nufft2_info(ctypes.Structure):
                 ("n_bins", ctypes.c_int64), ("n_pts", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_uint64), ("last_hip_error", ctypes.c_int32),
                 ("device", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class nufft2_group_info(ctypes.Structure):
+    _fields_ = [("n_members", ctypes.c_int32), ("n_classes", ctypes.c_int32),
+                ("setpts_kernels", ctypes.c_int32), ("exec_kernels", ctypes.c_int32),
+                ("table_bytes", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -78,6 +88,11 @@ def _load():
         "nufft2_debug_buffer": [H, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_uint64)],
         "nufft2_profile_enable": [H, ctypes.c_uint32],
         "nufft2_profile_read": [H, vp, vp],
+        "nufft2_group_create": [vp, i32, ctypes.POINTER(H)],
+        "nufft2_group_setpts": [H, vp, vp, vp],
+        "nufft2_group_exec": [H, vp, vp],
+        "nufft2_group_destroy": [H],
+        "nufft2_group_get_info": [H, ctypes.POINTER(nufft2_group_info)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -178,6 +193,40 @@ def nufft2_profile_read(handle):
     return st, ms, cnt
 
 
+def _ptr_array(values):
+    arr = (ctypes.c_void_p * len(values))()
+    for i, v in enumerate(values):
+        arr[i] = v or None
+    return arr
+
+
+def nufft2_group_create(handles):
+    """Returns (status, group handle) for a list of plan handles."""
+    arr = (ctypes.c_void_p * len(handles))(*[h.value for h in handles])
+    g = ctypes.c_void_p()
+    st = _lib.nufft2_group_create(arr, len(handles), ctypes.byref(g))
+    return st, g
+
+
+def nufft2_group_setpts(group, n_pts, phi_ptrs, theta_ptrs):
+    n = (ctypes.c_int64 * len(n_pts))(*[int(x) for x in n_pts])
+    return _lib.nufft2_group_setpts(group, n, _ptr_array(phi_ptrs), _ptr_array(theta_ptrs))
+
+
+def nufft2_group_exec(group, coeffs_ptrs, out_ptrs):
+    return _lib.nufft2_group_exec(group, _ptr_array(coeffs_ptrs), _ptr_array(out_ptrs))
+
+
+def nufft2_group_destroy(group):
+    return _lib.nufft2_group_destroy(group)
+
+
+def nufft2_group_get_info(group):
+    info = nufft2_group_info()
+    st = _lib.nufft2_group_get_info(group, ctypes.byref(info))
+    return st, info
+
+
 # ---- torch convenience -----------------------------------------------------
 class Plan:
     """A plan bound to torch tensors on the current device and stream.
@@ -275,6 +324,75 @@ class Plan:
     def destroy(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             nufft2_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Group:
+    """Plans run together (nufft2_group_*).
+
+    >>> g = Group([p0, p1, ...])                 # Plan objects on one stream
+    >>> g.setpts([phi0, phi1, ...], [theta0, ...])
+    >>> outs = g.exec([c0, c1, ...])             # list of output tensors
+    """
+
+    def __init__(self, plans):
+        self._torch = plans[0]._torch
+        self.plans = list(plans)
+        st, g = nufft2_group_create([p.handle for p in self.plans])
+        _check(st, "nufft2_group_create")
+        self.handle = g
+        self._keep = None
+
+    def info(self):
+        st, info = nufft2_group_get_info(self.handle)
+        _check(st, "nufft2_group_get_info")
+        return info.as_dict()
+
+    def setpts(self, phis, thetas):
+        t = self._torch
+        if len(phis) != len(self.plans) or len(thetas) != len(self.plans):
+            raise ValueError("one (phi, theta) pair per member")
+        for x in list(phis) + list(thetas):
+            if x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous():
+                raise TypeError("points must be contiguous float64 device tensors")
+        ns = [x.numel() for x in phis]
+        if any(a.numel() != b for a, b in zip(thetas, ns)):
+            raise ValueError("phi and theta differ in length")
+        _check(nufft2_group_setpts(self.handle, ns, [x.data_ptr() if x.numel() else 0 for x in phis],
+                                   [x.data_ptr() if x.numel() else 0 for x in thetas]),
+               "nufft2_group_setpts")
+        for p, n, a, b in zip(self.plans, ns, phis, thetas):
+            p.n_pts = n
+            p._pts = (a, b)
+
+    def exec(self, coeffs, outs=None):
+        t = self._torch
+        if len(coeffs) != len(self.plans):
+            raise ValueError("one coefficient tensor per member")
+        if outs is None:
+            outs = []
+            for p, c in zip(self.plans, coeffs):
+                dt = p.rdtype if p.real_output else p.cdtype
+                outs.append(t.empty((p.shape[0], max(p.n_pts, 1)), dtype=dt, device=c.device))
+        for p, c in zip(self.plans, coeffs):
+            if c.dtype != p.cdtype or not c.is_cuda or not c.is_contiguous():
+                raise TypeError(f"coeffs must be contiguous {p.cdtype} device tensors")
+            if tuple(c.shape) != p.shape and tuple(c.shape) != p.shape[1:]:
+                raise ValueError(f"coeffs shape {tuple(c.shape)} != {p.shape}")
+        _check(nufft2_group_exec(self.handle, [c.data_ptr() for c in coeffs],
+                                 [o.data_ptr() for o in outs]), "nufft2_group_exec")
+        self._keep = (coeffs, outs)
+        return [o[:, :p.n_pts] for o, p in zip(outs, self.plans)]
+
+    def destroy(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            nufft2_group_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
     def __del__(self):

@@ -130,6 +130,13 @@ def test_plan_argument_errors_before_device_work(nf):
     assert nf.nufft2_destroy(null) == nf.NUFFT2_OK
     assert nf.nufft2_get_info(null)[0] == nf.NUFFT2_ERR_ARG
     assert nf.nufft2_strerror(nf.NUFFT2_ERR_NO_POINTS) == "exec before setpts"
+    # groups: empty or null member lists, null group handles
+    assert nf.nufft2_group_create([])[0] == nf.NUFFT2_ERR_ARG
+    assert nf.nufft2_group_create([null])[0] == nf.NUFFT2_ERR_ARG
+    assert nf.nufft2_group_setpts(null, [1], [0], [0]) == nf.NUFFT2_ERR_ARG
+    assert nf.nufft2_group_exec(null, [0], [0]) == nf.NUFFT2_ERR_ARG
+    assert nf.nufft2_group_get_info(null)[0] == nf.NUFFT2_ERR_ARG
+    assert nf.nufft2_group_destroy(null) == nf.NUFFT2_OK
 
 
 def test_binding_has_no_fallback_path():

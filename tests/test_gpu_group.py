@@ -1,0 +1,182 @@
+"""Groups of plans (nufft2_group_*): segmented launches in HIP graphs.
+
+A group runs the same kernel bodies as single plans, so every member's
+output must be bit-identical to running its plan alone; on top of that the
+outputs meet the oracle at the plan tolerance.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2605_01313_amd import nufft2  # noqa: F401  (fails loudly if not built)
+    return torch, torch.device("cuda:0")
+
+
+# (prec, K, F, n_pts, eps): uneven sizes, both precisions, a member without
+# points, and two members of the same class
+MEMBERS = [
+    ("fp32", 63, 1, 3000, 1e-6),
+    ("fp32", 127, 3, 9000, 1e-6),
+    ("fp32", 63, 1, 2500, 1e-6),
+    ("fp64", 31, 2, 1500, 1e-12),
+    ("fp32", 255, 2, 0, 1e-6),
+    ("fp64", 63, 1, 4000, 1e-12),
+]
+
+
+def make_inputs(seed):
+    rng = np.random.default_rng(seed)
+    data = []
+    for prec, K, F, n, eps in MEMBERS:
+        coeffs = synth.random_complex(rng, (F, K, K)) * synth.envelope_algebraic(K, K, 1.5)[None]
+        phi = rng.uniform(-1.0, 2 * np.pi + 1.0, n)
+        theta = rng.uniform(-0.3, np.pi + 0.3, n)
+        data.append((coeffs, phi, theta))
+    return data
+
+
+def to_dev(torch, dev, prec, coeffs, phi, theta):
+    cdt = torch.complex64 if prec == "fp32" else torch.complex128
+    return (torch.from_numpy(coeffs).to(dev).to(cdt), torch.from_numpy(phi).to(dev),
+            torch.from_numpy(theta).to(dev))
+
+
+def build(torch_dev):
+    from paper_2605_01313_amd import Group, Plan
+    plans = [Plan(prec, K, K, n_fields=F, eps=eps) for prec, K, F, n, eps in MEMBERS]
+    return plans, Group(plans)
+
+
+def test_group_info_classes(torch_dev):
+    plans, g = build(torch_dev)
+    info = g.info()
+    say(f"case group_info {info}")
+    # classes: fp32 K63 F1 (2 members), fp32 K127 F3, fp64 K31 F2, fp32 K255 F2, fp64 K63 F1
+    assert info["n_members"] == len(MEMBERS) and info["n_classes"] == 5
+    assert info["exec_kernels"] == 15 and info["setpts_kernels"] == 6
+    g.destroy()
+
+
+def test_group_bit_identical_to_single_and_meets_oracle(torch_dev, oracle_mod):
+    torch, dev = torch_dev
+    say("case group_vs_single")
+    data = make_inputs(7)
+    plans, g = build(torch_dev)
+    devin = [to_dev(torch, dev, m[0], *d) for m, d in zip(MEMBERS, data)]
+    g.setpts([x[1] for x in devin], [x[2] for x in devin])
+    outs = [o.clone() for o in g.exec([x[0] for x in devin])]
+    torch.cuda.synchronize()
+    for p in plans:
+        assert p.check() == 0
+    # the same plans run one by one
+    for i, (p, x) in enumerate(zip(plans, devin)):
+        p.setpts(x[1], x[2])
+        single = p.exec(x[0])
+        torch.cuda.synchronize()
+        a, b = outs[i].cpu().numpy(), single.cpu().numpy()
+        assert a.shape == b.shape
+        assert np.array_equal(a, b), f"member {i} differs from its single run"
+    # oracle on every member with points
+    for i, ((prec, K, F, n, eps), (coeffs, phi, theta)) in enumerate(zip(MEMBERS, data)):
+        if n == 0:
+            continue
+        ref = oracle_mod.dfs_eval(coeffs, phi, theta)
+        got = outs[i].cpu().numpy()
+        errs = [float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(F)]
+        say(f"  member {i} {prec} K={K} F={F} n={n}: rel l2 {max(errs):.2e}")
+        assert max(errs) <= eps
+    g.destroy()
+
+
+def test_group_graph_replays_with_eager_work_between(torch_dev):
+    """Replaying the captured graphs gives the first result every time, with
+    other eager work and synchronisations in between."""
+    torch, dev = torch_dev
+    say("case group_replays")
+    data = make_inputs(8)
+    plans, g = build(torch_dev)
+    devin = [to_dev(torch, dev, m[0], *d) for m, d in zip(MEMBERS, data)]
+    phis, thetas, coeffs = [x[1] for x in devin], [x[2] for x in devin], [x[0] for x in devin]
+    outs = [torch.empty((F, max(n, 1)), dtype=c.dtype, device=dev)
+            for (prec, K, F, n, eps), c in zip(MEMBERS, coeffs)]
+    g.setpts(phis, thetas)
+    g.exec(coeffs, outs)
+    torch.cuda.synchronize()
+    # members without points write nothing: compare the written columns
+    ns = [m[3] for m in MEMBERS]
+    first = [o[:, :n].cpu().numpy().copy() for o, n in zip(outs, ns)]
+    scratch = torch.randn(1 << 20, device=dev)
+    for rep in range(4):
+        scratch.mul_(1.0001).add_(0.5)          # unrelated eager work
+        for o in outs:
+            o.zero_()
+        g.setpts(phis, thetas)
+        g.exec(coeffs, outs)
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            assert np.array_equal(o[:, :ns[i]].cpu().numpy(), first[i]), f"replay {rep} member {i}"
+    g.destroy()
+
+
+def test_group_pointer_and_count_changes(torch_dev, oracle_mod):
+    """New output buffers, new coefficient buffers and new point counts are
+    picked up (table rewrite, setpts graph recapture)."""
+    torch, dev = torch_dev
+    say("case group_changes")
+    plans, g = build(torch_dev)
+    for seed, scale in ((9, 1.0), (10, 0.5)):
+        data = make_inputs(seed)
+        if scale != 1.0:   # different point counts on the second round
+            data = [(c, p[: int(len(p) * scale)], t[: int(len(t) * scale)]) for c, p, t in data]
+        devin = [to_dev(torch, dev, m[0], *d) for m, d in zip(MEMBERS, data)]
+        g.setpts([x[1] for x in devin], [x[2] for x in devin])
+        outs = g.exec([x[0] for x in devin])
+        torch.cuda.synchronize()
+        for i, ((prec, K, F, n, eps), (coeffs, phi, theta)) in enumerate(zip(MEMBERS, data)):
+            if len(phi) == 0:
+                continue
+            sel = np.arange(0, len(phi), max(1, len(phi) // 200))
+            ref = oracle_mod.dfs_eval(coeffs, phi[sel], theta[sel])
+            got = outs[i].cpu().numpy()[:, sel]
+            err = max(float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(F))
+            assert err <= 3 * eps, (seed, i, err)
+    g.destroy()
+
+
+def test_group_argument_errors(torch_dev):
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Group, Nufft2Error, Plan, nufft2
+    say("case group_errors")
+    p0 = Plan("fp32", 31, 31, n_fields=1, eps=1e-6)
+    p1 = Plan("fp32", 31, 31, n_fields=1, eps=1e-6, stream=torch.cuda.Stream())
+    with pytest.raises(Nufft2Error):
+        Group([p0, p1])                      # mixed streams
+    with pytest.raises(Nufft2Error):
+        Group([p0, p0])                      # repeated plan
+    p2 = Plan("fp32", 31, 31, n_fields=1, eps=1e-6)
+    g = Group([p0, p2])
+    c = torch.zeros((1, 31, 31), dtype=torch.complex64, device=dev)
+    st = nufft2.nufft2_group_exec(g.handle, [c.data_ptr(), c.data_ptr()], [c.data_ptr(), c.data_ptr()])
+    assert st == nufft2.NUFFT2_ERR_NO_POINTS
+    phi = torch.zeros(4, dtype=torch.float64, device=dev)
+    st = nufft2.nufft2_group_setpts(g.handle, [4, 4], [phi.data_ptr(), 0], [phi.data_ptr(), phi.data_ptr()])
+    assert st == nufft2.NUFFT2_ERR_ARG
+    g.setpts([phi, phi], [phi, phi])
+    st = nufft2.nufft2_group_exec(g.handle, [c.data_ptr(), 0], [c.data_ptr(), c.data_ptr()])
+    assert st == nufft2.NUFFT2_ERR_ARG
+    g.destroy()
