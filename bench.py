@@ -170,6 +170,143 @@ def cpu_baseline(wl, gpu_out, target_s):
                       f"{dt:.1f} s", "gpu_rel_l2_on_sample": errs}
 
 
+def _member(spec):
+    import synth
+    return synth.ensemble_member(spec)
+
+
+def build_members(specs):
+    """Generate the members' inputs in worker processes (spawned: they import
+    numpy and scipy only, never the GPU runtime)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(16, os.cpu_count() or 1, len(specs)))
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_member, specs))
+
+
+def ensemble_bench(args, torch):
+    """Uneven ensemble: 64 members on 128x256 grids + 16 on 256x512, 3 fields
+    each, own seed, spectrum and 8-mode wind; FP32 eps 1e-6, width and tiles
+    from the autotuner; every step is one group setpts + one group exec (two
+    graph launches).  Compared with the plain path on the same GPU: FP64
+    eps 1e-12, one field per exec, synchronised after every exec."""
+    import tempfile
+
+    import numpy as np
+
+    import oracle
+    import synth
+    from paper_2605_01313_amd import Group, Plan, autotune
+    dev = torch.device("cuda:0")
+    specs = synth.ensemble_members()
+    log(f"bench: building {len(specs)} ensemble members")
+    members = build_members(specs)
+    F = members[0].n_fields
+    cache = args.tune_cache or os.path.join(tempfile.gettempdir(), "nufft2_tune.json")
+    tuned = {}
+    for m in members:
+        K = m.coeffs.shape[-1]
+        if K in tuned:
+            continue
+        phi = torch.from_numpy(m.phi).to(dev)
+        theta = torch.from_numpy(m.theta).to(dev)
+        tuned[K] = autotune("fp32", K, K, F, 1e-6, phi, theta, cache_path=cache)
+        log(f"bench: tuned K={K}: {tuned[K]}")
+    plans, coeffs, phis, thetas, outs = [], [], [], [], []
+    for m in members:
+        K = m.coeffs.shape[-1]
+        t = tuned[K]
+        plans.append(Plan("fp32", K, K, n_fields=F, eps=1e-6, w=t["w"], tile_theta=t["tile_theta"],
+                          tile_phi=t["tile_phi"]))
+        coeffs.append(torch.from_numpy(m.coeffs).to(dev).to(torch.complex64).contiguous())
+        phis.append(torch.from_numpy(m.phi).to(dev).contiguous())
+        thetas.append(torch.from_numpy(m.theta).to(dev).contiguous())
+        outs.append(torch.empty((F, m.n_pts), dtype=torch.complex64, device=dev))
+    g = Group(plans)
+    n_pf = sum(F * m.n_pts for m in members)
+
+    def step():
+        g.setpts(phis, thetas)
+        g.exec(coeffs, outs)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    lat = []
+    s = torch.cuda.current_stream()
+    for _ in range(min(args.steps, 100)):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        step()
+        b.record(s)
+        b.synchronize()
+        lat.append(a.elapsed_time(b))
+    lat.sort()
+    pct = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]
+    log(f"bench: ensemble {ms:.3f} ms/step, {n_pf / ms * 1e3:.3e} points*fields/s")
+
+    # plain path: one FP64 plan per grid size, one field per exec, synchronous
+    plain = {}
+    for m in members:
+        K = m.coeffs.shape[-1]
+        if K not in plain:
+            plain[K] = Plan("fp64", K, K, n_fields=1, eps=1e-12)
+    c64 = [torch.from_numpy(m.coeffs).to(dev).contiguous() for m in members]
+    o64 = [torch.empty((1, m.n_pts), dtype=torch.complex128, device=dev) for m in members]
+
+    def plain_step():
+        for i, m in enumerate(members):
+            p = plain[m.coeffs.shape[-1]]
+            p.setpts(phis[i], thetas[i])
+            for f in range(F):
+                p.exec(c64[i][f], o64[i])
+                torch.cuda.synchronize()
+
+    plain_step()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plain_step()
+    ms64 = (time.perf_counter() - t0) * 1e3 / reps
+    log(f"bench: plain FP64 path {ms64:.3f} ms/step")
+
+    # accuracy on a few members against the oracle (256 sampled points each)
+    step()
+    torch.cuda.synchronize()
+    errs = []
+    for i in (0, 31, 63, 64, 79):
+        m = members[i]
+        sel = synth.sample_indices(m.n_pts, 256, seed=20 + i)
+        ref = oracle.dfs_eval(m.coeffs, m.phi[sel], m.theta[sel])
+        got = outs[i].cpu().numpy()[:, sel]
+        errs.append(max(float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(F)))
+    info = g.info()
+    line = {
+        "metric": METRIC, "value": n_pf / (ms * 1e-3), "unit": "points*fields/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "ensemble_64x128x256_16x256x512_3fields", "members": len(members),
+                   "points_x_fields": n_pf, "eps": 1e-6, "tuned": {str(k): v for k, v in tuned.items()},
+                   "classes": info["n_classes"], "kernels_per_step": info["setpts_kernels"] + info["exec_kernels"],
+                   "step": "group setpts + group exec (two graph launches)"},
+        "latency_ms": {"p50": pct(0.5), "p99": pct(0.99)},
+        "plain_fp64_single_field": {"value": n_pf / (ms64 * 1e-3), "unit": "points*fields/s",
+                                    "ms_per_step": ms64, "eps": 1e-12,
+                                    "speedup_of_batched_fp32": ms64 / ms},
+        "rel_l2_vs_oracle_sampled": {"members": [0, 31, 63, 64, 79], "max": max(errs)},
+        "roofline": None, "cpu_baseline": None,
+    }
+    g.destroy()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,9 +314,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("sbr256", "wind1024"), default="sbr256",
+    ap.add_argument("--workload", choices=("sbr256", "wind1024", "ensemble"), default="sbr256",
                     help="sbr256: 256x512 grid, solid-body rotation (default); "
-                         "wind1024: 1024x2048 grid, 8-mode wind, Courant 8")
+                         "wind1024: 1024x2048 grid, 8-mode wind, Courant 8; "
+                         "ensemble: 64 + 16 members of uneven size as one group")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (ensemble)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter scale for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -193,6 +332,9 @@ def main():
 
     import synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "ensemble":
+        ensemble_bench(args, torch)
+        return
     if args.workload == "sbr256":
         log("bench: building the 256x512 solid-body-rotation workload")
         wl = synth.workload_sbr()

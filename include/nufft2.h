@@ -201,6 +201,45 @@ nufft2_status nufft2_group_destroy(nufft2_group g);
 nufft2_status nufft2_group_get_info(nufft2_group g, nufft2_group_info *info);
 
 /*
+ * nufft2_autotune -- choose the kernel width and gather tiles for a problem
+ * (the same shape, tolerance and point distribution as the caller's).
+ *   Width: the rule w0 = ceil(log10(1/eps)) + 1 is a guide, not the answer:
+ *   for w in w0 - 1, w0, w0 + 1 the tuner measures the relative l2 error of
+ *   a plan of width w against an FP64 plan of width min(16, w0 + 3) on the
+ *   first min(n_pts, 16384) of the caller's points and one field of
+ *   pseudo-random coefficients with a flat spectrum (the hardest case for a
+ *   given tolerance), and keeps the smallest w whose error is <= eps (w0 + 1
+ *   if none is).
+ *   Tiles: for that width it times setpts + exec of n_fields fields on all
+ *   n_pts points (HIP events on `stream`, median of 3 after a warm-up) for
+ *   each gather tile shape in a fixed candidate list that fits the LDS, and
+ *   keeps the fastest.
+ *   cache_path (may be NULL): a JSON file of earlier results, keyed by
+ *   precision, mode counts, fields, eps, point count rounded up to a power of
+ *   two and the device's architecture name; a hit skips the measurements,
+ *   a miss adds an entry (the file is rewritten through a temporary file).
+ *   opts_out receives w, tile_theta and tile_phi (other fields zero);
+ *   result (may be NULL) the measured error, time and whether the cache
+ *   answered.  The tuner creates and destroys its own plans and buffers on
+ *   the current device and synchronises `stream`.
+ *   Errors: as nufft2_plan for the arguments (n_pts must be >= 1), ERR_ALLOC,
+ *   ERR_HIP.
+ */
+typedef struct {
+    int32_t w, tile_theta, tile_phi;
+    int32_t from_cache;   /* 1: read from the cache file */
+    double err;           /* relative l2 error of the chosen width on the probe */
+    double ms;            /* setpts + exec time of the chosen configuration */
+    int32_t n_timed;      /* configurations timed */
+    int32_t reserved;
+} nufft2_tune_result;
+
+nufft2_status nufft2_autotune(nufft2_prec prec, int64_t n_modes_theta, int64_t n_modes_phi, int32_t n_fields,
+                              double eps, int64_t n_pts, const double *phi_dev, const double *theta_dev,
+                              void *stream, const char *cache_path, nufft2_opts *opts_out,
+                              nufft2_tune_result *result);
+
+/*
  * Host-only helpers (no device work; usable without a GPU).
  *
  * nufft2_kernel_params -- the width and shape the plan would choose for eps

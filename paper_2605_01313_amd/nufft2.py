@@ -32,7 +32,7 @@ EXPORTED = (
     "nufft2_get_info", "nufft2_check", "nufft2_set_stream", "nufft2_kernel_params",
     "nufft2_kernel_correction", "nufft2_debug_buffer", "nufft2_profile_enable",
     "nufft2_profile_read", "nufft2_group_create", "nufft2_group_setpts", "nufft2_group_exec",
-    "nufft2_group_destroy", "nufft2_group_get_info",
+    "nufft2_group_destroy", "nufft2_group_get_info", "nufft2_autotune",
 )
 NUFFT2_N_STAGES = 4
 STAGE_NAMES = ("setpts", "theta_pass", "phi_pass", "gather")
@@ -67,6 +67,15 @@ class nufft2_group_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class nufft2_tune_result(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_int32), ("tile_theta", ctypes.c_int32), ("tile_phi", ctypes.c_int32),
+                ("from_cache", ctypes.c_int32), ("err", ctypes.c_double), ("ms", ctypes.c_double),
+                ("n_timed", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -93,6 +102,8 @@ def _load():
         "nufft2_group_exec": [H, vp, vp],
         "nufft2_group_destroy": [H],
         "nufft2_group_get_info": [H, ctypes.POINTER(nufft2_group_info)],
+        "nufft2_autotune": [i32, i64, i64, i32, dbl, i64, vp, vp, vp, ctypes.c_char_p,
+                            ctypes.POINTER(nufft2_opts), ctypes.POINTER(nufft2_tune_result)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -225,6 +236,18 @@ def nufft2_group_get_info(group):
     info = nufft2_group_info()
     st = _lib.nufft2_group_get_info(group, ctypes.byref(info))
     return st, info
+
+
+def nufft2_autotune(prec, n_modes_theta, n_modes_phi, n_fields, eps, n_pts, phi_ptr, theta_ptr,
+                    stream=0, cache_path=None):
+    """Returns (status, nufft2_opts, nufft2_tune_result)."""
+    opts = nufft2_opts()
+    res = nufft2_tune_result()
+    st = _lib.nufft2_autotune(int(prec), int(n_modes_theta), int(n_modes_phi), int(n_fields), float(eps),
+                              int(n_pts), ctypes.c_void_p(phi_ptr or None), ctypes.c_void_p(theta_ptr or None),
+                              ctypes.c_void_p(stream or None),
+                              cache_path.encode() if cache_path else None, ctypes.byref(opts), ctypes.byref(res))
+    return st, opts, res
 
 
 # ---- torch convenience -----------------------------------------------------
@@ -400,3 +423,24 @@ class Group:
             self.destroy()
         except Exception:
             pass
+
+
+def autotune(prec, n_modes_theta, n_modes_phi, n_fields, eps, phi, theta, cache_path=None, stream=None):
+    """Tune width and tiles on the given points (float64 device tensors).
+
+    Returns a dict: w, tile_theta, tile_phi (keyword arguments for Plan) and
+    the measurement (err, ms, from_cache, n_timed).
+    """
+    import torch
+    prec_code = {"fp32": NUFFT2_FP32, "fp64": NUFFT2_FP64, NUFFT2_FP32: NUFFT2_FP32,
+                 NUFFT2_FP64: NUFFT2_FP64}[prec]
+    for x in (phi, theta):
+        if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
+            raise TypeError("points must be contiguous float64 device tensors")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st, opts, res = nufft2_autotune(prec_code, n_modes_theta, n_modes_phi, n_fields, eps, phi.numel(),
+                                    phi.data_ptr(), theta.data_ptr(), s.cuda_stream, cache_path)
+    _check(st, "nufft2_autotune")
+    out = res.as_dict()
+    out.update(w=opts.w, tile_theta=opts.tile_theta, tile_phi=opts.tile_phi)
+    return out

@@ -1,0 +1,78 @@
+"""Autotuner (nufft2_autotune): width by measured accuracy, tiles by time,
+JSON cache; the tuned plan meets the oracle at the requested tolerance."""
+import json
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TILES = {(8, 32), (16, 32), (16, 64), (32, 32), (8, 64), (32, 64)}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2605_01313_amd import nufft2  # noqa: F401  (fails loudly if not built)
+    return torch, torch.device("cuda:0")
+
+
+@pytest.mark.parametrize("prec,eps,J,F", [("fp32", 1e-6, 128, 3), ("fp64", 1e-12, 32, 1)])
+def test_autotune_choice_cache_and_accuracy(torch_dev, oracle_mod, tmp_path, prec, eps, J, F):
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Plan, autotune, nufft2_kernel_params
+    say(f"case autotune prec={prec} J={J}")
+    spec = synth.ensemble_members(n_small=1, n_large=0, J_small=J)[0]
+    wl = synth.ensemble_member(spec, n_fields=F)
+    K = wl.coeffs.shape[-1]
+    phi = torch.from_numpy(wl.phi).to(dev)
+    theta = torch.from_numpy(wl.theta).to(dev)
+    cache = str(tmp_path / "tune.json")
+    code = 1 if prec == "fp32" else 2
+    _, w0, _ = nufft2_kernel_params(code, eps)
+    r = autotune(prec, K, K, F, eps, phi, theta, cache_path=cache)
+    say(f"  tuned {r}")
+    assert w0 - 1 <= r["w"] <= w0 + 1
+    assert (r["tile_theta"], r["tile_phi"]) in TILES
+    assert r["from_cache"] == 0 and r["n_timed"] >= 3 and r["ms"] > 0
+    assert r["err"] <= eps or r["w"] == w0 + 1
+    # the cache answers the same question without measuring
+    r2 = autotune(prec, K, K, F, eps, phi, theta, cache_path=cache)
+    assert r2["from_cache"] == 1
+    assert (r2["w"], r2["tile_theta"], r2["tile_phi"]) == (r["w"], r["tile_theta"], r["tile_phi"])
+    with open(cache) as f:
+        entries = json.load(f)["nufft2_autotune"]
+    assert len(entries) == 1 and entries[0]["w"] == r["w"]
+    # the tuned plan meets the oracle on sampled points of this workload
+    plan = Plan(prec, K, K, n_fields=F, eps=eps, w=r["w"], tile_theta=r["tile_theta"],
+                tile_phi=r["tile_phi"])
+    plan.setpts(phi, theta)
+    cdt = torch.complex64 if prec == "fp32" else torch.complex128
+    out = plan.exec(torch.from_numpy(wl.coeffs).to(dev).to(cdt)).cpu().numpy()
+    sel = synth.sample_indices(wl.n_pts, 2000)
+    ref = oracle_mod.dfs_eval(wl.coeffs, wl.phi[sel], wl.theta[sel])
+    err = max(float(np.linalg.norm(out[f, sel] - ref[f]) / np.linalg.norm(ref[f])) for f in range(F))
+    say(f"  tuned plan rel l2 {err:.2e}")
+    assert err <= eps
+    plan.destroy()
+
+
+def test_autotune_argument_errors(torch_dev):
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import nufft2
+    x = torch.zeros(8, dtype=torch.float64, device=dev)
+    st, _, _ = nufft2.nufft2_autotune(1, 63, 63, 1, 1e-6, 0, x.data_ptr(), x.data_ptr())
+    assert st == nufft2.NUFFT2_ERR_ARG                  # no points
+    st, _, _ = nufft2.nufft2_autotune(1, 63, 63, 1, 1e-9, 8, x.data_ptr(), x.data_ptr())
+    assert st == nufft2.NUFFT2_ERR_EPS_RANGE
+    st, _, _ = nufft2.nufft2_autotune(1, 63, 63, 1, 1e-6, 8, 0, x.data_ptr())
+    assert st == nufft2.NUFFT2_ERR_ARG
