@@ -185,6 +185,117 @@ def build_members(specs):
         return list(ex.map(_member, specs))
 
 
+def _serving_points(job):
+    """Departure points of one payload: J, wind seed, Courant number."""
+    import numpy as np
+
+    import synth
+    J, seed, courant = job
+    phi_a, theta_a = synth.grid0_points(J)
+    wind = synth.StreamFunctionWind(np.random.default_rng(seed))
+    wind.normalize_courant(phi_a, theta_a, courant, J)
+    return wind.departures(phi_a, theta_a)
+
+
+def serving_bench(args, torch):
+    """Serving loop: Poisson arrivals (2000 requests/s by default) of requests
+    with a grid drawn from 64x128 .. 512x1024, 1-3 fields, FP32 eps 1e-6 (80%)
+    or FP64 eps 1e-12 (20%), each with the departure points of a random
+    8-mode wind.  Payloads are pregenerated in pinned host memory and reused
+    cyclically; latency runs from each request's scheduled arrival to the end
+    of its device-to-host copy."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import numpy as np
+
+    import synth
+    from paper_2605_01313_amd import Server
+    Js = (64, 128, 256, 512)
+    n_pts_pool, n_coef_pool = args.serve_pool, 2
+    rng = np.random.default_rng(2000)
+    jobs = [(J, 20000 + 100 * J + i, float(rng.uniform(2.0, 8.0))) for J in Js for i in range(n_pts_pool)]
+    log(f"bench: generating {len(jobs)} departure-point payloads")
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        pts = list(ex.map(_serving_points, jobs))
+    pool = {J: {"pts": [], "c32": [], "c64": []} for J in Js}
+    for (J, _, _), (phi, theta) in zip(jobs, pts):
+        pool[J]["pts"].append((torch.from_numpy(phi).pin_memory(), torch.from_numpy(theta).pin_memory()))
+    for J in Js:
+        K = 2 * J - 1
+        for i in range(n_coef_pool):
+            c = synth.random_complex(np.random.default_rng(30000 + 10 * J + i), (3, K, K))
+            c *= synth.envelope_algebraic(K, K, 1.5)[None]
+            pool[J]["c64"].append(torch.from_numpy(c).pin_memory())
+            pool[J]["c32"].append(torch.from_numpy(c).to(torch.complex64).pin_memory())
+    # the request stream
+    n_req = int(args.serve_rate * args.serve_seconds)
+    gaps = rng.exponential(1.0 / args.serve_rate, n_req)
+    arrivals = np.cumsum(gaps)
+    sizes = rng.choice(Js, n_req)
+    fields = rng.integers(1, 4, n_req)
+    is64 = rng.random(n_req) < 0.2
+    srv = Server(hbm_budget=args.serve_budget_gib << 30, max_inflight=args.serve_inflight)
+
+    def request(i, J, F, fp64):
+        c = pool[J]["c64" if fp64 else "c32"][i % n_coef_pool][:F]
+        phi, theta = pool[J]["pts"][i % n_pts_pool]
+        return ("fp64" if fp64 else "fp32", c, phi, theta, 1e-12 if fp64 else 1e-6)
+
+    # warm-up: one request of every (size, fields, precision) creates its plan
+    log("bench: serving warm-up (one request per plan key)")
+    for J in Js:
+        for F in (1, 2, 3):
+            for fp64 in (False, True):
+                prec, c, phi, theta, eps = request(0, J, F, fp64)
+                srv.submit(prec, c, phi, theta, eps)
+    srv.drain()
+    warm = srv.stats()
+    log(f"bench: serving {n_req} requests over {args.serve_seconds:.0f} s")
+    t_start = srv.clock() + 0.05
+    lag = 0.0
+    for i in range(n_req):
+        t_arr = t_start + arrivals[i]
+        while True:
+            now = srv.clock()
+            if now >= t_arr:
+                break
+            if t_arr - now > 0.002:
+                time.sleep(t_arr - now - 0.001)
+        lag = max(lag, srv.clock() - t_arr)
+        prec, c, phi, theta, eps = request(i, int(sizes[i]), int(fields[i]), bool(is64[i]))
+        srv.submit(prec, c, phi, theta, eps, t_arrival=t_arr)
+        if i % 20000 == 0:
+            log(f"bench: {i} requests submitted")
+    srv.drain()
+    st = srv.stats()
+    srv.destroy()
+    done = st["completed"] - warm["completed"]
+    pf = st["points_fields"] - warm["points_fields"]
+    span = st["last_completion"] - t_start
+    offered_pf = float(sum(2 * int(J) ** 2 * int(F) for J, F in zip(sizes, fields))) / args.serve_seconds
+    line = {
+        "metric": METRIC, "value": pf / span, "unit": "points*fields/s", "n_gpus": 1,
+        "steps": n_req, "warmup": warm["completed"], "ms_per_step": span * 1e3 / max(done, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "serving_poisson_mixed_grids", "rate_per_s": args.serve_rate,
+                   "seconds": args.serve_seconds, "grids": "64x128,128x256,256x512,512x1024",
+                   "fields": "1-3", "fp32_share": 0.8, "hbm_budget_gib": args.serve_budget_gib,
+                   "max_inflight": args.serve_inflight, "payload_pool_per_size": n_pts_pool,
+                   "step": "one request: H2D, setpts, exec, D2H"},
+        "latency_ms": {"p50": st["latency_p50"] * 1e3, "p99": st["latency_p99"] * 1e3,
+                       "max": st["latency_max"] * 1e3},
+        "serving": {"requests": done, "failed": st["failed"], "offered_points_fields_per_s": offered_pf,
+                    "submit_lag_max_ms": lag * 1e3, "plans_created": st["plans_created"],
+                    "plans_evicted": st["plans_evicted"], "hbm_high_water_gib": st["hbm_high_water"] / 2**30,
+                    "max_inflight_seen": st["max_inflight_seen"]},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def ensemble_bench(args, torch):
     """Uneven ensemble: 64 members on 128x256 grids + 16 on 256x512, 3 fields
     each, own seed, spectrum and 8-mode wind; FP32 eps 1e-6, width and tiles
@@ -314,10 +425,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("sbr256", "wind1024", "ensemble"), default="sbr256",
+    ap.add_argument("--workload", choices=("sbr256", "wind1024", "ensemble", "serving"), default="sbr256",
                     help="sbr256: 256x512 grid, solid-body rotation (default); "
                          "wind1024: 1024x2048 grid, 8-mode wind, Courant 8; "
-                         "ensemble: 64 + 16 members of uneven size as one group")
+                         "ensemble: 64 + 16 members of uneven size as one group; "
+                         "serving: Poisson request stream through the serving loop")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="requests per second")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-pool", type=int, default=8, help="point payloads per grid size")
+    ap.add_argument("--serve-budget-gib", type=int, default=16)
+    ap.add_argument("--serve-inflight", type=int, default=16)
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (ensemble)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter scale for rocprofv3 --pmc)")
@@ -334,6 +451,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "ensemble":
         ensemble_bench(args, torch)
+        return
+    if args.workload == "serving":
+        serving_bench(args, torch)
         return
     if args.workload == "sbr256":
         log("bench: building the 256x512 solid-body-rotation workload")

@@ -240,6 +240,79 @@ nufft2_status nufft2_autotune(nufft2_prec prec, int64_t n_modes_theta, int64_t n
                               nufft2_tune_result *result);
 
 /*
+ * Serving: a request loop that evaluates independent interpolation requests
+ * of mixed size and tolerance (section 5's evaluation, one request per
+ * point set) with continuous batching.  A scheduler thread admits queued
+ * requests in arrival order as soon as an in-flight slot is free and the
+ * request's device footprint (its plan's workspaces and its own input and
+ * output buffers) fits the HBM budget; admitted requests run on their
+ * slot's stream, so requests that arrive while others are on the GPU
+ * overlap with them.  Plans are cached by (precision, modes, fields, eps)
+ * and reused; idle cached plans are destroyed, least recently used first,
+ * when their memory is needed.  A request's result does not depend on what
+ * else runs with it (each runs on its own plan and buffers).
+ *
+ * nufft2_server_create -- opts: hbm_budget bytes of device memory for plans
+ *   and request buffers (0: 16 GiB), max_inflight requests on the device at
+ *   once (0: 8, at most 64).  The server owns one stream per slot (default
+ *   priority), a pinned host staging buffer per slot for discarded outputs,
+ *   and the scheduler thread; it runs on the current device.
+ *   Errors: ERR_ARG, ERR_ALLOC, ERR_HIP.
+ * nufft2_server_submit -- queue one request (returns at once).  The host
+ *   buffers must stay valid and unchanged until the request completes;
+ *   pinned memory lets the copies overlap with other work.  out_host may be
+ *   NULL: the result is copied to a server staging buffer and dropped (the
+ *   copy still counts toward the latency).  t_arrival is the request's
+ *   arrival time on the server clock (nufft2_server_clock); latency runs
+ *   from it to the end of the device-to-host copy.  *ticket identifies the
+ *   request.  Errors: ERR_ARG (bad sizes, eps, null inputs, or a request
+ *   whose footprint alone exceeds the budget), ERR_EPS_RANGE.
+ * nufft2_server_wait -- block until the request has completed; its status
+ *   (a plan or HIP error of that request) and latency in seconds.
+ * nufft2_server_stats -- counters and latency percentiles of the requests
+ *   completed so far (and the high-water mark of reserved device memory).
+ * nufft2_server_drain -- block until every submitted request has completed.
+ * nufft2_server_destroy -- drain, stop the thread, free everything.
+ */
+typedef struct nufft2_server_s *nufft2_server;
+typedef struct {
+    uint64_t hbm_budget;
+    int32_t max_inflight;
+    int32_t reserved;
+} nufft2_server_opts;
+
+typedef struct {
+    int32_t prec;                /* nufft2_prec */
+    int32_t n_fields;
+    int64_t n_modes_theta, n_modes_phi;
+    double eps;
+    int64_t n_pts;               /* >= 1 */
+    const void *coeffs_host;     /* [n_fields][Kt][Kp] complex, plan precision */
+    const double *phi_host, *theta_host;  /* [n_pts] each */
+    void *out_host;              /* [n_fields][n_pts] complex, or NULL */
+    double t_arrival;            /* seconds, server clock */
+} nufft2_request;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t points_fields;       /* sum over completed requests */
+    double latency_p50, latency_p99, latency_max;  /* seconds */
+    double first_arrival, last_completion;          /* server clock */
+    int64_t plans_created, plans_evicted;
+    uint64_t hbm_high_water;     /* bytes reserved at most at once */
+    int32_t max_inflight_seen;
+    int32_t reserved;
+} nufft2_server_stats_t;
+
+nufft2_status nufft2_server_create(const nufft2_server_opts *opts, nufft2_server *out);
+double nufft2_server_clock(nufft2_server s);
+nufft2_status nufft2_server_submit(nufft2_server s, const nufft2_request *req, uint64_t *ticket);
+nufft2_status nufft2_server_wait(nufft2_server s, uint64_t ticket, nufft2_status *req_status, double *latency);
+nufft2_status nufft2_server_drain(nufft2_server s);
+nufft2_status nufft2_server_stats(nufft2_server s, nufft2_server_stats_t *stats);
+nufft2_status nufft2_server_destroy(nufft2_server s);
+
+/*
  * Host-only helpers (no device work; usable without a GPU).
  *
  * nufft2_kernel_params -- the width and shape the plan would choose for eps

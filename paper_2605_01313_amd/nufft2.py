@@ -32,7 +32,9 @@ EXPORTED = (
     "nufft2_get_info", "nufft2_check", "nufft2_set_stream", "nufft2_kernel_params",
     "nufft2_kernel_correction", "nufft2_debug_buffer", "nufft2_profile_enable",
     "nufft2_profile_read", "nufft2_group_create", "nufft2_group_setpts", "nufft2_group_exec",
-    "nufft2_group_destroy", "nufft2_group_get_info", "nufft2_autotune",
+    "nufft2_group_destroy", "nufft2_group_get_info", "nufft2_autotune", "nufft2_server_create",
+    "nufft2_server_clock", "nufft2_server_submit", "nufft2_server_wait", "nufft2_server_drain",
+    "nufft2_server_stats", "nufft2_server_destroy",
 )
 NUFFT2_N_STAGES = 4
 STAGE_NAMES = ("setpts", "theta_pass", "phi_pass", "gather")
@@ -76,6 +78,33 @@ class nufft2_tune_result(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class nufft2_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class nufft2_request(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("n_fields", ctypes.c_int32),
+                ("n_modes_theta", ctypes.c_int64), ("n_modes_phi", ctypes.c_int64),
+                ("eps", ctypes.c_double), ("n_pts", ctypes.c_int64),
+                ("coeffs_host", ctypes.c_void_p), ("phi_host", ctypes.c_void_p),
+                ("theta_host", ctypes.c_void_p), ("out_host", ctypes.c_void_p),
+                ("t_arrival", ctypes.c_double)]
+
+
+class nufft2_server_stats_t(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("points_fields", ctypes.c_int64), ("latency_p50", ctypes.c_double),
+                ("latency_p99", ctypes.c_double), ("latency_max", ctypes.c_double),
+                ("first_arrival", ctypes.c_double), ("last_completion", ctypes.c_double),
+                ("plans_created", ctypes.c_int64), ("plans_evicted", ctypes.c_int64),
+                ("hbm_high_water", ctypes.c_uint64), ("max_inflight_seen", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -104,11 +133,19 @@ def _load():
         "nufft2_group_get_info": [H, ctypes.POINTER(nufft2_group_info)],
         "nufft2_autotune": [i32, i64, i64, i32, dbl, i64, vp, vp, vp, ctypes.c_char_p,
                             ctypes.POINTER(nufft2_opts), ctypes.POINTER(nufft2_tune_result)],
+        "nufft2_server_create": [ctypes.POINTER(nufft2_server_opts), ctypes.POINTER(H)],
+        "nufft2_server_submit": [H, ctypes.POINTER(nufft2_request), ctypes.POINTER(ctypes.c_uint64)],
+        "nufft2_server_wait": [H, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(dbl)],
+        "nufft2_server_drain": [H],
+        "nufft2_server_stats": [H, ctypes.POINTER(nufft2_server_stats_t)],
+        "nufft2_server_destroy": [H],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    lib.nufft2_server_clock.argtypes = [H]
+    lib.nufft2_server_clock.restype = ctypes.c_double
     lib.nufft2_strerror.argtypes = [ctypes.c_int]
     lib.nufft2_strerror.restype = ctypes.c_char_p
     return lib
@@ -248,6 +285,47 @@ def nufft2_autotune(prec, n_modes_theta, n_modes_phi, n_fields, eps, n_pts, phi_
                               ctypes.c_void_p(stream or None),
                               cache_path.encode() if cache_path else None, ctypes.byref(opts), ctypes.byref(res))
     return st, opts, res
+
+
+def nufft2_server_create(hbm_budget=0, max_inflight=0):
+    """Returns (status, server handle)."""
+    o = nufft2_server_opts(int(hbm_budget), int(max_inflight), 0)
+    h = ctypes.c_void_p()
+    st = _lib.nufft2_server_create(ctypes.byref(o), ctypes.byref(h))
+    return st, h
+
+
+def nufft2_server_clock(server):
+    return _lib.nufft2_server_clock(server)
+
+
+def nufft2_server_submit(server, req):
+    """req: nufft2_request.  Returns (status, ticket)."""
+    t = ctypes.c_uint64()
+    st = _lib.nufft2_server_submit(server, ctypes.byref(req), ctypes.byref(t))
+    return st, t.value
+
+
+def nufft2_server_wait(server, ticket):
+    """Returns (status, request status, latency seconds)."""
+    rs = ctypes.c_int()
+    lat = ctypes.c_double()
+    st = _lib.nufft2_server_wait(server, int(ticket), ctypes.byref(rs), ctypes.byref(lat))
+    return st, rs.value, lat.value
+
+
+def nufft2_server_drain(server):
+    return _lib.nufft2_server_drain(server)
+
+
+def nufft2_server_stats(server):
+    s = nufft2_server_stats_t()
+    st = _lib.nufft2_server_stats(server, ctypes.byref(s))
+    return st, s
+
+
+def nufft2_server_destroy(server):
+    return _lib.nufft2_server_destroy(server)
 
 
 # ---- torch convenience -----------------------------------------------------
@@ -444,3 +522,73 @@ def autotune(prec, n_modes_theta, n_modes_phi, n_fields, eps, phi, theta, cache_
     out = res.as_dict()
     out.update(w=opts.w, tile_theta=opts.tile_theta, tile_phi=opts.tile_phi)
     return out
+
+
+class Server:
+    """Request loop with continuous batching (nufft2_server_*).
+
+    Host tensors (pinned for overlap) stay referenced until their request
+    completes.
+
+    >>> srv = Server(hbm_budget=8 << 30, max_inflight=8)
+    >>> t = srv.submit("fp32", coeffs, phi, theta, eps=1e-6, out=out)   # CPU tensors
+    >>> status, latency = srv.wait(t)
+    """
+
+    def __init__(self, hbm_budget=0, max_inflight=0):
+        st, h = nufft2_server_create(hbm_budget, max_inflight)
+        _check(st, "nufft2_server_create")
+        self.handle = h
+        self._live = {}
+
+    def clock(self):
+        return nufft2_server_clock(self.handle)
+
+    def submit(self, prec, coeffs, phi, theta, eps, out=None, t_arrival=None):
+        import torch
+        code = {"fp32": NUFFT2_FP32, "fp64": NUFFT2_FP64}[prec]
+        cdt = torch.complex64 if code == NUFFT2_FP32 else torch.complex128
+        if coeffs.dtype != cdt or coeffs.is_cuda or not coeffs.is_contiguous() or coeffs.dim() != 3:
+            raise TypeError(f"coeffs must be a contiguous host {cdt} tensor (F, Kt, Kp)")
+        for x in (phi, theta):
+            if x.dtype != torch.float64 or x.is_cuda or not x.is_contiguous():
+                raise TypeError("points must be contiguous host float64 tensors")
+        F, Kt, Kp = coeffs.shape
+        n = phi.numel()
+        if out is not None and (out.dtype != cdt or out.is_cuda or tuple(out.shape) != (F, n)
+                                or not out.is_contiguous()):
+            raise TypeError(f"out must be a contiguous host {cdt} tensor ({F}, {n})")
+        req = nufft2_request(code, F, Kt, Kp, float(eps), n, coeffs.data_ptr(), phi.data_ptr(),
+                             theta.data_ptr(), out.data_ptr() if out is not None else None,
+                             self.clock() if t_arrival is None else float(t_arrival))
+        st, ticket = nufft2_server_submit(self.handle, req)
+        _check(st, "nufft2_server_submit")
+        self._live[ticket] = (coeffs, phi, theta, out)
+        return ticket
+
+    def wait(self, ticket):
+        st, rs, lat = nufft2_server_wait(self.handle, ticket)
+        _check(st, "nufft2_server_wait")
+        self._live.pop(ticket, None)
+        return rs, lat
+
+    def drain(self):
+        _check(nufft2_server_drain(self.handle), "nufft2_server_drain")
+        self._live.clear()
+
+    def stats(self):
+        st, s = nufft2_server_stats(self.handle)
+        _check(st, "nufft2_server_stats")
+        return s.as_dict()
+
+    def destroy(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            nufft2_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

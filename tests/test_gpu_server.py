@@ -1,0 +1,125 @@
+"""Serving loop (nufft2_server_*): continuous batching of mixed requests.
+
+Each request's result must be the same alone and in the mix (bit-identical:
+a request always runs on a plan of its own key with its own buffers), and
+meet the oracle at the request's tolerance.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2605_01313_amd import nufft2  # noqa: F401  (fails loudly if not built)
+    return torch, torch.device("cuda:0")
+
+
+def make_requests(torch, n, seed):
+    """Mixed sizes, field counts and tolerances; pinned host tensors."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        K = int(rng.choice([31, 63, 127]))
+        F = int(rng.integers(1, 4))
+        prec = "fp64" if rng.random() < 0.3 else "fp32"
+        eps = 1e-12 if prec == "fp64" else 1e-6
+        P = int(rng.integers(500, 6000))
+        c = synth.random_complex(rng, (F, K, K)) * synth.envelope_algebraic(K, K, 1.5)[None]
+        phi = rng.uniform(-1.0, 2 * np.pi + 1.0, P)
+        theta = rng.uniform(-0.3, np.pi + 0.3, P)
+        cdt = torch.complex64 if prec == "fp32" else torch.complex128
+        reqs.append({
+            "prec": prec, "eps": eps, "c_np": c, "phi_np": phi, "theta_np": theta,
+            "coeffs": torch.from_numpy(c).to(cdt).pin_memory(),
+            "phi": torch.from_numpy(phi).pin_memory(), "theta": torch.from_numpy(theta).pin_memory(),
+            "out": torch.empty((F, P), dtype=cdt).pin_memory(),
+        })
+    return reqs
+
+
+def test_server_results_same_alone_and_in_the_mix(torch_dev, oracle_mod):
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Server
+    say("case server_mix")
+    reqs = make_requests(torch, 24, seed=5)
+    srv = Server(hbm_budget=2 << 30, max_inflight=6)
+    tickets = []
+    for i, r in enumerate(reqs):
+        tickets.append(srv.submit(r["prec"], r["coeffs"], r["phi"], r["theta"], r["eps"], out=r["out"]))
+        if i % 5 == 4:
+            time.sleep(0.002)          # some arrive while others are on the GPU
+    for t in tickets:
+        status, lat = srv.wait(t)
+        assert status == 0 and lat > 0
+    st = srv.stats()
+    say(f"  stats {st}")
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["max_inflight_seen"] >= 2          # requests overlapped on the device
+    mix = [r["out"].numpy().copy() for r in reqs]
+    srv.destroy()
+    # alone: a fresh server that runs one request at a time
+    alone = Server(hbm_budget=2 << 30, max_inflight=1)
+    for i, r in enumerate(reqs):
+        r["out"].zero_()
+        t = alone.submit(r["prec"], r["coeffs"], r["phi"], r["theta"], r["eps"], out=r["out"])
+        assert alone.wait(t)[0] == 0
+        assert np.array_equal(r["out"].numpy(), mix[i]), f"request {i} differs alone and in the mix"
+    assert alone.stats()["max_inflight_seen"] == 1
+    alone.destroy()
+    # and against the oracle
+    for i, r in enumerate(reqs[:8]):
+        ref = oracle_mod.dfs_eval(r["c_np"], r["phi_np"], r["theta_np"])
+        got = mix[i]
+        err = max(float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(ref.shape[0]))
+        assert err <= r["eps"], (i, r["prec"], err)
+
+
+def test_server_small_budget_queues_and_evicts(torch_dev):
+    """A budget of about two requests: everything completes, memory stays
+    within the budget, and idle plans are evicted for new keys."""
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Server
+    say("case server_budget")
+    reqs = make_requests(torch, 16, seed=6)
+    budget = 16 << 20
+    srv = Server(hbm_budget=budget, max_inflight=8)
+    tickets = [srv.submit(r["prec"], r["coeffs"], r["phi"], r["theta"], r["eps"], out=r["out"]) for r in reqs]
+    for t in tickets:
+        assert srv.wait(t)[0] == 0
+    st = srv.stats()
+    say(f"  stats {st}")
+    assert st["completed"] == len(reqs)
+    assert st["hbm_high_water"] <= budget
+    assert st["plans_evicted"] > 0
+    srv.destroy()
+
+
+def test_server_argument_errors(torch_dev):
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Nufft2Error, Server, nufft2
+    srv = Server(hbm_budget=64 << 20, max_inflight=2)
+    c = torch.zeros((1, 31, 31), dtype=torch.complex64)
+    x = torch.zeros(10, dtype=torch.float64)
+    with pytest.raises(Nufft2Error):
+        srv.submit("fp32", c, x, x, 1e-9)                   # eps below FP32 range
+    big = torch.zeros((3, 1023, 1023), dtype=torch.complex64)
+    with pytest.raises(Nufft2Error):
+        srv.submit("fp32", big, x, x, 1e-6)                 # footprint above the budget
+    req = nufft2.nufft2_request(1, 1, 31, 31, 1e-6, 0, c.data_ptr(), x.data_ptr(), x.data_ptr(), None, 0.0)
+    assert nufft2.nufft2_server_submit(srv.handle, req)[0] == nufft2.NUFFT2_ERR_ARG   # no points
+    assert nufft2.nufft2_server_wait(srv.handle, 999)[0] == nufft2.NUFFT2_ERR_ARG     # unknown ticket
+    srv.destroy()
