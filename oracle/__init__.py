@@ -13,6 +13,10 @@ Contents
                     oracle's own rounding at the largest sizes.
   * `std_to_exp` -- the map of eq. dfs_fourier_coeffs from standard-DFS
                     cos/sin coefficients to exp-form coefficients.
+  * `dfs_analysis` -- grid values on Grid [0] -> exp-form coefficients, in
+                    the paper's order: Fourier transform in phi, cosine /
+                    sine transforms in theta (section 4), then `std_to_exp`;
+                    the transforms are written as plain sums.
 """
 from __future__ import annotations
 
@@ -159,3 +163,64 @@ def std_to_exp(fc, fs):
                 put(n, -m, b)
                 put(-n, -m, -b)
     return ft
+
+
+def grid0_nodes(J):
+    """Grid [0] of section 3 with J latitudes: theta_i = (i + 1/2) pi / J
+    (i < J), phi_k = pi k / J (k < 2J)."""
+    theta = (np.arange(J) + 0.5) * np.pi / J
+    phi = np.arange(2 * J) * np.pi / J
+    return theta, phi
+
+
+def dfs_analysis(values):
+    """Exp-form DFS coefficients of fields sampled on Grid [0] (section 4).
+
+    values: real array [F][J][2J]; row i is colatitude theta_i, column k is
+    longitude phi_k (`grid0_nodes`).  Truncation N = M = J - 1.
+
+    Steps, as the paper orders them:
+      1. Fourier transform in phi of every row: a_m(theta_i), b_m(theta_i),
+         the cos(m phi) and sin(m phi) coefficients, m = 0 .. M.
+      2. In theta, for each m: the cosine transform (even m, basis
+         cos(n theta), n = 0 .. N) or the sine transform (odd m, basis
+         sin(n theta), n = 1 .. N) of a_m and b_m on the half-offset nodes.
+         This gives the standard-DFS coefficients fc[n, m], fs[n, m]
+         (eq. std_dfs).
+      3. `std_to_exp`: the map of eq. dfs_fourier_coeffs.
+    Both transforms are the discrete orthogonality sums of their bases on
+    these nodes, written out (no FFT).
+
+    Returns complex [F][2J-1][2J-1], centred (row a <-> n = a - (J-1)).
+    """
+    values = np.asarray(values, dtype=np.float64)
+    if values.ndim == 2:
+        values = values[None]
+    F, J, L = values.shape
+    if L != 2 * J:
+        raise ValueError("values must be [F][J][2J]")
+    theta, phi = grid0_nodes(J)
+    N = M = J - 1
+    m = np.arange(M + 1)
+    n = np.arange(N + 1)
+    # 1. phi: f(phi) = a_0 + sum_{m>=1} a_m cos(m phi) + b_m sin(m phi)
+    cos_pm = np.cos(np.outer(phi, m))            # [2J, M+1]
+    sin_pm = np.sin(np.outer(phi, m))
+    a = values @ cos_pm / J                      # [F, J, M+1]
+    a[..., 0] *= 0.5
+    b = values @ sin_pm / J
+    # 2. theta: g(theta) = sum_n c_n cos(n theta)  or  sum_{n>=1} s_n sin(n theta)
+    w_cos = np.full(N + 1, 2.0 / J)
+    w_cos[0] = 1.0 / J
+    proj_cos = w_cos[:, None] * np.cos(np.outer(n, theta))     # [N+1, J]
+    proj_sin = (2.0 / J) * np.sin(np.outer(n, theta))
+    proj_sin[0] = 0.0
+    even = (m % 2 == 0)[None, :]
+    out = np.empty((F, 2 * N + 1, 2 * M + 1), dtype=np.complex128)
+    for f in range(F):
+        fc = np.where(even, proj_cos @ a[f], proj_sin @ a[f])    # [N+1, M+1]
+        fs = np.where(even, proj_cos @ b[f], proj_sin @ b[f])
+        fs[:, 0] = 0.0
+        # 3. eq. dfs_fourier_coeffs
+        out[f] = std_to_exp(fc, fs)
+    return out
