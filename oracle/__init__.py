@@ -13,6 +13,9 @@ Contents
                     oracle's own rounding at the largest sizes.
   * `std_to_exp` -- the map of eq. dfs_fourier_coeffs from standard-DFS
                     cos/sin coefficients to exp-form coefficients.
+  * `rotation_pq`, `rotate_uv` -- the rotation Q of section 3 that expresses
+                    a vector at the departure point in the arrival point's
+                    local (east, north) frame.
   * `dfs_analysis` -- grid values on Grid [0] -> exp-form coefficients, in
                     the paper's order: Fourier transform in phi, cosine /
                     sine transforms in theta (section 4), then `std_to_exp`;
@@ -224,3 +227,30 @@ def dfs_analysis(values):
         # 3. eq. dfs_fourier_coeffs
         out[f] = std_to_exp(fc, fs)
     return out
+
+
+def rotation_pq(phi_a, theta_a, phi_d, theta_d):
+    """Entries p, q of the rotation Q = [[p, q], [-q, p]] of section 3 (after
+    eq. sslforceb), FP64: phi longitude, theta colatitude, A arrival, D
+    departure;
+
+        p = (sin th_A sin th_D + (1 + cos th_A cos th_D) cos(ph_A - ph_D)) / (1 + cos eta)
+        q = (cos th_A + cos th_D) sin(ph_A - ph_D) / (1 + cos eta)
+
+    with cos eta = r_A . r_D for the unit position vectors.  Undefined for
+    antipodal pairs (1 + cos eta = 0)."""
+    pa, ta, pd, td = (np.asarray(x, dtype=np.float64) for x in (phi_a, theta_a, phi_d, theta_d))
+    sa, ca, sd, cd = np.sin(ta), np.cos(ta), np.sin(td), np.cos(td)
+    dphi = pa - pd
+    cos_eta = sa * sd * np.cos(dphi) + ca * cd
+    den = 1.0 + cos_eta
+    p = (sa * sd + (1.0 + ca * cd) * np.cos(dphi)) / den
+    q = (ca + cd) * np.sin(dphi) / den
+    return p, q
+
+
+def rotate_uv(u, v, phi_a, theta_a, phi_d, theta_d):
+    """(u, v) at the departure points (east, north components) expressed at
+    the arrival points: (p u + q v, -q u + p v)."""
+    p, q = rotation_pq(phi_a, theta_a, phi_d, theta_d)
+    return p * u + q * v, -q * u + p * v

@@ -120,3 +120,48 @@ def test_numpy_fft_of_the_glide_doubled_torus():
             want[a + J - 1, b + J - 1] = G[a % (2 * J), b % (2 * J)]
     got = oracle.dfs_analysis(vals)[0]
     assert np.abs(got - want).max() < 1e-13
+
+
+# ---- the rotation Q of section 3 ---------------------------------------------
+def _frame(phi, th):
+    r = np.array([np.sin(th) * np.cos(phi), np.sin(th) * np.sin(phi), np.cos(th)])
+    east = np.array([-np.sin(phi), np.cos(phi), 0.0])
+    north = np.array([-np.cos(th) * np.cos(phi), -np.cos(th) * np.sin(phi), np.sin(th)])
+    return r, east, north
+
+
+def test_rotation_is_parallel_transport_along_the_great_circle():
+    """Geometry, not the formula: rotate the departure point's east and north
+    unit vectors about r_D x r_A by the angle between r_D and r_A (Rodrigues)
+    and read them in the arrival point's frame."""
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        pa, pd = rng.uniform(-7, 7, 2)
+        ta, td = rng.uniform(0.05, np.pi - 0.05, 2)
+        rA, eA, nA = _frame(pa, ta)
+        rD, eD, nD = _frame(pd, td)
+        axis = np.cross(rD, rA)
+        ang = np.arctan2(np.linalg.norm(axis), rD @ rA)
+        k = axis / np.linalg.norm(axis)
+
+        def R(x):
+            return x * np.cos(ang) + np.cross(k, x) * np.sin(ang) + k * (k @ x) * (1 - np.cos(ang))
+
+        Q = np.array([[eA @ R(eD), eA @ R(nD)], [nA @ R(eD), nA @ R(nD)]])
+        p, q = oracle.rotation_pq(pa, ta, pd, td)
+        assert np.allclose(Q, [[p, q], [-q, p]], atol=1e-12)
+
+
+def test_rotation_special_cases():
+    rng = np.random.default_rng(4)
+    pa, ta = rng.uniform(0, 2 * np.pi, 100), rng.uniform(0.1, 3.0, 100)
+    pd, td = pa + rng.uniform(-0.3, 0.3, 100), ta + rng.uniform(-0.3, 0.3, 100)
+    p, q = oracle.rotation_pq(pa, ta, pd, td)
+    assert np.allclose(p * p + q * q, 1.0, atol=1e-13)      # a rotation
+    p0, q0 = oracle.rotation_pq(pa, ta, pa, ta)                # no displacement
+    assert np.allclose(p0, 1.0) and np.allclose(q0, 0.0)
+    pm, qm = oracle.rotation_pq(pa, ta, pa, td)                # along a meridian
+    assert np.allclose(pm, 1.0) and np.allclose(qm, 0.0, atol=1e-15)
+    u, v = rng.standard_normal(100), rng.standard_normal(100)
+    ur, vr = oracle.rotate_uv(u, v, pa, ta, pd, td)
+    assert np.allclose(ur * ur + vr * vr, u * u + v * v)         # lengths kept
