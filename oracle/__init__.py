@@ -192,7 +192,10 @@ def dfs_analysis(values):
          (eq. std_dfs).
       3. `std_to_exp`: the map of eq. dfs_fourier_coeffs.
     Both transforms are the discrete orthogonality sums of their bases on
-    these nodes, written out (no FFT).
+    these nodes, written out (no FFT).  The trigonometric factors of the node
+    angles are taken at exactly reduced arguments: m phi_k = pi (m k mod 2J) / J
+    and n theta_i = pi (n (2i + 1) mod 4J) / (2J), so that their rounding does
+    not grow with m k or n i.
 
     Returns complex [F][2J-1][2J-1], centred (row a <-> n = a - (J-1)).
     """
@@ -202,21 +205,24 @@ def dfs_analysis(values):
     F, J, L = values.shape
     if L != 2 * J:
         raise ValueError("values must be [F][J][2J]")
-    theta, phi = grid0_nodes(J)
     N = M = J - 1
     m = np.arange(M + 1)
     n = np.arange(N + 1)
+    k = np.arange(2 * J)
+    i = np.arange(J)
     # 1. phi: f(phi) = a_0 + sum_{m>=1} a_m cos(m phi) + b_m sin(m phi)
-    cos_pm = np.cos(np.outer(phi, m))            # [2J, M+1]
-    sin_pm = np.sin(np.outer(phi, m))
+    arg_p = np.pi * (np.outer(k, m) % (2 * J)) / J            # m phi_k, [2J, M+1]
+    cos_pm = np.cos(arg_p)
+    sin_pm = np.sin(arg_p)
     a = values @ cos_pm / J                      # [F, J, M+1]
     a[..., 0] *= 0.5
     b = values @ sin_pm / J
     # 2. theta: g(theta) = sum_n c_n cos(n theta)  or  sum_{n>=1} s_n sin(n theta)
     w_cos = np.full(N + 1, 2.0 / J)
     w_cos[0] = 1.0 / J
-    proj_cos = w_cos[:, None] * np.cos(np.outer(n, theta))     # [N+1, J]
-    proj_sin = (2.0 / J) * np.sin(np.outer(n, theta))
+    arg_t = np.pi * (np.outer(n, 2 * i + 1) % (4 * J)) / (2 * J)   # n theta_i, [N+1, J]
+    proj_cos = w_cos[:, None] * np.cos(arg_t)
+    proj_sin = (2.0 / J) * np.sin(arg_t)
     proj_sin[0] = 0.0
     even = (m % 2 == 0)[None, :]
     out = np.empty((F, 2 * N + 1, 2 * M + 1), dtype=np.complex128)
