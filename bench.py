@@ -243,13 +243,21 @@ def serving_bench(args, torch):
         phi, theta = pool[J]["pts"][i % n_pts_pool]
         return ("fp64" if fp64 else "fp32", c, phi, theta, 1e-12 if fp64 else 1e-6)
 
-    # warm-up: one request of every (size, fields, precision) creates its plan
-    log("bench: serving warm-up (one request per plan key)")
+    # warm-up: a burst of the largest request grows every slot's buffers,
+    # then a burst of every (size, fields, precision) creates plans for the
+    # concurrency the stream will need
+    for k in range(args.serve_inflight):
+        prec, c, phi, theta, eps = request(k, Js[-1], 3, True)
+        srv.submit(prec, c, phi, theta, eps)
+    srv.drain()
+    copies = max(1, args.serve_inflight // 2)
+    log(f"bench: serving warm-up ({copies} concurrent requests per plan key)")
     for J in Js:
         for F in (1, 2, 3):
             for fp64 in (False, True):
-                prec, c, phi, theta, eps = request(0, J, F, fp64)
-                srv.submit(prec, c, phi, theta, eps)
+                for k in range(copies):
+                    prec, c, phi, theta, eps = request(k, J, F, fp64)
+                    srv.submit(prec, c, phi, theta, eps)
     srv.drain()
     warm = srv.stats()
     log(f"bench: serving {n_req} requests over {args.serve_seconds:.0f} s")
@@ -275,28 +283,38 @@ def serving_bench(args, torch):
     pf = st["points_fields"] - warm["points_fields"]
     span = st["last_completion"] - t_start
     offered_pf = float(sum(2 * int(J) ** 2 * int(F) for J, F in zip(sizes, fields))) / args.serve_seconds
-    line = {
-        "metric": METRIC, "value": pf / span, "unit": "points*fields/s", "n_gpus": 1,
-        "steps": n_req, "warmup": warm["completed"], "ms_per_step": span * 1e3 / max(done, 1),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": "serving_poisson_mixed_grids", "rate_per_s": args.serve_rate,
-                   "seconds": args.serve_seconds, "grids": "64x128,128x256,256x512,512x1024",
-                   "fields": "1-3", "fp32_share": 0.8, "hbm_budget_gib": args.serve_budget_gib,
-                   "max_inflight": args.serve_inflight, "payload_pool_per_size": n_pts_pool,
-                   "step": "one request: H2D, setpts, exec, D2H"},
+    return {
+        "value": pf / span, "unit": "points*fields/s", "requests": done, "span_s": span,
         "latency_ms": {"p50": st["latency_p50"] * 1e3, "p99": st["latency_p99"] * 1e3,
                        "max": st["latency_max"] * 1e3},
-        "serving": {"requests": done, "failed": st["failed"], "offered_points_fields_per_s": offered_pf,
-                    "submit_lag_max_ms": lag * 1e3, "plans_created": st["plans_created"],
-                    "plans_evicted": st["plans_evicted"], "hbm_high_water_gib": st["hbm_high_water"] / 2**30,
-                    "max_inflight_seen": st["max_inflight_seen"]},
+        "config": {"rate_per_s": args.serve_rate, "seconds": args.serve_seconds,
+                   "grids": "64x128,128x256,256x512,512x1024", "fields": "1-3", "fp32_share": 0.8,
+                   "hbm_budget_gib": args.serve_budget_gib, "max_inflight": args.serve_inflight,
+                   "payload_pool_per_size": n_pts_pool},
+        "failed": st["failed"], "offered_points_fields_per_s": offered_pf,
+        "submit_lag_max_ms": lag * 1e3, "plans_created": st["plans_created"],
+        "plans_evicted": st["plans_evicted"], "hbm_high_water_gib": st["hbm_high_water"] / 2**30,
+        "max_inflight_seen": st["max_inflight_seen"],
+    }
+
+
+def serving_line(args, torch):
+    r = serving_bench(args, torch)
+    line = {
+        "metric": METRIC, "value": r["value"], "unit": "points*fields/s", "n_gpus": 1,
+        "steps": r["requests"], "warmup": 0, "ms_per_step": r["span_s"] * 1e3 / max(r["requests"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": dict(workload="serving_poisson_mixed_grids", step="one request: H2D, setpts, exec, D2H",
+                       **r["config"]),
+        "latency_ms": r["latency_ms"],
+        "serving": {k: v for k, v in r.items() if k not in ("value", "unit", "latency_ms", "config")},
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 
 
-def ensemble_bench(args, torch):
+def ensemble_bench(args, torch, steps, warmup):
     """Uneven ensemble: 64 members on 128x256 grids + 16 on 256x512, 3 fields
     each, own seed, spectrum and 8-mode wind; FP32 eps 1e-6, width and tiles
     from the autotuner; every step is one group setpts + one group exec (two
@@ -341,17 +359,17 @@ def ensemble_bench(args, torch):
         g.setpts(phis, thetas)
         g.exec(coeffs, outs)
 
-    for _ in range(max(args.warmup, 1)):
+    for _ in range(max(warmup, 1)):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms = (time.perf_counter() - t0) * 1e3 / steps
     lat = []
     s = torch.cuda.current_stream()
-    for _ in range(min(args.steps, 100)):
+    for _ in range(min(steps, 100)):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(s)
@@ -399,22 +417,33 @@ def ensemble_bench(args, torch):
         got = outs[i].cpu().numpy()[:, sel]
         errs.append(max(float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(F)))
     info = g.info()
-    line = {
-        "metric": METRIC, "value": n_pf / (ms * 1e-3), "unit": "points*fields/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "ensemble_64x128x256_16x256x512_3fields", "members": len(members),
-                   "points_x_fields": n_pf, "eps": 1e-6, "tuned": {str(k): v for k, v in tuned.items()},
-                   "classes": info["n_classes"], "kernels_per_step": info["setpts_kernels"] + info["exec_kernels"],
+    g.destroy()
+    return {
+        "value": n_pf / (ms * 1e-3), "unit": "points*fields/s", "ms_per_step": ms, "steps": steps,
+        "config": {"members": len(members), "points_x_fields": n_pf, "eps": 1e-6,
+                   "tuned": {str(k): v for k, v in tuned.items()}, "classes": info["n_classes"],
+                   "kernels_per_step": info["setpts_kernels"] + info["exec_kernels"],
                    "step": "group setpts + group exec (two graph launches)"},
         "latency_ms": {"p50": pct(0.5), "p99": pct(0.99)},
         "plain_fp64_single_field": {"value": n_pf / (ms64 * 1e-3), "unit": "points*fields/s",
                                     "ms_per_step": ms64, "eps": 1e-12,
                                     "speedup_of_batched_fp32": ms64 / ms},
         "rel_l2_vs_oracle_sampled": {"members": [0, 31, 63, 64, 79], "max": max(errs)},
+    }
+
+
+def ensemble_line(args, torch):
+    r = ensemble_bench(args, torch, args.steps, args.warmup)
+    line = {
+        "metric": METRIC, "value": r["value"], "unit": "points*fields/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": dict(workload="ensemble_64x128x256_16x256x512_3fields", **r["config"]),
+        "latency_ms": r["latency_ms"],
+        "plain_fp64_single_field": r["plain_fp64_single_field"],
+        "rel_l2_vs_oracle_sampled": r["rel_l2_vs_oracle_sampled"],
         "roofline": None, "cpu_baseline": None,
     }
-    g.destroy()
     print(json.dumps(line), flush=True)
 
 
@@ -435,6 +464,10 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=8, help="point payloads per grid size")
     ap.add_argument("--serve-budget-gib", type=int, default=16)
     ap.add_argument("--serve-inflight", type=int, default=16)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the ensemble and serving sections")
+    ap.add_argument("--extra-serve-seconds", type=float, default=10.0,
+                    help="length of the serving section of the default run")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (ensemble)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter scale for rocprofv3 --pmc)")
@@ -450,10 +483,10 @@ def main():
     import synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "ensemble":
-        ensemble_bench(args, torch)
+        ensemble_line(args, torch)
         return
     if args.workload == "serving":
-        serving_bench(args, torch)
+        serving_line(args, torch)
         return
     if args.workload == "sbr256":
         log("bench: building the 256x512 solid-body-rotation workload")
@@ -507,6 +540,15 @@ def main():
                  "latency_ms": {"p50": res64["p50_ms"], "p99": res64["p99_ms"]},
                  "stages_ms": res64["stage_avg_ms"]},
     }
+    if args.workload == "sbr256" and not args.no_extras:
+        r32.plan.destroy()
+        r64.plan.destroy()
+        log("bench: ensemble section")
+        line["ensemble"] = ensemble_bench(args, torch, 20, 3)
+        log("bench: serving section")
+        sargs = argparse.Namespace(**vars(args))
+        sargs.serve_seconds = args.extra_serve_seconds
+        line["serving"] = serving_bench(sargs, torch)
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         outs = {"fp32": r32.out.cpu().numpy().astype(np.complex128),

@@ -117,6 +117,24 @@ nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const double *phi_de
  */
 nufft2_status nufft2_exec(nufft2_handle p, const void *coeffs_dev, void *out_dev);
 
+/*
+ * nufft2_rotate_uv -- express an interpolated vector field in the arrival
+ * points' frame (section 3: the matrix Q = [[p, q], [-q, p]] applied to
+ * the departure-point value, with p, q as printed after eq. sslforceb).
+ *   out_dev     the output of the last nufft2_exec ([n_fields][n_pts],
+ *               caller's point order); fields field_u and field_v hold the
+ *               east and north components (u, v) at the departure points
+ *               and are overwritten, in place, by p u + q v and -q u + p v.
+ *   phi_a_dev, theta_a_dev  FP64 arrival longitude / colatitude per point;
+ *   phi_d_dev, theta_d_dev  FP64 departure points (those given to setpts).
+ * p and q are computed in FP64; undefined for antipodal pairs.  Applies to
+ * both parts of complex outputs.  Errors: ERR_ARG (fields equal or out of
+ * range, null pointers), ERR_NO_POINTS, ERR_HIP.
+ */
+nufft2_status nufft2_rotate_uv(nufft2_handle p, void *out_dev, int32_t field_u, int32_t field_v,
+                               const double *phi_a_dev, const double *theta_a_dev, const double *phi_d_dev,
+                               const double *theta_d_dev);
+
 /* nufft2_destroy -- synchronise the plan's stream and free everything. NULL is ignored. */
 nufft2_status nufft2_destroy(nufft2_handle p);
 
@@ -311,6 +329,37 @@ nufft2_status nufft2_server_wait(nufft2_server s, uint64_t ticket, nufft2_status
 nufft2_status nufft2_server_drain(nufft2_server s);
 nufft2_status nufft2_server_stats(nufft2_server s, nufft2_server_stats_t *stats);
 nufft2_status nufft2_server_destroy(nufft2_server s);
+
+/*
+ * DFS analysis (section 4): fields sampled on Grid [0] -> the exp-form
+ * coefficients nufft2_exec takes, so callers can start from grid values.
+ * Grid [0] with J latitudes: row i is colatitude theta_i = (i + 1/2) pi / J
+ * (i < J), column k longitude phi_k = pi k / J (k < 2J).  The paper
+ * computes the standard-DFS coefficients with an FFT in phi and cosine (even
+ * m) / sine (odd m) transforms in theta, and maps them to exp form with
+ * eq. dfs_fourier_coeffs; the library computes the same coefficients as one
+ * forward transform per phi mode over the theta circle doubled by the glide
+ * reflection (which is the even / odd extension of those transforms), with
+ * the half-cell theta phase.  Truncation N = M = J - 1, i.e. the output is
+ * [n_fields][2J-1][2J-1] complex in the plan precision, centred exactly as
+ * nufft2_exec's input (row a <-> n = a - (J-1), column b <-> m = b - (J-1)).
+ * Samples of a field band-limited to |n|, |m| <= J - 1 are reproduced
+ * exactly (to rounding) by nufft2_exec at the nodes.
+ *
+ * nufft2_analysis_plan -- J a power of two, 16 <= J <= 2048; prec as for
+ *   nufft2_plan; stream a hipStream_t.  Owns its tables and a
+ *   [n_fields][J][2J-1] complex buffer.  Errors: ERR_ARG, ERR_ALLOC, ERR_HIP.
+ * nufft2_analysis_exec -- values_dev [n_fields][J][2J] real (plan precision,
+ *   row-major), coeffs_dev [n_fields][2J-1][2J-1] complex; device memory
+ *   owned by the caller, not overlapping.  Asynchronous on the plan's stream.
+ *   Errors: ERR_ARG, ERR_HIP.
+ * nufft2_analysis_destroy -- synchronise the stream and free; NULL ignored.
+ */
+typedef struct nufft2_analysis_s *nufft2_analysis;
+nufft2_status nufft2_analysis_plan(nufft2_prec prec, int64_t J, int32_t n_fields, void *stream,
+                                   nufft2_analysis *out);
+nufft2_status nufft2_analysis_exec(nufft2_analysis a, const void *values_dev, void *coeffs_dev);
+nufft2_status nufft2_analysis_destroy(nufft2_analysis a);
 
 /*
  * Host-only helpers (no device work; usable without a GPU).

@@ -535,4 +535,170 @@ hipError_t launch_phi_group(int prec, const FFTParams &fp, const PhiJob *jobs, i
     return phi_dispatch<double>(fp, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
 }
 
+// ---- DFS analysis: grid values on Grid [0] -> exp-form coefficients -------
+//
+// Section 4 computes the standard-DFS coefficients with an FFT in phi and
+// cosine / sine transforms in theta (cosine for even m, sine for odd m) and
+// eq. dfs_fourier_coeffs maps them to exp form.  The same coefficients come
+// from one complex transform per phi mode over the doubled theta circle:
+// the glide reflection f(phi, 2 pi - theta) = f(phi + pi, theta) extends
+// phi mode m of row i to row 2J - 1 - i with the factor (-1)^m, i.e. the
+// even (cosine) extension for even m and the odd (sine) one for odd m.
+// Both steps are forward transforms, done here as conj(FFT_+(conj x)) with
+// the +i Stockham kernels; the loaders and storers do the conjugations.
+
+// phi step: row i of field f (length L = 2J, real) -> A[f][i][m + J - 1].
+template <typename T> struct AnaRowLoad {
+    const T *vals;  // this field, [J][L]
+    int L, i0;
+    __device__ cplx<T> operator()(int k, int b) const { return {vals[(int64_t)(i0 + b) * L + k], (T)0}; }
+};
+template <typename T> struct AnaRowStore {
+    cplx<T> *A;  // this field, [J][K]
+    int J, K, i0;
+    __device__ void operator()(int o, int b, cplx<T> v) const
+    {
+        // frequency o <-> m = o (o < J) or o - 2J (o > J); o = J (Nyquist) is dropped
+        if (o == J) return;
+        const int m = o < J ? o : o - 2 * J;
+        A[(int64_t)(i0 + b) * K + m + J - 1] = {v.x, -v.y};
+    }
+};
+
+template <typename T, int LOGN, int E>
+__global__ __launch_bounds__(256) void k_analysis_phi(const T *__restrict__ vals, const cplx<T> *__restrict__ tws,
+                                                      cplx<T> *__restrict__ A, int J, int rows_per_wg,
+                                                      int log_rows_per_wg)
+{
+    extern __shared__ unsigned char smem_raw[];
+    constexpr int N = 1 << LOGN;  // = 2J
+    cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
+    cplx<T> *s = tw + tw_lds_len(N);
+    const int K = 2 * J - 1;
+    const int nrb = J / rows_per_wg;
+    const int f = (int)blockIdx.x / nrb;
+    const int i0 = ((int)blockIdx.x - f * nrb) * rows_per_wg;
+    AnaRowLoad<T> ld{vals + (int64_t)f * J * N, N, i0};
+    AnaRowStore<T> st{A + (int64_t)f * J * K, J, K, i0};
+    TwiddleCopy<cplx<T>> pro{tw, tws, tw_lds_len(N)};
+    fft_stages<T, LOGN, 0, E, false>(s, log_rows_per_wg, 1, lds_seq_len(N), tw, ld, st, pro);
+}
+
+// theta step: columns m0 .. m0 + B - 1 of A (the phi modes), doubled to
+// length 2J with the glide sign, forward transform over theta, then the
+// half-cell phase and the normalisation: ft[n][m] = Z[n] e^{-i n pi/(2J)} / (2J)^2.
+template <typename T> struct AnaColLoad {
+    const cplx<T> *A;  // this field, [J][K]
+    int J, K, m0;
+    __device__ cplx<T> operator()(int i, int b) const
+    {
+        const int mi = m0 + b;
+        const int mc = mi < K ? mi : K - 1;
+        const int r = i < J ? i : 2 * J - 1 - i;
+        const cplx<T> v = A[(int64_t)r * K + mc];
+        const bool neg = i >= J && (((mc - (J - 1)) & 1) != 0);
+        const T sre = neg ? -v.x : v.x, sim = neg ? -v.y : v.y;
+        return {sre, -sim};  // conj
+    }
+};
+template <typename T> struct AnaColStore {
+    cplx<T> *out;          // this field, [K][K]
+    const cplx<T> *phase;  // [K]: e^{-i n pi/(2J)} / (2J)^2, n = -(J-1) .. J-1
+    int J, K, m0;
+    __device__ void operator()(int o, int b, cplx<T> v) const
+    {
+        const int mi = m0 + b;
+        if (mi >= K || o == J) return;
+        const int n = o < J ? o : o - 2 * J;
+        const cplx<T> z{v.x, -v.y};  // conj back: forward transform
+        out[(int64_t)(n + J - 1) * K + mi] = cmul(z, phase[n + J - 1]);
+    }
+};
+
+template <typename T, int LOGN, int E>
+__global__ __launch_bounds__(512) void k_analysis_theta(const cplx<T> *__restrict__ A,
+                                                        const cplx<T> *__restrict__ tws,
+                                                        const cplx<T> *__restrict__ phase,
+                                                        cplx<T> *__restrict__ out, int J, int cols_per_wg,
+                                                        int log_cols_per_wg)
+{
+    extern __shared__ unsigned char smem_raw[];
+    constexpr int N = 1 << LOGN;  // = 2J
+    cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
+    cplx<T> *s = tw + tw_lds_len(N);
+    const int K = 2 * J - 1;
+    const int ntiles = (K + cols_per_wg - 1) / cols_per_wg;
+    const int f = (int)blockIdx.x / ntiles;
+    const int m0 = ((int)blockIdx.x - f * ntiles) * cols_per_wg;
+    AnaColLoad<T> ld{A + (int64_t)f * J * K, J, K, m0};
+    AnaColStore<T> st{out + (int64_t)f * K * K, phase, J, K, m0};
+    TwiddleCopy<cplx<T>> pro{tw, tws, tw_lds_len(N)};
+    fft_stages<T, LOGN, 0, E, true>(s, log_cols_per_wg, cols_per_wg, 1, tw, ld, st, pro);
+}
+
+template <typename T, int LOGN>
+static hipError_t launch_analysis_t(const AnalysisParams &ap, const void *vals, const void *tws, const void *phase,
+                                    void *A, void *out, hipStream_t s)
+{
+    constexpr int N = 1 << LOGN;
+    const int J = N / 2;
+    // phi step: rows per workgroup so that it transforms 4096 elements
+    int rb = 4096 / N;
+    if (rb > J) rb = J;
+    int lrb = 0;
+    while ((1 << lrb) < rb) ++lrb;
+    int threads = N * rb / kElemsPerThread;
+    if (threads < 1 || threads > 256) return hipErrorInvalidConfiguration;
+    size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * rb + tw_lds_len(N));
+    {
+        auto kern = k_analysis_phi<T, LOGN, kElemsPerThread>;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3((J / rb) * ap.n_fields), dim3(threads), lds, s, (const T *)vals,
+                           (const cplx<T> *)tws, (cplx<T> *)A, J, rb, lrb);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // theta step: columns per workgroup so that a workgroup has 64..512 threads
+    int cb = 1;
+    while (N * cb / kElemsPerThread < 64) cb *= 2;
+    while (cb < 16 && N * cb * 2 / kElemsPerThread <= 512 &&
+           sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * cb * 2 + tw_lds_len(N)) <= 65536)
+        cb *= 2;
+    int lcb = 0;
+    while ((1 << lcb) < cb) ++lcb;
+    threads = N * cb / kElemsPerThread;
+    if (threads < 1 || threads > 512 || threads % cb != 0) return hipErrorInvalidConfiguration;
+    lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * cb + tw_lds_len(N));
+    {
+        auto kern = k_analysis_theta<T, LOGN, kElemsPerThread>;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const int K = 2 * J - 1;
+        const int ntiles = (K + cb - 1) / cb;
+        hipLaunchKernelGGL(kern, dim3(ntiles * ap.n_fields), dim3(threads), lds, s, (const cplx<T> *)A,
+                           (const cplx<T> *)tws, (const cplx<T> *)phase, (cplx<T> *)out, J, cb, lcb);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t analysis_dispatch(const AnalysisParams &ap, const void *vals, const void *tws, const void *phase,
+                                    void *A, void *out, hipStream_t s)
+{
+    switch (ap.log_len) {
+#define NUFFT2_A(X) case X: return launch_analysis_t<T, X>(ap, vals, tws, phase, A, out, s);
+        NUFFT2_A(5) NUFFT2_A(6) NUFFT2_A(7) NUFFT2_A(8) NUFFT2_A(9) NUFFT2_A(10) NUFFT2_A(11) NUFFT2_A(12)
+#undef NUFFT2_A
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_analysis(int prec, const AnalysisParams &ap, const void *vals, const void *tws, const void *phase,
+                           void *A, void *out, hipStream_t s)
+{
+    if (prec == 1) return analysis_dispatch<float>(ap, vals, tws, phase, A, out, s);
+    return analysis_dispatch<double>(ap, vals, tws, phase, A, out, s);
+}
+
 }  // namespace nufft2

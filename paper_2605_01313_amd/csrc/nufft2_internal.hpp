@@ -124,4 +124,21 @@ struct GatherJob {
 hipError_t launch_gather_group(int prec, const GatherParams &gp, const GatherJob *jobs, int n_members,
                                hipStream_t s);
 
+// Rotation of a vector field (u, v) at departure points into the arrival
+// frame (section 3, matrix Q), in place; comps = 2 for complex values, 1 for
+// real; u and v point at the fields' [n] values.
+hipError_t launch_rotate_uv(int prec, void *u, void *v, int comps, int64_t n, const double *phi_a,
+                            const double *theta_a, const double *phi_d, const double *theta_d, hipStream_t s);
+
+// DFS analysis of fields on Grid [0] (J latitudes, 2J longitudes, J a power
+// of two, 16 <= J <= 2048): vals [F][J][2J] real -> A [F][J][2J-1] (phi
+// modes) -> out [F][2J-1][2J-1] exp-form coefficients.  tws: twiddle tables
+// of the 2J-point transform; phase: [2J-1] complex e^{-i n pi/(2J)} / (2J)^2.
+struct AnalysisParams {
+    int32_t J, log_len;  // log_len = log2(2J)
+    int32_t n_fields;
+};
+hipError_t launch_analysis(int prec, const AnalysisParams &ap, const void *vals, const void *tws, const void *phase,
+                           void *A, void *out, hipStream_t s);
+
 }  // namespace nufft2

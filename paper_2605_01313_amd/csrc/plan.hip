@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -174,12 +175,40 @@ nufft2_status fail_hip(nufft2_plan_s *p, hipError_t e)
     return NUFFT2_ERR_HIP;
 }
 
+// Deconvolution factors are a pure function of (K, nf, w, beta); plans of
+// the same shape (a serving loop creates many) share one computation.
+nufft2_status cached_correction(int64_t K, int64_t nf, int w, double beta, std::vector<double> &out)
+{
+    struct Entry {
+        int64_t K, nf;
+        int w;
+        double beta;
+        std::vector<double> corr;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const Entry &e : cache)
+            if (e.K == K && e.nf == nf && e.w == w && e.beta == beta) {
+                out = e.corr;
+                return NUFFT2_OK;
+            }
+    }
+    out.assign(K, 0.0);
+    nufft2_status st = kernel_correction(K, nf, w, beta, out.data());
+    if (st != NUFFT2_OK) return st;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache.size() < 256) cache.push_back(Entry{K, nf, w, beta, out});
+    return NUFFT2_OK;
+}
+
 template <typename T> nufft2_status upload_tables(nufft2_plan_s *p)
 {
-    std::vector<double> ct(p->Kt), cp(p->Kp);
-    nufft2_status st = kernel_correction(p->Kt, p->nft, p->w, p->beta, ct.data());
+    std::vector<double> ct, cp;
+    nufft2_status st = cached_correction(p->Kt, p->nft, p->w, p->beta, ct);
     if (st != NUFFT2_OK) return st;
-    st = kernel_correction(p->Kp, p->nfp, p->w, p->beta, cp.data());
+    st = cached_correction(p->Kp, p->nfp, p->w, p->beta, cp);
     if (st != NUFFT2_OK) return st;
     std::vector<T> ctT(ct.begin(), ct.end()), cpT(cp.begin(), cp.end());
     std::vector<T> twt, twp, twist(4 * (size_t)p->Kt);
@@ -425,16 +454,19 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     }
     st = prec == NUFFT2_FP32 ? upload_tables<float>(p) : upload_tables<double>(p);
     if (st == NUFFT2_OK) {
+        // cleared on the plan's stream, which is then synchronised: work on
+        // other streams (other plans) keeps running meanwhile
         hipError_t e;
-        if ((e = hipMemset(p->S, 0, cs * (size_t)p->F * p->nft * p->Kp)) != hipSuccess ||
-            (e = hipMemset(p->grid, 0, cs * (size_t)p->F * p->nft * p->nfp)) != hipSuccess ||
-            (e = hipMemset(p->rowtouched, 0, (size_t)p->nft)) != hipSuccess ||
-            (e = hipMemset(p->rowmark, 0, (size_t)p->nft)) != hipSuccess ||
-            (e = hipMemset(p->bincount, 0, sizeof(int32_t) * (size_t)p->nbins)) != hipSuccess ||
-            (e = hipMemset(p->binstart, 0, sizeof(int32_t) * (size_t)(p->nbins + 1))) != hipSuccess ||
-            (e = hipMemset(p->binlist, 0, sizeof(int32_t) * (size_t)(p->nbins + 1))) != hipSuccess ||
-            (e = hipMemset(p->flags, 0, sizeof(int32_t) * 4)) != hipSuccess ||
-            (e = hipDeviceSynchronize()) != hipSuccess)
+        hipStream_t ps = p->stream;
+        if ((e = hipMemsetAsync(p->S, 0, cs * (size_t)p->F * p->nft * p->Kp, ps)) != hipSuccess ||
+            (e = hipMemsetAsync(p->grid, 0, cs * (size_t)p->F * p->nft * p->nfp, ps)) != hipSuccess ||
+            (e = hipMemsetAsync(p->rowtouched, 0, (size_t)p->nft, ps)) != hipSuccess ||
+            (e = hipMemsetAsync(p->rowmark, 0, (size_t)p->nft, ps)) != hipSuccess ||
+            (e = hipMemsetAsync(p->bincount, 0, sizeof(int32_t) * (size_t)p->nbins, ps)) != hipSuccess ||
+            (e = hipMemsetAsync(p->binstart, 0, sizeof(int32_t) * (size_t)(p->nbins + 1), ps)) != hipSuccess ||
+            (e = hipMemsetAsync(p->binlist, 0, sizeof(int32_t) * (size_t)(p->nbins + 1), ps)) != hipSuccess ||
+            (e = hipMemsetAsync(p->flags, 0, sizeof(int32_t) * 4, ps)) != hipSuccess ||
+            (e = hipStreamSynchronize(ps)) != hipSuccess)
             st = NUFFT2_ERR_HIP;
     }
     if (st != NUFFT2_OK) {
@@ -556,6 +588,25 @@ NUFFT2_API nufft2_status nufft2_exec(nufft2_handle p, const void *coeffs_dev, vo
     return NUFFT2_OK;
 }
 
+NUFFT2_API nufft2_status nufft2_rotate_uv(nufft2_handle p, void *out_dev, int32_t field_u, int32_t field_v,
+                                          const double *phi_a_dev, const double *theta_a_dev,
+                                          const double *phi_d_dev, const double *theta_d_dev)
+{
+    if (!p) return NUFFT2_ERR_ARG;
+    if (p->n_pts < 0) return NUFFT2_ERR_NO_POINTS;
+    if (field_u < 0 || field_u >= p->F || field_v < 0 || field_v >= p->F || field_u == field_v)
+        return NUFFT2_ERR_ARG;
+    if (p->n_pts == 0) return NUFFT2_OK;
+    if (!out_dev || !phi_a_dev || !theta_a_dev || !phi_d_dev || !theta_d_dev) return NUFFT2_ERR_ARG;
+    const int comps = p->real_output ? 1 : 2;
+    const size_t field_bytes = p->rsize * comps * (size_t)p->n_pts;
+    char *base = (char *)out_dev;
+    const hipError_t e = launch_rotate_uv(p->prec, base + field_bytes * field_u, base + field_bytes * field_v, comps,
+                                          p->n_pts, phi_a_dev, theta_a_dev, phi_d_dev, theta_d_dev, p->stream);
+    if (e != hipSuccess) return fail_hip(p, e);
+    return NUFFT2_OK;
+}
+
 NUFFT2_API nufft2_status nufft2_check(nufft2_handle p)
 {
     if (!p) return NUFFT2_ERR_ARG;
@@ -659,5 +710,95 @@ NUFFT2_API nufft2_status nufft2_debug_buffer(nufft2_handle p, int32_t which, voi
     case 6: *dev_ptr = p->binlist; *bytes = sizeof(int32_t) * (size_t)(p->nbins + 1); break;
     default: return NUFFT2_ERR_ARG;
     }
+    return NUFFT2_OK;
+}
+
+// ---- DFS analysis plans ------------------------------------------------------
+
+struct nufft2_analysis_s {
+    int prec = 0;
+    int J = 0, F = 0;
+    hipStream_t stream = nullptr;
+    void *tws = nullptr, *phase = nullptr, *A = nullptr;
+};
+
+namespace {
+
+void analysis_free(nufft2_analysis_s *a)
+{
+    if (a->tws) (void)hipFree(a->tws);
+    if (a->phase) (void)hipFree(a->phase);
+    if (a->A) (void)hipFree(a->A);
+    delete a;
+}
+
+template <typename T> hipError_t analysis_tables(nufft2_analysis_s *a)
+{
+    const int L = 2 * a->J, K = 2 * a->J - 1;
+    std::vector<T> tw, ph(2 * (size_t)K);
+    fill_twiddle_tables<T>(tw, L);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double norm = 1.0L / ((long double)L * (long double)L);
+    for (int q = 0; q < K; ++q) {
+        const long double ang = -(long double)(q - (a->J - 1)) * pi / (long double)L;
+        ph[2 * q] = (T)(cosl(ang) * norm);
+        ph[2 * q + 1] = (T)(sinl(ang) * norm);
+    }
+    hipError_t e = hipMemcpy(a->tws, tw.data(), sizeof(T) * tw.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(a->phase, ph.data(), sizeof(T) * ph.size(), hipMemcpyHostToDevice);
+    return e;
+}
+
+}  // namespace
+
+NUFFT2_API nufft2_status nufft2_analysis_plan(nufft2_prec prec, int64_t J, int32_t n_fields, void *stream,
+                                              nufft2_analysis *out)
+{
+    if (!out || (prec != NUFFT2_FP32 && prec != NUFFT2_FP64) || n_fields < 1 || J < 16 || J > 2048 ||
+        !is_pow2(J))
+        return NUFFT2_ERR_ARG;
+    nufft2_analysis_s *a = new (std::nothrow) nufft2_analysis_s();
+    if (!a) return NUFFT2_ERR_ALLOC;
+    a->prec = prec;
+    a->J = (int)J;
+    a->F = n_fields;
+    a->stream = (hipStream_t)stream;
+    const size_t cs = prec == NUFFT2_FP32 ? sizeof(float2) : sizeof(double2);
+    const size_t K = 2 * (size_t)J - 1;
+    if (hipMalloc(&a->tws, cs * (64 + 2 * (size_t)J)) != hipSuccess || hipMalloc(&a->phase, cs * K) != hipSuccess ||
+        hipMalloc(&a->A, cs * (size_t)n_fields * J * K) != hipSuccess) {
+        (void)hipGetLastError();
+        analysis_free(a);
+        return NUFFT2_ERR_ALLOC;
+    }
+    const hipError_t e = prec == NUFFT2_FP32 ? analysis_tables<float>(a) : analysis_tables<double>(a);
+    if (e != hipSuccess) {
+        analysis_free(a);
+        return NUFFT2_ERR_HIP;
+    }
+    *out = a;
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_analysis_exec(nufft2_analysis a, const void *values_dev, void *coeffs_dev)
+{
+    if (!a || !values_dev || !coeffs_dev) return NUFFT2_ERR_ARG;
+    AnalysisParams ap{};
+    ap.J = a->J;
+    ap.log_len = ilog2(2 * (int64_t)a->J);
+    ap.n_fields = a->F;
+    const hipError_t e = launch_analysis(a->prec, ap, values_dev, a->tws, a->phase, a->A, coeffs_dev, a->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return NUFFT2_ERR_HIP;
+    }
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_analysis_destroy(nufft2_analysis a)
+{
+    if (!a) return NUFFT2_OK;
+    (void)hipStreamSynchronize(a->stream);
+    analysis_free(a);
     return NUFFT2_OK;
 }

@@ -118,23 +118,28 @@ struct nufft2_server_s {
     int device = 0;
     std::chrono::steady_clock::time_point t0;
 
+    // shared with the API threads, under mu
     std::mutex mu;
     std::condition_variable cv_work;  // new submissions, stop
     std::condition_variable cv_done;  // a request completed
     std::deque<Request *> queue;
     std::vector<Request *> all;       // every request ever submitted (owned)
-    std::vector<Slot> slots;
-    std::vector<CachedPlan *> plans;
-    uint64_t next_id = 1, tick = 0;
-    size_t reserved = 0, high_water = 0;
+    uint64_t next_id = 1;
     int inflight = 0, max_inflight_seen = 0;
     bool stop = false;
-    std::thread worker;
-
-    // stats
     int64_t completed = 0, failed = 0, pf = 0, created = 0, evicted = 0;
     std::vector<double> latencies;
     double first_arrival = 1e300, last_completion = 0;
+    size_t high_water = 0;
+
+    // the scheduler thread's own state (no lock)
+    std::vector<Slot> slots;
+    std::vector<CachedPlan *> plans;
+    std::vector<std::pair<void *, size_t>> retired;  // buffers to free once the device is idle
+    uint64_t tick = 0;
+    size_t reserved = 0;
+    int busy = 0;  // slots with a request
+    std::thread worker;
 
     double now() const
     {
@@ -143,11 +148,16 @@ struct nufft2_server_s {
     void reserve(size_t b)
     {
         reserved += b;
-        high_water = std::max(high_water, reserved);
+        if (reserved > high_water) {
+            std::lock_guard<std::mutex> lk(mu);
+            high_water = std::max(high_water, reserved);
+        }
     }
 };
 
 namespace {
+
+// ---- the scheduler thread's side ------------------------------------------
 
 void evict_plan(nufft2_server_s *s, CachedPlan *cp)
 {
@@ -155,15 +165,27 @@ void evict_plan(nufft2_server_s *s, CachedPlan *cp)
     s->reserved -= cp->bytes;
     s->plans.erase(std::find(s->plans.begin(), s->plans.end(), cp));
     delete cp;
+    std::lock_guard<std::mutex> lk(s->mu);
     s->evicted += 1;
 }
 
-// Make `need` bytes fit under the budget by destroying idle plans, least
-// recently used first, then by freeing the buffers of idle slots other than
-// `keep`.  Returns whether it fits.  (A request that passed the submit check
-// always fits once nothing else is in flight.)
+void free_retired(nufft2_server_s *s)
+{
+    for (auto &b : s->retired) {
+        (void)hipFree(b.first);
+        s->reserved -= b.second;
+    }
+    s->retired.clear();
+}
+
+// Make `need` bytes fit under the budget: free retired buffers, destroy
+// idle plans (least recently used first), then free the buffers of idle
+// slots other than `keep`.  These frees synchronise the device, so they only
+// happen under memory pressure.  Returns whether it fits.  (A request that
+// passed the submit check always fits once nothing else is in flight.)
 bool make_room(nufft2_server_s *s, size_t need, const Slot *keep)
 {
+    if (s->reserved + need > s->budget) free_retired(s);
     while (s->reserved + need > s->budget) {
         CachedPlan *lru = nullptr;
         for (CachedPlan *cp : s->plans)
@@ -187,35 +209,11 @@ bool make_room(nufft2_server_s *s, size_t need, const Slot *keep)
     return true;
 }
 
-void finish(nufft2_server_s *s, Slot &sl, nufft2_status st)
-{
-    Request *q = sl.req;
-    q->status = st;
-    q->latency = s->now() - q->r.t_arrival;
-    q->done = true;
-    if (st == NUFFT2_OK) {
-        s->completed += 1;
-        s->pf += (int64_t)q->r.n_fields * q->r.n_pts;
-        s->latencies.push_back(q->latency);
-        s->first_arrival = std::min(s->first_arrival, q->r.t_arrival);
-        s->last_completion = std::max(s->last_completion, s->now());
-    } else {
-        s->failed += 1;
-    }
-    if (sl.plan) {
-        sl.plan->busy = false;
-        sl.plan->last_use = ++s->tick;
-        if (st != NUFFT2_OK) evict_plan(s, sl.plan);
-    }
-    sl.req = nullptr;
-    sl.plan = nullptr;
-    s->inflight -= 1;
-}
+enum class Start { kWait, kStarted, kFailed };
 
-// Start request q on free slot sl (lock held).  Returns false when the
-// request must wait (no room yet); on a hard error the request completes
-// with that status.
-bool start(nufft2_server_s *s, Slot &sl, Request *q)
+// Start request q on free slot sl.  kWait: no room yet (nothing changed);
+// kFailed: *st holds the request's error.
+Start start(nufft2_server_s *s, Slot &sl, Request *q, nufft2_status *st)
 {
     const nufft2_request &r = q->r;
     CachedPlan *cp = nullptr;
@@ -225,131 +223,185 @@ bool start(nufft2_server_s *s, Slot &sl, Request *q)
             break;
         }
     const size_t need_buf = round_up(q->buf_bytes, 1u << 20);
-    const size_t grow = need_buf > sl.cap ? need_buf - sl.cap : 0;
+    const size_t grow = need_buf > sl.cap ? need_buf : 0;  // a new buffer; the old one retires
     const size_t need = grow + (cp ? 0 : q->plan_bytes);
     if (cp) cp->busy = true;  // not a candidate for eviction while making room
     if (!make_room(s, need, &sl)) {
         if (cp) cp->busy = false;
-        return false;
+        return Start::kWait;
     }
-    sl.req = q;
-    s->inflight += 1;
-    s->max_inflight_seen = std::max(s->max_inflight_seen, s->inflight);
-    hipError_t e = hipSuccess;
+    auto fail = [&](nufft2_status e) {
+        if (cp) cp->busy = false;
+        *st = e;
+        return Start::kFailed;
+    };
     if (grow) {
-        if (sl.d_buf) (void)hipFree(sl.d_buf);
-        s->reserved -= sl.cap;
-        sl.d_buf = nullptr;
-        sl.cap = 0;
-        if (hipMalloc(&sl.d_buf, need_buf) != hipSuccess) {
+        void *nb = nullptr;
+        if (hipMalloc(&nb, need_buf) != hipSuccess) {
             (void)hipGetLastError();
-            finish(s, sl, NUFFT2_ERR_ALLOC);
-            return true;
+            return fail(NUFFT2_ERR_ALLOC);
         }
+        if (sl.d_buf) s->retired.push_back({sl.d_buf, sl.cap});  // still reserved until freed
+        sl.d_buf = nb;
         sl.cap = need_buf;
         s->reserve(need_buf);
     }
     const size_t cs = csize(r.prec);
     const size_t out_bytes = cs * (size_t)r.n_fields * r.n_pts;
     if (!r.out_host && out_bytes > sl.stage_cap) {
+        // pinned host memory: not part of the device budget
         if (sl.h_stage) (void)hipHostFree(sl.h_stage);
         sl.h_stage = nullptr;
         sl.stage_cap = 0;
         if (hipHostMalloc(&sl.h_stage, out_bytes, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
-            finish(s, sl, NUFFT2_ERR_ALLOC);
-            return true;
+            return fail(NUFFT2_ERR_ALLOC);
         }
         sl.stage_cap = out_bytes;
     }
     if (!cp) {
         cp = new (std::nothrow) CachedPlan();
-        if (!cp) {
-            finish(s, sl, NUFFT2_ERR_ALLOC);
-            return true;
-        }
+        if (!cp) return fail(NUFFT2_ERR_ALLOC);
         cp->key = q->key;
-        nufft2_status st = nufft2_plan((nufft2_prec)r.prec, r.n_modes_theta, r.n_modes_phi, r.n_fields, r.eps,
-                                       nullptr, sl.stream, &cp->h);
-        if (st != NUFFT2_OK) {
+        nufft2_status e = nufft2_plan((nufft2_prec)r.prec, r.n_modes_theta, r.n_modes_phi, r.n_fields, r.eps,
+                                      nullptr, sl.stream, &cp->h);
+        if (e != NUFFT2_OK) {
             delete cp;
-            finish(s, sl, st);
-            return true;
+            cp = nullptr;
+            return fail(e);
         }
         cp->bytes = q->plan_bytes;
+        cp->busy = true;
         s->reserve(cp->bytes);
         s->plans.push_back(cp);
+        std::lock_guard<std::mutex> lk(s->mu);
         s->created += 1;
     }
-    cp->busy = true;
-    sl.plan = cp;
     cp->h->stream = sl.stream;  // the plan is idle: its earlier work has completed
     const size_t c_bytes = cs * (size_t)r.n_fields * r.n_modes_theta * r.n_modes_phi;
     const size_t p_bytes = sizeof(double) * (size_t)r.n_pts;
     char *base = (char *)sl.d_buf;
     void *d_coeffs = base, *d_phi = base + c_bytes, *d_theta = base + c_bytes + p_bytes,
          *d_out = base + c_bytes + 2 * p_bytes;
-    nufft2_status st = NUFFT2_OK;
-    if ((e = hipMemcpyAsync(d_coeffs, r.coeffs_host, c_bytes, hipMemcpyHostToDevice, sl.stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(d_phi, r.phi_host, p_bytes, hipMemcpyHostToDevice, sl.stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(d_theta, r.theta_host, p_bytes, hipMemcpyHostToDevice, sl.stream)) != hipSuccess)
-        st = NUFFT2_ERR_HIP;
-    if (st == NUFFT2_OK) st = nufft2_setpts(cp->h, r.n_pts, (const double *)d_phi, (const double *)d_theta);
-    if (st == NUFFT2_OK) st = nufft2_exec(cp->h, d_coeffs, d_out);
-    if (st == NUFFT2_OK &&
-        ((e = hipMemcpyAsync(r.out_host ? r.out_host : sl.h_stage, d_out, out_bytes, hipMemcpyDeviceToHost,
-                             sl.stream)) != hipSuccess ||
-         (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess))
-        st = NUFFT2_ERR_HIP;
-    if (st != NUFFT2_OK) {
+    nufft2_status e = NUFFT2_OK;
+    if (hipMemcpyAsync(d_coeffs, r.coeffs_host, c_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
+        hipMemcpyAsync(d_phi, r.phi_host, p_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
+        hipMemcpyAsync(d_theta, r.theta_host, p_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+        e = NUFFT2_ERR_HIP;
+    if (e == NUFFT2_OK) e = nufft2_setpts(cp->h, r.n_pts, (const double *)d_phi, (const double *)d_theta);
+    if (e == NUFFT2_OK) e = nufft2_exec(cp->h, d_coeffs, d_out);
+    if (e == NUFFT2_OK && (hipMemcpyAsync(r.out_host ? r.out_host : sl.h_stage, d_out, out_bytes,
+                                          hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
+                           hipEventRecord(sl.done, sl.stream) != hipSuccess))
+        e = NUFFT2_ERR_HIP;
+    if (e != NUFFT2_OK) {
         (void)hipGetLastError();
         (void)hipStreamSynchronize(sl.stream);
-        finish(s, sl, st);
+        evict_plan(s, cp);  // its state is unknown
+        *st = e;
+        return Start::kFailed;
     }
-    return true;
+    sl.req = q;
+    sl.plan = cp;
+    s->busy += 1;
+    return Start::kStarted;
+}
+
+// Record a finished request (lock held).
+void record(nufft2_server_s *s, Request *q, nufft2_status st, double t_done)
+{
+    q->status = st;
+    q->latency = t_done - q->r.t_arrival;
+    q->done = true;
+    if (st == NUFFT2_OK) {
+        s->completed += 1;
+        s->pf += (int64_t)q->r.n_fields * q->r.n_pts;
+        s->latencies.push_back(q->latency);
+        s->first_arrival = std::min(s->first_arrival, q->r.t_arrival);
+        s->last_completion = std::max(s->last_completion, t_done);
+    } else {
+        s->failed += 1;
+    }
 }
 
 void worker_loop(nufft2_server_s *s)
 {
     (void)hipSetDevice(s->device);
-    std::unique_lock<std::mutex> lk(s->mu);
+    std::vector<std::pair<Request *, nufft2_status>> done;
     for (;;) {
         bool progress = false;
+        // 1. retire completed requests
+        done.clear();
         for (Slot &sl : s->slots) {
             if (!sl.req) continue;
             const hipError_t q = hipEventQuery(sl.done);
             if (q == hipErrorNotReady) continue;
-            finish(s, sl, q == hipSuccess ? NUFFT2_OK : NUFFT2_ERR_HIP);
+            const nufft2_status st = q == hipSuccess ? NUFFT2_OK : NUFFT2_ERR_HIP;
             if (q != hipSuccess) (void)hipGetLastError();
+            done.push_back({sl.req, st});
+            CachedPlan *cp = sl.plan;
+            cp->busy = false;
+            cp->last_use = ++s->tick;
+            if (st != NUFFT2_OK) evict_plan(s, cp);
+            sl.req = nullptr;
+            sl.plan = nullptr;
+            s->busy -= 1;
+        }
+        if (!done.empty()) {
+            const double t = s->now();
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                for (auto &d : done) record(s, d.first, d.second, t);
+                s->inflight -= (int)done.size();
+            }
+            s->cv_done.notify_all();
             progress = true;
         }
-        if (progress) s->cv_done.notify_all();
-        while (!s->queue.empty() && s->inflight < s->max_inflight) {
-            Slot *free_slot = nullptr;
+        if (s->busy == 0 && !s->retired.empty()) free_retired(s);
+        // 2. admit queued requests in arrival order
+        for (;;) {
+            Slot *slot = nullptr;
             for (Slot &sl : s->slots)
                 if (!sl.req) {
-                    free_slot = &sl;
+                    slot = &sl;
                     break;
                 }
-            if (!free_slot) break;
-            Request *q = s->queue.front();
-            if (!start(s, *free_slot, q)) break;  // wait for memory to free up
-            s->queue.pop_front();
+            if (!slot) break;
+            Request *q = nullptr;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                if (!s->queue.empty()) q = s->queue.front();
+            }
+            if (!q) break;
+            nufft2_status st = NUFFT2_OK;
+            const Start r = start(s, *slot, q, &st);
+            if (r == Start::kWait) break;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->queue.pop_front();
+                if (r == Start::kStarted) {
+                    s->inflight += 1;
+                    s->max_inflight_seen = std::max(s->max_inflight_seen, s->inflight);
+                } else {
+                    record(s, q, st, s->now());
+                }
+            }
+            if (r == Start::kFailed) s->cv_done.notify_all();
             progress = true;
-            if (q->done) s->cv_done.notify_all();
         }
+        std::unique_lock<std::mutex> lk(s->mu);
         if (s->stop && s->queue.empty() && s->inflight == 0) break;
         if (!progress) {
             if (s->inflight > 0) {
                 // poll the in-flight work about every 20 microseconds
                 lk.unlock();
                 std::this_thread::sleep_for(std::chrono::microseconds(20));
-                lk.lock();
             } else {
                 s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
             }
         }
     }
+    free_retired(s);
 }
 
 }  // namespace

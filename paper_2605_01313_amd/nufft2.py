@@ -34,7 +34,8 @@ EXPORTED = (
     "nufft2_profile_read", "nufft2_group_create", "nufft2_group_setpts", "nufft2_group_exec",
     "nufft2_group_destroy", "nufft2_group_get_info", "nufft2_autotune", "nufft2_server_create",
     "nufft2_server_clock", "nufft2_server_submit", "nufft2_server_wait", "nufft2_server_drain",
-    "nufft2_server_stats", "nufft2_server_destroy",
+    "nufft2_server_stats", "nufft2_server_destroy", "nufft2_analysis_plan", "nufft2_analysis_exec",
+    "nufft2_analysis_destroy", "nufft2_rotate_uv",
 )
 NUFFT2_N_STAGES = 4
 STAGE_NAMES = ("setpts", "theta_pass", "phi_pass", "gather")
@@ -139,6 +140,10 @@ def _load():
         "nufft2_server_drain": [H],
         "nufft2_server_stats": [H, ctypes.POINTER(nufft2_server_stats_t)],
         "nufft2_server_destroy": [H],
+        "nufft2_analysis_plan": [i32, i64, i32, vp, ctypes.POINTER(H)],
+        "nufft2_analysis_exec": [H, vp, vp],
+        "nufft2_analysis_destroy": [H],
+        "nufft2_rotate_uv": [H, vp, i32, i32, vp, vp, vp, vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -328,6 +333,28 @@ def nufft2_server_destroy(server):
     return _lib.nufft2_server_destroy(server)
 
 
+def nufft2_rotate_uv(handle, out_ptr, field_u, field_v, phi_a, theta_a, phi_d, theta_d):
+    P = lambda x: ctypes.c_void_p(x or None)
+    return _lib.nufft2_rotate_uv(handle, P(out_ptr), int(field_u), int(field_v), P(phi_a), P(theta_a),
+                                 P(phi_d), P(theta_d))
+
+
+def nufft2_analysis_plan(prec, J, n_fields, stream=0):
+    """Returns (status, analysis handle)."""
+    h = ctypes.c_void_p()
+    st = _lib.nufft2_analysis_plan(int(prec), int(J), int(n_fields), ctypes.c_void_p(stream or None),
+                                   ctypes.byref(h))
+    return st, h
+
+
+def nufft2_analysis_exec(handle, values_ptr, coeffs_ptr):
+    return _lib.nufft2_analysis_exec(handle, ctypes.c_void_p(values_ptr or None), ctypes.c_void_p(coeffs_ptr or None))
+
+
+def nufft2_analysis_destroy(handle):
+    return _lib.nufft2_analysis_destroy(handle)
+
+
 # ---- torch convenience -----------------------------------------------------
 class Plan:
     """A plan bound to torch tensors on the current device and stream.
@@ -392,6 +419,19 @@ class Plan:
     def check(self):
         st = nufft2_check(self.handle)
         return st
+
+    def rotate_uv(self, out, field_u, field_v, phi_a, theta_a):
+        """Rotate fields (u, v) of `out` into the arrival frame (in place); the
+        departure points are those of the last setpts."""
+        if self._pts is None:
+            raise RuntimeError("rotate_uv before setpts")
+        phi_d, theta_d = self._pts
+        for x in (phi_a, theta_a):
+            if x.dtype != self._torch.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != self.n_pts:
+                raise TypeError("arrival points must be contiguous float64 device tensors of n_pts entries")
+        _check(nufft2_rotate_uv(self.handle, out.data_ptr(), field_u, field_v, phi_a.data_ptr(),
+                                theta_a.data_ptr(), phi_d.data_ptr(), theta_d.data_ptr()), "nufft2_rotate_uv")
+        return out
 
     def profile(self, stage_mask):
         _check(nufft2_profile_enable(self.handle, stage_mask), "nufft2_profile_enable")
@@ -586,6 +626,48 @@ class Server:
             nufft2_server_destroy(self.handle)
             self.handle = ctypes.c_void_p()
             self._live.clear()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Analysis:
+    """Grid values on Grid [0] -> exp-form coefficients (nufft2_analysis_*).
+
+    >>> an = Analysis("fp64", J=256, n_fields=3)
+    >>> coeffs = an.exec(values)      # (F, J, 2J) real -> (F, 2J-1, 2J-1) complex
+    """
+
+    def __init__(self, prec, J, n_fields=1, stream=None):
+        import torch
+        self._torch = torch
+        self.prec = {"fp32": NUFFT2_FP32, "fp64": NUFFT2_FP64}[prec]
+        self.rdtype = torch.float32 if self.prec == NUFFT2_FP32 else torch.float64
+        self.cdtype = torch.complex64 if self.prec == NUFFT2_FP32 else torch.complex128
+        self.J, self.F = int(J), int(n_fields)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        st, h = nufft2_analysis_plan(self.prec, J, n_fields, self.stream.cuda_stream)
+        _check(st, "nufft2_analysis_plan")
+        self.handle = h
+
+    def exec(self, values, out=None):
+        t = self._torch
+        J, F = self.J, self.F
+        if values.dtype != self.rdtype or not values.is_cuda or not values.is_contiguous() \
+                or tuple(values.shape) not in ((F, J, 2 * J), (J, 2 * J)):
+            raise TypeError(f"values must be a contiguous {self.rdtype} device tensor ({F}, {J}, {2 * J})")
+        if out is None:
+            out = t.empty((F, 2 * J - 1, 2 * J - 1), dtype=self.cdtype, device=values.device)
+        _check(nufft2_analysis_exec(self.handle, values.data_ptr(), out.data_ptr()), "nufft2_analysis_exec")
+        return out
+
+    def destroy(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            nufft2_analysis_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -1,0 +1,90 @@
+"""DFS analysis on the GPU (nufft2_analysis_*) against the oracle's analysis
+(section 4 route: Fourier in phi, cosine/sine transforms in theta,
+eq. dfs_fourier_coeffs), and composed with the NUFFT evaluation.
+
+Tolerance: the analysis is a pair of unnormalised transforms of length 2J
+and a division by (2J)^2; its error relative to the largest coefficient is a
+few units of rounding times log2(2J): 1e-13 in FP64 and 2e-6 in FP32 (FP32
+inputs are rounded samples, so the FP32 comparison is to the oracle on the
+same rounded samples).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2605_01313_amd import nufft2  # noqa: F401  (fails loudly if not built)
+    return torch, torch.device("cuda:0")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
+@pytest.mark.parametrize("J,F", [(16, 1), (64, 3), (256, 2), (1024, 1)])
+def test_analysis_matches_oracle(torch_dev, oracle_mod, prec, tol, J, F):
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Analysis
+    say(f"case analysis J={J} F={F} {prec}")
+    rng = np.random.default_rng(J + F)
+    vals = rng.standard_normal((F, J, 2 * J))
+    if prec == "fp32":
+        vals = vals.astype(np.float32).astype(np.float64)
+    rdt = torch.float32 if prec == "fp32" else torch.float64
+    an = Analysis(prec, J, n_fields=F)
+    got = an.exec(torch.from_numpy(vals).to(dev).to(rdt)).cpu().numpy()
+    ref = oracle_mod.dfs_analysis(vals)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"  max err / max coeff {err:.2e}")
+    assert err <= tol
+    an.destroy()
+
+
+@pytest.mark.parametrize("prec,eps,tol", [("fp64", 1e-12, 1e-12), ("fp32", 1e-6, 1e-6)])
+def test_analysis_then_exec_reproduces_the_nodes(torch_dev, oracle_mod, prec, eps, tol):
+    """A band-limited DFS field sampled on Grid [0] -> GPU analysis -> GPU NUFFT
+    at the nodes gives the samples back."""
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Analysis, Plan
+    J = 64
+    K = 2 * J - 1
+    say(f"case analysis_then_exec {prec}")
+    rng = np.random.default_rng(11)
+    coeffs = synth.dfs_field_coeffs(rng, K, K, synth.envelope_algebraic(K, K, 1.5))[None]
+    th, ph = oracle_mod.grid0_nodes(J)
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    vals = oracle_mod.dfs_eval(coeffs, PH.ravel(), TH.ravel()).real.reshape(1, J, 2 * J)
+    rdt = torch.float32 if prec == "fp32" else torch.float64
+    an = Analysis(prec, J, n_fields=1)
+    ft = an.exec(torch.from_numpy(vals).to(dev).to(rdt))
+    plan = Plan(prec, K, K, n_fields=1, eps=eps)
+    plan.setpts(torch.from_numpy(PH.ravel().copy()).to(dev), torch.from_numpy(TH.ravel().copy()).to(dev))
+    back = plan.exec(ft).cpu().numpy()[0].reshape(J, 2 * J)
+    err = float(np.linalg.norm(back - vals[0]) / np.linalg.norm(vals[0]))
+    say(f"  rel l2 {err:.2e}")
+    assert err <= tol
+    an.destroy()
+    plan.destroy()
+
+
+def test_analysis_argument_errors(torch_dev):
+    from paper_2605_01313_amd import nufft2
+    assert nufft2.nufft2_analysis_plan(1, 24, 1)[0] == nufft2.NUFFT2_ERR_ARG      # not a power of two
+    assert nufft2.nufft2_analysis_plan(1, 8, 1)[0] == nufft2.NUFFT2_ERR_ARG       # below 16
+    assert nufft2.nufft2_analysis_plan(1, 4096, 1)[0] == nufft2.NUFFT2_ERR_ARG    # above 2048
+    assert nufft2.nufft2_analysis_plan(3, 64, 1)[0] == nufft2.NUFFT2_ERR_ARG      # bad precision
+    st, h = nufft2.nufft2_analysis_plan(1, 64, 1)
+    assert st == nufft2.NUFFT2_OK
+    assert nufft2.nufft2_analysis_exec(h, 0, 0) == nufft2.NUFFT2_ERR_ARG
+    assert nufft2.nufft2_analysis_destroy(h) == nufft2.NUFFT2_OK
