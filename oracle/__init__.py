@@ -20,6 +20,9 @@ Contents
                     the paper's order: Fourier transform in phi, cosine /
                     sine transforms in theta (section 4), then `std_to_exp`;
                     the transforms are written as plain sums.
+  * `pr_to_std`, `std_to_pr`, `exp_to_std`, `zonal_cutoff`, `zonal_filter`
+                 -- the partial-regularity expansion and the zonal filter of
+                    section 4 (`partial_regularity.py`).
 """
 from __future__ import annotations
 
@@ -260,3 +263,9 @@ def rotate_uv(u, v, phi_a, theta_a, phi_d, theta_d):
     the arrival points: (p u + q v, -q u + p v)."""
     p, q = rotation_pq(phi_a, theta_a, phi_d, theta_d)
     return p * u + q * v, -q * u + p * v
+
+
+from .partial_regularity import (  # noqa: E402,F401
+    exp_to_std, normal_system, pr_range, pr_to_std, std_to_pr, std_weights,
+    zonal_cutoff, zonal_filter, zonal_limit,
+)
