@@ -362,6 +362,57 @@ nufft2_status nufft2_analysis_exec(nufft2_analysis a, const void *values_dev, vo
 nufft2_status nufft2_analysis_destroy(nufft2_analysis a);
 
 /*
+ * nufft2_analysis_set_zonal_filter -- the zonal filter of section 4 for the
+ * following nufft2_analysis_exec calls: at Grid [0] colatitude theta_i the
+ * longitudinal wavenumbers m > M_zf(theta_i) = min(M, M0 + M sin theta_i),
+ * M = J - 1, are removed from the samples before the theta transforms (the
+ * same as filtering the grid values row by row first).  The paper uses
+ * M0 = 20.  M0 < 0 turns the filter off (the default).  Synchronises the
+ * plan's stream.  Errors: ERR_ARG (null handle), ERR_HIP.
+ */
+nufft2_status nufft2_analysis_set_zonal_filter(nufft2_analysis a, int32_t M0);
+
+/*
+ * Partial-regularity DFS expansion (section 4, eq. pr_dfs).  Column m of
+ * the basis multiplies cos(m phi) and sin(m phi) by
+ *   m = 0: cos(n theta), n = 0..N;          m = 1: sin(theta) cos(n theta), n = 0..N-1;
+ *   even m >= 2: sin(theta) sin(n theta), n = 1..N-1;
+ *   odd m >= 3: sin^2(theta) sin(n theta), n = 1..N-2.
+ * Layouts (device memory owned by the caller, not overlapping):
+ *   coeffs  [n_fields][2N+1][2M+1] complex in the plan precision, exp form
+ *           (eq. std_dfs_exp), centred exactly as nufft2_exec's input with
+ *           K_theta = 2N+1, K_phi = 2M+1 (and as nufft2_analysis_exec's output
+ *           with N = M = J - 1);
+ *   pr      [n_fields][2][N+1][M+1] real in the plan precision: [f][0][n][m]
+ *           multiplies cos(m phi), [f][1][n][m] sin(m phi); entries outside a
+ *           column's range are written as zero and ignored on input.
+ *
+ * nufft2_pr_plan -- 5 <= N, M <= 2047, 1 <= n_fields <= 64; stream a
+ *   hipStream_t.  Factors the four per-class normal matrices on the host and
+ *   owns them plus an FP64 work buffer of 16 (N+1)(M+1) n_fields bytes.
+ *   Errors: ERR_ARG, ERR_ALLOC, ERR_HIP.
+ * nufft2_pr_project -- least-squares projection (section 4): reads coeffs as
+ *   standard coefficients (the least-squares inverse of
+ *   eq. dfs_fourier_coeffs, exact for real DFS fields) and writes the pr
+ *   coefficients whose residual is orthogonal to every basis function of
+ *   its column (the printed conditions; tridiagonal and pentadiagonal
+ *   systems per column).  Computed in FP64 for both precisions.
+ * nufft2_pr_synthesize -- pr coefficients -> exp-form coefficients (the
+ *   conversion after eq. std_dfs, then eq. dfs_fourier_coeffs), computed in
+ *   FP64 and rounded once.  For even m >= 2 the standard n = 0 coefficient
+ *   is f_{1,m} / 2 (the constant term of sin(theta)^2; the printed 0 would
+ *   not vanish at the poles).
+ * Both are asynchronous on the plan's stream.  Errors: ERR_ARG, ERR_HIP.
+ * nufft2_pr_destroy -- synchronise the stream and free; NULL ignored.
+ */
+typedef struct nufft2_pr_s *nufft2_pr;
+nufft2_status nufft2_pr_plan(nufft2_prec prec, int64_t N, int64_t M, int32_t n_fields, void *stream,
+                             nufft2_pr *out);
+nufft2_status nufft2_pr_project(nufft2_pr h, const void *coeffs_dev, void *pr_dev);
+nufft2_status nufft2_pr_synthesize(nufft2_pr h, const void *pr_dev, void *coeffs_dev);
+nufft2_status nufft2_pr_destroy(nufft2_pr h);
+
+/*
  * Host-only helpers (no device work; usable without a GPU).
  *
  * nufft2_kernel_params -- the width and shape the plan would choose for eps

@@ -553,22 +553,26 @@ template <typename T> struct AnaRowLoad {
     int L, i0;
     __device__ cplx<T> operator()(int k, int b) const { return {vals[(int64_t)(i0 + b) * L + k], (T)0}; }
 };
+// The zonal filter of section 4, when on (cut != nullptr), keeps at row i
+// only the wavenumbers |m| <= cut[i] (the integer part of M_zf(theta_i)).
 template <typename T> struct AnaRowStore {
     cplx<T> *A;  // this field, [J][K]
+    const int32_t *cut;
     int J, K, i0;
     __device__ void operator()(int o, int b, cplx<T> v) const
     {
         // frequency o <-> m = o (o < J) or o - 2J (o > J); o = J (Nyquist) is dropped
         if (o == J) return;
         const int m = o < J ? o : o - 2 * J;
-        A[(int64_t)(i0 + b) * K + m + J - 1] = {v.x, -v.y};
+        const bool keep = !cut || (m < 0 ? -m : m) <= cut[i0 + b];
+        A[(int64_t)(i0 + b) * K + m + J - 1] = keep ? cplx<T>{v.x, -v.y} : cplx<T>{(T)0, (T)0};
     }
 };
 
 template <typename T, int LOGN, int E>
 __global__ __launch_bounds__(256) void k_analysis_phi(const T *__restrict__ vals, const cplx<T> *__restrict__ tws,
-                                                      cplx<T> *__restrict__ A, int J, int rows_per_wg,
-                                                      int log_rows_per_wg)
+                                                      const int32_t *__restrict__ cut, cplx<T> *__restrict__ A,
+                                                      int J, int rows_per_wg, int log_rows_per_wg)
 {
     extern __shared__ unsigned char smem_raw[];
     constexpr int N = 1 << LOGN;  // = 2J
@@ -579,7 +583,7 @@ __global__ __launch_bounds__(256) void k_analysis_phi(const T *__restrict__ vals
     const int f = (int)blockIdx.x / nrb;
     const int i0 = ((int)blockIdx.x - f * nrb) * rows_per_wg;
     AnaRowLoad<T> ld{vals + (int64_t)f * J * N, N, i0};
-    AnaRowStore<T> st{A + (int64_t)f * J * K, J, K, i0};
+    AnaRowStore<T> st{A + (int64_t)f * J * K, cut, J, K, i0};
     TwiddleCopy<cplx<T>> pro{tw, tws, tw_lds_len(N)};
     fft_stages<T, LOGN, 0, E, false>(s, log_rows_per_wg, 1, lds_seq_len(N), tw, ld, st, pro);
 }
@@ -655,7 +659,7 @@ static hipError_t launch_analysis_t(const AnalysisParams &ap, const void *vals, 
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, dim3((J / rb) * ap.n_fields), dim3(threads), lds, s, (const T *)vals,
-                           (const cplx<T> *)tws, (cplx<T> *)A, J, rb, lrb);
+                           (const cplx<T> *)tws, ap.zonal_cut, (cplx<T> *)A, J, rb, lrb);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -137,6 +137,7 @@ hipError_t launch_rotate_uv(int prec, void *u, void *v, int comps, int64_t n, co
 struct AnalysisParams {
     int32_t J, log_len;  // log_len = log2(2J)
     int32_t n_fields;
+    const int32_t *zonal_cut;  // [J] kept |m| per row (device), or nullptr: no zonal filter
 };
 hipError_t launch_analysis(int prec, const AnalysisParams &ap, const void *vals, const void *tws, const void *phase,
                            void *A, void *out, hipStream_t s);

@@ -720,6 +720,8 @@ struct nufft2_analysis_s {
     int J = 0, F = 0;
     hipStream_t stream = nullptr;
     void *tws = nullptr, *phase = nullptr, *A = nullptr;
+    int32_t *cut = nullptr;  // zonal filter: kept |m| per row
+    bool zonal = false;
 };
 
 namespace {
@@ -729,6 +731,7 @@ void analysis_free(nufft2_analysis_s *a)
     if (a->tws) (void)hipFree(a->tws);
     if (a->phase) (void)hipFree(a->phase);
     if (a->A) (void)hipFree(a->A);
+    if (a->cut) (void)hipFree(a->cut);
     delete a;
 }
 
@@ -766,7 +769,8 @@ NUFFT2_API nufft2_status nufft2_analysis_plan(nufft2_prec prec, int64_t J, int32
     const size_t cs = prec == NUFFT2_FP32 ? sizeof(float2) : sizeof(double2);
     const size_t K = 2 * (size_t)J - 1;
     if (hipMalloc(&a->tws, cs * (64 + 2 * (size_t)J)) != hipSuccess || hipMalloc(&a->phase, cs * K) != hipSuccess ||
-        hipMalloc(&a->A, cs * (size_t)n_fields * J * K) != hipSuccess) {
+        hipMalloc(&a->A, cs * (size_t)n_fields * J * K) != hipSuccess ||
+        hipMalloc(&a->cut, sizeof(int32_t) * (size_t)J) != hipSuccess) {
         (void)hipGetLastError();
         analysis_free(a);
         return NUFFT2_ERR_ALLOC;
@@ -787,11 +791,40 @@ NUFFT2_API nufft2_status nufft2_analysis_exec(nufft2_analysis a, const void *val
     ap.J = a->J;
     ap.log_len = ilog2(2 * (int64_t)a->J);
     ap.n_fields = a->F;
+    ap.zonal_cut = a->zonal ? a->cut : nullptr;
     const hipError_t e = launch_analysis(a->prec, ap, values_dev, a->tws, a->phase, a->A, coeffs_dev, a->stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return NUFFT2_ERR_HIP;
     }
+    return NUFFT2_OK;
+}
+
+// Zonal filter (section 4): M_zf(theta_i) = min(M, M0 + M sin theta_i) with
+// M = J - 1 at the Grid [0] colatitudes; row i keeps |m| <= floor(M_zf).
+NUFFT2_API nufft2_status nufft2_analysis_set_zonal_filter(nufft2_analysis a, int32_t M0)
+{
+    if (!a) return NUFFT2_ERR_ARG;
+    if (M0 < 0) {
+        a->zonal = false;
+        return NUFFT2_OK;
+    }
+    const double pi = 3.14159265358979323846;
+    const int M = a->J - 1;
+    std::vector<int32_t> cut(a->J);
+    for (int i = 0; i < a->J; ++i) {
+        const double theta = ((double)i + 0.5) * pi / (double)a->J;
+        double lim = (double)M0 + (double)M * sin(theta);
+        if (lim > (double)M) lim = (double)M;
+        cut[i] = (int32_t)floor(lim);
+    }
+    // ordered after earlier work on the plan's stream that reads the table
+    if (hipStreamSynchronize(a->stream) != hipSuccess ||
+        hipMemcpy(a->cut, cut.data(), sizeof(int32_t) * cut.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return NUFFT2_ERR_HIP;
+    }
+    a->zonal = true;
     return NUFFT2_OK;
 }
 

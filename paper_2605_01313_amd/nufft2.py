@@ -35,7 +35,8 @@ EXPORTED = (
     "nufft2_group_destroy", "nufft2_group_get_info", "nufft2_autotune", "nufft2_server_create",
     "nufft2_server_clock", "nufft2_server_submit", "nufft2_server_wait", "nufft2_server_drain",
     "nufft2_server_stats", "nufft2_server_destroy", "nufft2_analysis_plan", "nufft2_analysis_exec",
-    "nufft2_analysis_destroy", "nufft2_rotate_uv",
+    "nufft2_analysis_destroy", "nufft2_rotate_uv", "nufft2_analysis_set_zonal_filter", "nufft2_pr_plan",
+    "nufft2_pr_project", "nufft2_pr_synthesize", "nufft2_pr_destroy",
 )
 NUFFT2_N_STAGES = 4
 STAGE_NAMES = ("setpts", "theta_pass", "phi_pass", "gather")
@@ -144,6 +145,11 @@ def _load():
         "nufft2_analysis_exec": [H, vp, vp],
         "nufft2_analysis_destroy": [H],
         "nufft2_rotate_uv": [H, vp, i32, i32, vp, vp, vp, vp],
+        "nufft2_analysis_set_zonal_filter": [H, i32],
+        "nufft2_pr_plan": [i32, i64, i64, i32, vp, ctypes.POINTER(H)],
+        "nufft2_pr_project": [H, vp, vp],
+        "nufft2_pr_synthesize": [H, vp, vp],
+        "nufft2_pr_destroy": [H],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -353,6 +359,30 @@ def nufft2_analysis_exec(handle, values_ptr, coeffs_ptr):
 
 def nufft2_analysis_destroy(handle):
     return _lib.nufft2_analysis_destroy(handle)
+
+
+def nufft2_analysis_set_zonal_filter(handle, M0):
+    return _lib.nufft2_analysis_set_zonal_filter(handle, int(M0))
+
+
+def nufft2_pr_plan(prec, N, M, n_fields, stream=0):
+    """Returns (status, partial-regularity plan handle)."""
+    h = ctypes.c_void_p()
+    st = _lib.nufft2_pr_plan(int(prec), int(N), int(M), int(n_fields), ctypes.c_void_p(stream or None),
+                             ctypes.byref(h))
+    return st, h
+
+
+def nufft2_pr_project(handle, coeffs_ptr, pr_ptr):
+    return _lib.nufft2_pr_project(handle, ctypes.c_void_p(coeffs_ptr or None), ctypes.c_void_p(pr_ptr or None))
+
+
+def nufft2_pr_synthesize(handle, pr_ptr, coeffs_ptr):
+    return _lib.nufft2_pr_synthesize(handle, ctypes.c_void_p(pr_ptr or None), ctypes.c_void_p(coeffs_ptr or None))
+
+
+def nufft2_pr_destroy(handle):
+    return _lib.nufft2_pr_destroy(handle)
 
 
 # ---- torch convenience -----------------------------------------------------
@@ -653,6 +683,10 @@ class Analysis:
         _check(st, "nufft2_analysis_plan")
         self.handle = h
 
+    def set_zonal_filter(self, M0=20):
+        """Zonal filter of section 4 on the following execs (M0 < 0: off)."""
+        _check(nufft2_analysis_set_zonal_filter(self.handle, M0), "nufft2_analysis_set_zonal_filter")
+
     def exec(self, values, out=None):
         t = self._torch
         J, F = self.J, self.F
@@ -667,6 +701,61 @@ class Analysis:
     def destroy(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             nufft2_analysis_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class PartialRegularity:
+    """Partial-regularity DFS expansion (nufft2_pr_*): exp-form coefficients
+    <-> pr coefficients.
+
+    >>> pr = PartialRegularity("fp64", N=255, M=255, n_fields=3)
+    >>> x = pr.project(coeffs)          # (F, 2N+1, 2M+1) complex -> (F, 2, N+1, M+1) real
+    >>> c = pr.synthesize(x)            # back to exp form (the projection of coeffs)
+    """
+
+    def __init__(self, prec, N, M, n_fields=1, stream=None):
+        import torch
+        self._torch = torch
+        self.prec = {"fp32": NUFFT2_FP32, "fp64": NUFFT2_FP64}[prec]
+        self.rdtype = torch.float32 if self.prec == NUFFT2_FP32 else torch.float64
+        self.cdtype = torch.complex64 if self.prec == NUFFT2_FP32 else torch.complex128
+        self.N, self.M, self.F = int(N), int(M), int(n_fields)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        st, h = nufft2_pr_plan(self.prec, N, M, n_fields, self.stream.cuda_stream)
+        _check(st, "nufft2_pr_plan")
+        self.handle = h
+
+    def _want(self, x, dtype, shape, what):
+        if x.dtype != dtype or not x.is_cuda or not x.is_contiguous() or tuple(x.shape) != shape:
+            raise TypeError(f"{what} must be a contiguous {dtype} device tensor {shape}")
+
+    def project(self, coeffs, out=None):
+        N, M, F = self.N, self.M, self.F
+        self._want(coeffs, self.cdtype, (F, 2 * N + 1, 2 * M + 1), "coeffs")
+        if out is None:
+            out = self._torch.empty((F, 2, N + 1, M + 1), dtype=self.rdtype, device=coeffs.device)
+        self._want(out, self.rdtype, (F, 2, N + 1, M + 1), "out")
+        _check(nufft2_pr_project(self.handle, coeffs.data_ptr(), out.data_ptr()), "nufft2_pr_project")
+        return out
+
+    def synthesize(self, pr, out=None):
+        N, M, F = self.N, self.M, self.F
+        self._want(pr, self.rdtype, (F, 2, N + 1, M + 1), "pr")
+        if out is None:
+            out = self._torch.empty((F, 2 * N + 1, 2 * M + 1), dtype=self.cdtype, device=pr.device)
+        self._want(out, self.cdtype, (F, 2 * N + 1, 2 * M + 1), "out")
+        _check(nufft2_pr_synthesize(self.handle, pr.data_ptr(), out.data_ptr()), "nufft2_pr_synthesize")
+        return out
+
+    def destroy(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            nufft2_pr_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
