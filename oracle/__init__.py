@@ -23,6 +23,9 @@ Contents
   * `pr_to_std`, `std_to_pr`, `exp_to_std`, `zonal_cutoff`, `zonal_filter`
                  -- the partial-regularity expansion and the zonal filter of
                     section 4 (`partial_regularity.py`).
+  * `gl_nodes`, `gl_analysis` -- samples on the Gauss-Legendre grid -> exp-form
+                    coefficients (section 5's interpolation for the SHT model,
+                    `gl.py`).
 """
 from __future__ import annotations
 
@@ -269,3 +272,4 @@ from .partial_regularity import (  # noqa: E402,F401
     exp_to_std, normal_system, pr_range, pr_to_std, std_to_pr, std_weights,
     zonal_cutoff, zonal_filter, zonal_limit,
 )
+from .gl import gl_analysis, gl_latitude_matrices, gl_nodes  # noqa: E402,F401
