@@ -26,19 +26,43 @@ from __future__ import annotations
 import numpy as np
 
 
-def gl_nodes(J: int):
-    """(theta [J] increasing, phi [2J]) of the Gauss-Legendre grid."""
+def _legendre_and_derivative(J, z):
+    """P_J(z) and P_J'(z) by the three-term recurrence (elementwise)."""
+    p0, p1 = np.ones_like(z), z
+    for n in range(2, J + 1):
+        p0, p1 = p1, ((2 * n - 1) * z * p1 - (n - 1) * p0) / n
+    if J == 1:
+        p0 = np.ones_like(z)
+    return p1, J * (z * p1 - p0) / (z * z - 1)
+
+
+def _gl_theta_ld(J: int):
+    """Colatitudes of the Legendre roots in numpy's long double: numpy's
+    Gauss-Legendre nodes as the start, then Newton steps in theta on
+    P_J(cos theta) (an FP64 cosine near the poles only fixes theta to
+    ~1e-14, because d theta = dz / sin theta)."""
     z, _ = np.polynomial.legendre.leggauss(J)
-    theta = np.sort(np.arccos(z))
+    th = np.sort(np.arccos(z)).astype(np.longdouble)
+    for _ in range(3):
+        p, dp = _legendre_and_derivative(J, np.cos(th))
+        th = th + p / (np.sin(th) * dp)          # d/dtheta P_J(cos theta) = -sin(theta) P_J'
+    return th
+
+
+def gl_nodes(J: int):
+    """(theta [J] increasing, phi [2J]) of the Gauss-Legendre grid, FP64."""
+    theta = _gl_theta_ld(J).astype(np.float64)
     phi = np.arange(2 * J) * np.pi / J
     return theta, phi
 
 
 def gl_latitude_matrices(J: int):
-    """C_even[j, n] = cos(n theta_j), n = 0..J-1; C_odd[j, n] = sin((n+1) theta_j)."""
-    theta, _ = gl_nodes(J)
-    n = np.arange(J)
-    return np.cos(np.outer(theta, n)), np.sin(np.outer(theta, n + 1))
+    """C_even[j, n] = cos(n theta_j), n = 0..J-1; C_odd[j, n] = sin((n+1) theta_j),
+    evaluated in long double at the long-double nodes and rounded to FP64."""
+    th = _gl_theta_ld(J)
+    n = np.arange(J, dtype=np.longdouble)
+    return (np.cos(np.outer(th, n)).astype(np.float64),
+            np.sin(np.outer(th, n + 1)).astype(np.float64))
 
 
 def gl_analysis(values):

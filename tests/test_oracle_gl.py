@@ -24,6 +24,23 @@ def test_nodes_are_legendre_roots(J):
     assert np.allclose(th, np.pi - th[::-1], atol=1e-14)          # symmetric about the equator
 
 
+def test_nodes_against_40_digit_newton():
+    """Nodes near the poles, where an FP64 arccos of the Legendre root is
+    off by ~1e-14: Newton in theta at 40 digits (mpmath)."""
+    import mpmath as mpm
+    mpm.mp.dps = 40
+    J = 1024
+    th, _ = oracle.gl_nodes(J)
+    for i in (0, 1, 5, 511, 1018, 1023):
+        t = mpm.mpf(th[i])
+        for _ in range(4):
+            h = mpm.mpf("1e-28")
+            f = mpm.legendre(J, mpm.cos(t))
+            df = (mpm.legendre(J, mpm.cos(t + h)) - mpm.legendre(J, mpm.cos(t - h))) / (2 * h)
+            t -= f / df
+        assert abs(float(th[i] - t)) <= 2.5e-16, i
+
+
 def exp_series_values(coeffs, J):
     th, ph = oracle.gl_nodes(J)
     T, P = np.meshgrid(th, ph, indexing="ij")
@@ -118,10 +135,10 @@ def test_least_squares_fit_of_the_basis():
 
 
 PLANTS = [
-    ("theta = np.sort(np.arccos(z))", "theta = np.arccos(z)"),                  # rows in z order
+    ("th = np.sort(np.arccos(z)).astype(np.longdouble)", "th = np.arccos(z).astype(np.longdouble)"),  # z order
     ("g = np.fft.fft(values, axis=2) / (2 * J)", "g = np.fft.fft(values, axis=2) / J"),
     ("out[:, J + n, col] = -0.5j * b[n - 1]", "out[:, J + n, col] = 0.5j * b[n - 1]"),
-    ("np.sin(np.outer(theta, n + 1))", "np.sin(np.outer(theta, n))"),
+    ("np.sin(np.outer(th, n + 1))", "np.sin(np.outer(th, n))"),
     ("if m % 2 == 0:\n            a = np.linalg.solve(Ce, rhs)", "if m % 2 == 1:\n            a = np.linalg.solve(Ce, rhs)"),
 ]
 
