@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 
 METRIC = "departure-pt interps/s (points*fields) at eps 1e-6 FP32 vs 1e-12 FP64; p99 latency"
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # dense matrix-core peaks of the MI355X
 STAGES = ("setpts", "theta_pass", "phi_pass", "gather")
 SINGLE_KERNEL_STAGES = ("theta_pass", "phi_pass", "gather")
 KERNEL_SOURCES = {"setpts": "setpts.hip", "theta_pass": "fft.hip", "phi_pass": "fft.hip",
@@ -432,6 +433,101 @@ def ensemble_bench(args, torch, steps, warmup):
     }
 
 
+def upstream_bench(torch, prec, J=1024, F=3, reps=20):
+    """The steps around the interpolation, on the 1024 x 2048 grid with 3
+    fields: DFS analysis of grid values with the zonal filter (M0 = 20), the
+    partial-regularity projection and synthesis (N = M = J - 1), the
+    rotation of (u, v) into the arrival frame at 2,097,152 points, and the
+    analysis of samples on the Gauss-Legendre grid of the same size.  Each is
+    timed with HIP events on the stream it runs on; `frac` is its algorithmic
+    bytes (inputs read once, outputs written once) per launch over its
+    average time, against 8 TB/s, except for the Gauss-Legendre analysis,
+    whose latitude product is a dense contraction priced against the MFMA
+    peak of its precision."""
+    import numpy as np
+
+    import synth
+    from paper_2605_01313_amd import Analysis, GLAnalysis, PartialRegularity, Plan
+    dev = torch.device("cuda:0")
+    rdt = torch.float32 if prec == "fp32" else torch.float64
+    cdt = torch.complex64 if prec == "fp32" else torch.complex128
+    rs = 4 if prec == "fp32" else 8
+    cs = 2 * rs
+    K, N = 2 * J - 1, J - 1
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    vals = torch.randn((F, J, 2 * J), dtype=rdt, device=dev, generator=gen)
+    an = Analysis(prec, J, n_fields=F)
+    an.set_zonal_filter(20)
+    coeffs = torch.empty((F, K, K), dtype=cdt, device=dev)
+    pr = PartialRegularity(prec, N, N, n_fields=F)
+    x = torch.empty((F, 2, N + 1, N + 1), dtype=rdt, device=dev)
+    phi_a, theta_a = synth.grid0_points(J)
+    rng = np.random.default_rng(4)
+    P = phi_a.size
+    phi_d = torch.from_numpy(phi_a + rng.uniform(-0.05, 0.05, P)).to(dev)
+    theta_d = torch.from_numpy(theta_a + rng.uniform(-0.05, 0.05, P)).to(dev)
+    phi_a = torch.from_numpy(phi_a).to(dev)
+    theta_a = torch.from_numpy(theta_a).to(dev)
+    plan = Plan(prec, 31, 31, n_fields=F, eps=1e-6 if prec == "fp32" else 1e-12)
+    plan.setpts(phi_d, theta_d)
+    out = torch.randn((F, P), dtype=cdt, device=dev, generator=gen)
+    gl = GLAnalysis(prec, J, n_fields=F)
+    gl_out = torch.empty((F, 2 * J + 1, K), dtype=cdt, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timeit(fn):
+        for _ in range(3):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return sum(a.elapsed_time(b) for a, b in ev) / reps
+
+    ops = {
+        "analysis_zonal": (lambda: an.exec(vals, coeffs), F * J * 2 * J * rs + F * K * K * cs),
+        "pr_project": (lambda: pr.project(coeffs, x), F * K * K * cs + F * 2 * J * J * rs),
+        "pr_synthesize": (lambda: pr.synthesize(x, coeffs), F * 2 * J * J * rs + F * K * K * cs),
+        "rotate_uv": (lambda: plan.rotate_uv(out, 1, 2, phi_a, theta_a), 4 * P * 8 + 4 * P * cs),
+    }
+    res = {}
+    for name, (fn, nbytes) in ops.items():
+        ms = timeit(fn)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[name] = {"ms": ms, "alg_bytes": nbytes, "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        log(f"bench: upstream {prec} {name} {ms:.4f} ms, {gbs:.0f} GB/s")
+    # Gauss-Legendre analysis: longitude FFT + the latitude product on the
+    # matrix cores, 2 J^2 (4J - 2) flops per field (the two parities' J x J
+    # inverses times 2(J - 1) and 2J real columns); MFMA-bound
+    ms = timeit(lambda: gl.exec(vals, gl_out))
+    flops = 2.0 * J * J * (4 * J - 2) * F
+    peak = MFMA_PEAK_TFLOPS[prec]
+    tfs = flops / (ms * 1e-3) / 1e12
+    res["gl_analysis"] = {"ms": ms, "flops": flops, "achieved_tflops": tfs, "peak_tflops": peak,
+                          "frac": tfs / peak, "bound": "mfma"}
+    log(f"bench: upstream {prec} gl_analysis {ms:.4f} ms, {tfs:.1f} TFLOP/s")
+    for o in (an, pr, plan, gl):
+        o.destroy()
+    return {"grid": f"{J}x{2 * J}", "n_fields": F, "n_points": P, "ops": res}
+
+
+def upstream_line(args, torch):
+    r = {prec: upstream_bench(torch, prec) for prec in ("fp32", "fp64")}
+    ms = r["fp32"]["ops"]["analysis_zonal"]["ms"]
+    line = {
+        "metric": "upstream steps: analysis, pr projection / synthesis, (u, v) rotation, GL analysis",
+        "value": None,
+        "unit": None, "n_gpus": 1, "steps": 20, "warmup": 3, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic", "config": {"workload": "upstream_grid1024x2048_3fields"},
+        "upstream": r, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def ensemble_line(args, torch):
     r = ensemble_bench(args, torch, args.steps, args.warmup)
     line = {
@@ -454,18 +550,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("sbr256", "wind1024", "ensemble", "serving"), default="sbr256",
+    ap.add_argument("--workload", choices=("sbr256", "wind1024", "ensemble", "serving", "upstream"),
+                    default="sbr256",
                     help="sbr256: 256x512 grid, solid-body rotation (default); "
                          "wind1024: 1024x2048 grid, 8-mode wind, Courant 8; "
                          "ensemble: 64 + 16 members of uneven size as one group; "
-                         "serving: Poisson request stream through the serving loop")
+                         "serving: Poisson request stream through the serving loop; "
+                         "upstream: analysis, partial-regularity and rotation kernels at 1024x2048")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="requests per second")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-pool", type=int, default=8, help="point payloads per grid size")
     ap.add_argument("--serve-budget-gib", type=int, default=16)
     ap.add_argument("--serve-inflight", type=int, default=16)
     ap.add_argument("--no-extras", action="store_true",
-                    help="default workload only: skip the ensemble and serving sections")
+                    help="default workload only: skip the ensemble, serving and upstream sections")
     ap.add_argument("--extra-serve-seconds", type=float, default=10.0,
                     help="length of the serving section of the default run")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (ensemble)")
@@ -487,6 +585,9 @@ def main():
         return
     if args.workload == "serving":
         serving_line(args, torch)
+        return
+    if args.workload == "upstream":
+        upstream_line(args, torch)
         return
     if args.workload == "sbr256":
         log("bench: building the 256x512 solid-body-rotation workload")
@@ -549,6 +650,8 @@ def main():
         sargs = argparse.Namespace(**vars(args))
         sargs.serve_seconds = args.extra_serve_seconds
         line["serving"] = serving_bench(sargs, torch)
+        log("bench: upstream section")
+        line["upstream"] = {prec: upstream_bench(torch, prec) for prec in ("fp32", "fp64")}
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         outs = {"fp32": r32.out.cpu().numpy().astype(np.complex128),

@@ -413,6 +413,40 @@ nufft2_status nufft2_pr_synthesize(nufft2_pr h, const void *pr_dev, void *coeffs
 nufft2_status nufft2_pr_destroy(nufft2_pr h);
 
 /*
+ * DFS coefficients from samples on the Gauss-Legendre grid (section 2,
+ * eq. GLGrid; section 5, the interpolation used for the SHT model).  Row j
+ * of the grid is colatitude theta_j = arccos(z_j), z_j the roots of the
+ * degree-J Legendre polynomial, in increasing theta; column k is longitude
+ * phi_k = pi k / J.  After an FFT in longitude (|m| <= J - 1), each m is
+ * interpolated in latitude in the standard DFS parity: cos(n theta),
+ * n = 0..J-1, for even m and sin(n theta), n = 1..J, for odd m, by the
+ * inverses of the two J x J latitude matrices (formed once per plan from
+ * their LU factors in long double; applied on the matrix cores).  The
+ * output is the exp form of eq. std_dfs_exp with n = -J..J and
+ * m = -(J-1)..J-1: [n_fields][2J+1][2J-1] complex in the plan precision,
+ * centred (row a <-> n = a - J, column b <-> m = b - (J-1)), the input of
+ * nufft2_exec with K_theta = 2J+1, K_phi = 2J-1.  The series it defines
+ * takes the (longitude-truncated) samples at the grid nodes.
+ *
+ * nufft2_gl_nodes -- host helper: theta[J] (host array of J doubles), the
+ *   grid's colatitudes.  1 <= J <= 4096.  Errors: ERR_ARG.
+ * nufft2_gl_plan -- J a power of two, 16 <= J <= 1024; prec as for
+ *   nufft2_plan; stream a hipStream_t.  Owns the inverses (2 J^2 reals),
+ *   twiddle tables and an [n_fields][J][2J-1] complex buffer.  Plan creation
+ *   inverts two J x J matrices on the host (about a second at J = 1024).
+ *   Errors: ERR_ARG, ERR_ALLOC, ERR_HIP.
+ * nufft2_gl_exec -- values_dev [n_fields][J][2J] real (plan precision,
+ *   row-major), coeffs_dev as above; device memory owned by the caller, not
+ *   overlapping.  Asynchronous on the plan's stream.  Errors: ERR_ARG, ERR_HIP.
+ * nufft2_gl_destroy -- synchronise the stream and free; NULL ignored.
+ */
+typedef struct nufft2_gl_s *nufft2_gl;
+nufft2_status nufft2_gl_nodes(int64_t J, double *theta);
+nufft2_status nufft2_gl_plan(nufft2_prec prec, int64_t J, int32_t n_fields, void *stream, nufft2_gl *out);
+nufft2_status nufft2_gl_exec(nufft2_gl g, const void *values_dev, void *coeffs_dev);
+nufft2_status nufft2_gl_destroy(nufft2_gl g);
+
+/*
  * Host-only helpers (no device work; usable without a GPU).
  *
  * nufft2_kernel_params -- the width and shape the plan would choose for eps

@@ -4,8 +4,8 @@ for one AMD Instinct MI355X (gfx950).
 The computation lives in libnufft2.so (HIP kernels behind the C ABI of
 include/nufft2.h); `nufft2` is its Python binding.
 """
-from .nufft2 import (NUFFT2_FP32, NUFFT2_FP64, Analysis, Group, Nufft2Error, PartialRegularity, Plan,  # noqa: F401
-                     Server,
+from .nufft2 import (NUFFT2_FP32, NUFFT2_FP64, Analysis, GLAnalysis, Group, Nufft2Error,  # noqa: F401
+                     PartialRegularity, Plan, Server,
                      autotune,
                      nufft2_autotune, nufft2_check,
                      nufft2_debug_buffer, nufft2_destroy, nufft2_exec, nufft2_get_info,

@@ -640,27 +640,38 @@ __global__ __launch_bounds__(512) void k_analysis_theta(const cplx<T> *__restric
     fft_stages<T, LOGN, 0, E, true>(s, log_cols_per_wg, cols_per_wg, 1, tw, ld, st, pro);
 }
 
+// phi step only: rows per workgroup so that it transforms 4096 elements
+template <typename T, int LOGN>
+static hipError_t launch_analysis_rows_t(const AnalysisParams &ap, const void *vals, const void *tws, void *A,
+                                         hipStream_t s)
+{
+    constexpr int N = 1 << LOGN;
+    const int J = N / 2;
+    int rb = 4096 / N;
+    if (rb > J) rb = J;
+    int lrb = 0;
+    while ((1 << lrb) < rb) ++lrb;
+    const int threads = N * rb / kElemsPerThread;
+    if (threads < 1 || threads > 256) return hipErrorInvalidConfiguration;
+    const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * rb + tw_lds_len(N));
+    auto kern = k_analysis_phi<T, LOGN, kElemsPerThread>;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3((J / rb) * ap.n_fields), dim3(threads), lds, s, (const T *)vals,
+                       (const cplx<T> *)tws, ap.zonal_cut, (cplx<T> *)A, J, rb, lrb);
+    return hipGetLastError();
+}
+
 template <typename T, int LOGN>
 static hipError_t launch_analysis_t(const AnalysisParams &ap, const void *vals, const void *tws, const void *phase,
                                     void *A, void *out, hipStream_t s)
 {
     constexpr int N = 1 << LOGN;
     const int J = N / 2;
-    // phi step: rows per workgroup so that it transforms 4096 elements
-    int rb = 4096 / N;
-    if (rb > J) rb = J;
-    int lrb = 0;
-    while ((1 << lrb) < rb) ++lrb;
-    int threads = N * rb / kElemsPerThread;
-    if (threads < 1 || threads > 256) return hipErrorInvalidConfiguration;
-    size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * rb + tw_lds_len(N));
+    int threads;
+    size_t lds;
     {
-        auto kern = k_analysis_phi<T, LOGN, kElemsPerThread>;
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(kern, dim3((J / rb) * ap.n_fields), dim3(threads), lds, s, (const T *)vals,
-                           (const cplx<T> *)tws, ap.zonal_cut, (cplx<T> *)A, J, rb, lrb);
-        hipError_t e = hipGetLastError();
+        const hipError_t e = launch_analysis_rows_t<T, LOGN>(ap, vals, tws, A, s);
         if (e != hipSuccess) return e;
     }
     // theta step: columns per workgroup so that a workgroup has 64..512 threads
@@ -703,6 +714,25 @@ hipError_t launch_analysis(int prec, const AnalysisParams &ap, const void *vals,
 {
     if (prec == 1) return analysis_dispatch<float>(ap, vals, tws, phase, A, out, s);
     return analysis_dispatch<double>(ap, vals, tws, phase, A, out, s);
+}
+
+template <typename T>
+static hipError_t analysis_rows_dispatch(const AnalysisParams &ap, const void *vals, const void *tws, void *A,
+                                         hipStream_t s)
+{
+    switch (ap.log_len) {
+#define NUFFT2_A(X) case X: return launch_analysis_rows_t<T, X>(ap, vals, tws, A, s);
+        NUFFT2_A(5) NUFFT2_A(6) NUFFT2_A(7) NUFFT2_A(8) NUFFT2_A(9) NUFFT2_A(10) NUFFT2_A(11) NUFFT2_A(12)
+#undef NUFFT2_A
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_analysis_rows(int prec, const AnalysisParams &ap, const void *vals, const void *tws, void *A,
+                                hipStream_t s)
+{
+    if (prec == 1) return analysis_rows_dispatch<float>(ap, vals, tws, A, s);
+    return analysis_rows_dispatch<double>(ap, vals, tws, A, s);
 }
 
 }  // namespace nufft2

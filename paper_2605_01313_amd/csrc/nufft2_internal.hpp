@@ -141,5 +141,18 @@ struct AnalysisParams {
 };
 hipError_t launch_analysis(int prec, const AnalysisParams &ap, const void *vals, const void *tws, const void *phase,
                            void *A, void *out, hipStream_t s);
+// The phi step alone: A[f][i][m + J - 1] = sum_k vals[f][i][k] e^{-i m pi k / J}
+// (unnormalised), |m| <= J - 1, with the zonal filter when ap.zonal_cut is set.
+hipError_t launch_analysis_rows(int prec, const AnalysisParams &ap, const void *vals, const void *tws, void *A,
+                                hipStream_t s);
+
+// Gauss-Legendre latitude step: for each field and each parity p of m, the
+// coefficient columns inv[p] (J x J, row-major: coefficient index x sample)
+// times the phi-step samples A[f][j][m + J - 1] of the m of parity p, scaled
+// by 1/(2J) and written in exp form to out[f][n + J][m + J - 1]
+// ([F][2J+1][2J-1] complex): even m -> cos(n theta), n = 0..J-1; odd m ->
+// sin(n theta), n = 1..J.
+hipError_t launch_gl_latitude(int prec, int J, int n_fields, const void *inv, const void *A, void *out,
+                              hipStream_t s);
 
 }  // namespace nufft2

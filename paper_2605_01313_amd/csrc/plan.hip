@@ -8,6 +8,7 @@
 
 #include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "nufft2.h"
@@ -833,5 +834,170 @@ NUFFT2_API nufft2_status nufft2_analysis_destroy(nufft2_analysis a)
     if (!a) return NUFFT2_OK;
     (void)hipStreamSynchronize(a->stream);
     analysis_free(a);
+    return NUFFT2_OK;
+}
+
+// ---- Gauss-Legendre DFS analysis ----------------------------------------------
+
+namespace {
+
+// Roots of the degree-J Legendre polynomial (Newton from cos(pi (k + 3/4) /
+// (J + 1/2)), long double), as colatitudes in increasing order.
+void gl_colatitudes(int J, std::vector<long double> &theta)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    theta.resize(J);
+    for (int k = 0; k < J; ++k) {
+        long double z = cosl(pi * ((long double)k + 0.75L) / ((long double)J + 0.5L));
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1.0L, p1 = z;
+            for (int n = 2; n <= J; ++n) {
+                const long double p2 = ((2.0L * n - 1.0L) * z * p1 - (n - 1.0L) * p0) / (long double)n;
+                p0 = p1;
+                p1 = p2;
+            }
+            const long double dp = (long double)J * (z * p1 - p0) / (z * z - 1.0L);
+            const long double dz = p1 / dp;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L * fabsl(z) + 1e-30L) break;
+        }
+        theta[k] = acosl(z);  // z decreases with k: theta increases
+    }
+}
+
+// Inverse of the J x J matrix M (row-major) by LU with partial pivoting
+// (Gauss-Jordan on [M | I]), long double; false if singular.
+bool invert_ld(int J, std::vector<long double> &M, std::vector<long double> &inv)
+{
+    inv.assign((size_t)J * J, 0.0L);
+    for (int i = 0; i < J; ++i) inv[(size_t)i * J + i] = 1.0L;
+    for (int c = 0; c < J; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < J; ++r)
+            if (fabsl(M[(size_t)r * J + c]) > fabsl(M[(size_t)piv * J + c])) piv = r;
+        if (M[(size_t)piv * J + c] == 0.0L) return false;
+        if (piv != c)
+            for (int k = 0; k < J; ++k) {
+                std::swap(M[(size_t)c * J + k], M[(size_t)piv * J + k]);
+                std::swap(inv[(size_t)c * J + k], inv[(size_t)piv * J + k]);
+            }
+        const long double d = 1.0L / M[(size_t)c * J + c];
+        for (int k = 0; k < J; ++k) {
+            M[(size_t)c * J + k] *= d;
+            inv[(size_t)c * J + k] *= d;
+        }
+        for (int r = 0; r < J; ++r) {
+            if (r == c) continue;
+            const long double f = M[(size_t)r * J + c];
+            if (f == 0.0L) continue;
+            long double *mr = &M[(size_t)r * J], *ir = &inv[(size_t)r * J];
+            const long double *mc = &M[(size_t)c * J], *ic = &inv[(size_t)c * J];
+            for (int k = c; k < J; ++k) mr[k] -= f * mc[k];
+            for (int k = 0; k < J; ++k) ir[k] -= f * ic[k];
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+struct nufft2_gl_s {
+    int prec = 0;
+    int J = 0, F = 0;
+    hipStream_t stream = nullptr;
+    void *tws = nullptr, *inv = nullptr, *A = nullptr;
+};
+
+static void gl_free(nufft2_gl_s *g)
+{
+    if (g->tws) (void)hipFree(g->tws);
+    if (g->inv) (void)hipFree(g->inv);
+    if (g->A) (void)hipFree(g->A);
+    delete g;
+}
+
+template <typename T> static hipError_t gl_tables(nufft2_gl_s *g)
+{
+    const int J = g->J;
+    std::vector<long double> th;
+    gl_colatitudes(J, th);
+    std::vector<T> out(2 * (size_t)J * J);
+    for (int p = 0; p < 2; ++p) {
+        // rows: samples j; columns: basis n (cos(n theta), n < J; sin((n + 1) theta))
+        std::vector<long double> M((size_t)J * J), inv;
+        for (int j = 0; j < J; ++j)
+            for (int n = 0; n < J; ++n)
+                M[(size_t)j * J + n] = p == 0 ? cosl((long double)n * th[j]) : sinl((long double)(n + 1) * th[j]);
+        if (!invert_ld(J, M, inv)) return hipErrorInvalidValue;
+        for (size_t e = 0; e < inv.size(); ++e) out[(size_t)p * J * J + e] = (T)inv[e];
+    }
+    std::vector<T> tw;
+    fill_twiddle_tables<T>(tw, 2 * J);
+    hipError_t e = hipMemcpy(g->inv, out.data(), sizeof(T) * out.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g->tws, tw.data(), sizeof(T) * tw.size(), hipMemcpyHostToDevice);
+    return e;
+}
+
+NUFFT2_API nufft2_status nufft2_gl_nodes(int64_t J, double *theta)
+{
+    if (!theta || J < 1 || J > 4096) return NUFFT2_ERR_ARG;
+    std::vector<long double> th;
+    gl_colatitudes((int)J, th);
+    for (int64_t j = 0; j < J; ++j) theta[j] = (double)th[j];
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_gl_plan(nufft2_prec prec, int64_t J, int32_t n_fields, void *stream, nufft2_gl *out)
+{
+    if (!out || (prec != NUFFT2_FP32 && prec != NUFFT2_FP64) || n_fields < 1 || J < 16 || J > 1024 ||
+        !is_pow2(J))
+        return NUFFT2_ERR_ARG;
+    nufft2_gl_s *g = new (std::nothrow) nufft2_gl_s();
+    if (!g) return NUFFT2_ERR_ALLOC;
+    g->prec = prec;
+    g->J = (int)J;
+    g->F = n_fields;
+    g->stream = (hipStream_t)stream;
+    const size_t rs = prec == NUFFT2_FP32 ? sizeof(float) : sizeof(double);
+    const size_t K = 2 * (size_t)J - 1;
+    if (hipMalloc(&g->tws, 2 * rs * (64 + 2 * (size_t)J)) != hipSuccess ||
+        hipMalloc(&g->inv, rs * 2 * (size_t)J * J) != hipSuccess ||
+        hipMalloc(&g->A, 2 * rs * (size_t)n_fields * J * K) != hipSuccess) {
+        (void)hipGetLastError();
+        gl_free(g);
+        return NUFFT2_ERR_ALLOC;
+    }
+    const hipError_t e = prec == NUFFT2_FP32 ? gl_tables<float>(g) : gl_tables<double>(g);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        gl_free(g);
+        return NUFFT2_ERR_HIP;
+    }
+    *out = g;
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_gl_exec(nufft2_gl g, const void *values_dev, void *coeffs_dev)
+{
+    if (!g || !values_dev || !coeffs_dev) return NUFFT2_ERR_ARG;
+    AnalysisParams ap{};
+    ap.J = g->J;
+    ap.log_len = ilog2(2 * (int64_t)g->J);
+    ap.n_fields = g->F;
+    ap.zonal_cut = nullptr;
+    hipError_t e = launch_analysis_rows(g->prec, ap, values_dev, g->tws, g->A, g->stream);
+    if (e == hipSuccess) e = launch_gl_latitude(g->prec, g->J, g->F, g->inv, g->A, coeffs_dev, g->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return NUFFT2_ERR_HIP;
+    }
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_gl_destroy(nufft2_gl g)
+{
+    if (!g) return NUFFT2_OK;
+    (void)hipStreamSynchronize(g->stream);
+    gl_free(g);
     return NUFFT2_OK;
 }

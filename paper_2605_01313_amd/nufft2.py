@@ -36,7 +36,8 @@ EXPORTED = (
     "nufft2_server_clock", "nufft2_server_submit", "nufft2_server_wait", "nufft2_server_drain",
     "nufft2_server_stats", "nufft2_server_destroy", "nufft2_analysis_plan", "nufft2_analysis_exec",
     "nufft2_analysis_destroy", "nufft2_rotate_uv", "nufft2_analysis_set_zonal_filter", "nufft2_pr_plan",
-    "nufft2_pr_project", "nufft2_pr_synthesize", "nufft2_pr_destroy",
+    "nufft2_pr_project", "nufft2_pr_synthesize", "nufft2_pr_destroy", "nufft2_gl_nodes", "nufft2_gl_plan",
+    "nufft2_gl_exec", "nufft2_gl_destroy",
 )
 NUFFT2_N_STAGES = 4
 STAGE_NAMES = ("setpts", "theta_pass", "phi_pass", "gather")
@@ -150,6 +151,10 @@ def _load():
         "nufft2_pr_project": [H, vp, vp],
         "nufft2_pr_synthesize": [H, vp, vp],
         "nufft2_pr_destroy": [H],
+        "nufft2_gl_nodes": [i64, vp],
+        "nufft2_gl_plan": [i32, i64, i32, vp, ctypes.POINTER(H)],
+        "nufft2_gl_exec": [H, vp, vp],
+        "nufft2_gl_destroy": [H],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -383,6 +388,29 @@ def nufft2_pr_synthesize(handle, pr_ptr, coeffs_ptr):
 
 def nufft2_pr_destroy(handle):
     return _lib.nufft2_pr_destroy(handle)
+
+
+def nufft2_gl_nodes(J):
+    """Returns (status, numpy array of the J Gauss-Legendre colatitudes)."""
+    import numpy as np
+    out = np.zeros(max(int(J), 1), dtype=np.float64)
+    st = _lib.nufft2_gl_nodes(int(J), out.ctypes.data_as(ctypes.c_void_p))
+    return st, out
+
+
+def nufft2_gl_plan(prec, J, n_fields, stream=0):
+    """Returns (status, Gauss-Legendre analysis handle)."""
+    h = ctypes.c_void_p()
+    st = _lib.nufft2_gl_plan(int(prec), int(J), int(n_fields), ctypes.c_void_p(stream or None), ctypes.byref(h))
+    return st, h
+
+
+def nufft2_gl_exec(handle, values_ptr, coeffs_ptr):
+    return _lib.nufft2_gl_exec(handle, ctypes.c_void_p(values_ptr or None), ctypes.c_void_p(coeffs_ptr or None))
+
+
+def nufft2_gl_destroy(handle):
+    return _lib.nufft2_gl_destroy(handle)
 
 
 # ---- torch convenience -----------------------------------------------------
@@ -756,6 +784,47 @@ class PartialRegularity:
     def destroy(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             nufft2_pr_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class GLAnalysis:
+    """Samples on the Gauss-Legendre grid -> exp-form coefficients (nufft2_gl_*).
+
+    >>> gl = GLAnalysis("fp64", J=256, n_fields=3)
+    >>> coeffs = gl.exec(values)      # (F, J, 2J) real -> (F, 2J+1, 2J-1) complex
+    """
+
+    def __init__(self, prec, J, n_fields=1, stream=None):
+        import torch
+        self._torch = torch
+        self.prec = {"fp32": NUFFT2_FP32, "fp64": NUFFT2_FP64}[prec]
+        self.rdtype = torch.float32 if self.prec == NUFFT2_FP32 else torch.float64
+        self.cdtype = torch.complex64 if self.prec == NUFFT2_FP32 else torch.complex128
+        self.J, self.F = int(J), int(n_fields)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        st, h = nufft2_gl_plan(self.prec, J, n_fields, self.stream.cuda_stream)
+        _check(st, "nufft2_gl_plan")
+        self.handle = h
+
+    def exec(self, values, out=None):
+        J, F = self.J, self.F
+        if values.dtype != self.rdtype or not values.is_cuda or not values.is_contiguous() \
+                or tuple(values.shape) not in ((F, J, 2 * J), (J, 2 * J)):
+            raise TypeError(f"values must be a contiguous {self.rdtype} device tensor ({F}, {J}, {2 * J})")
+        if out is None:
+            out = self._torch.empty((F, 2 * J + 1, 2 * J - 1), dtype=self.cdtype, device=values.device)
+        _check(nufft2_gl_exec(self.handle, values.data_ptr(), out.data_ptr()), "nufft2_gl_exec")
+        return out
+
+    def destroy(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            nufft2_gl_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
     def __del__(self):

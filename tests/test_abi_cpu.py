@@ -148,3 +148,25 @@ def test_binding_has_no_fallback_path():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "numpy.fft" not in text and "np.fft" not in text, f
+
+
+@pytest.mark.parametrize("J", [1, 2, 7, 16, 256, 1024])
+def test_gl_nodes_are_the_gauss_legendre_colatitudes(nf, oracle_mod, J):
+    """Host helper, no device work: the library's Newton iteration (long
+    double) against numpy's Gauss-Legendre nodes used by the oracle."""
+    st, th = nf.nufft2_gl_nodes(J)
+    assert st == nf.NUFFT2_OK
+    want, _ = oracle_mod.gl_nodes(J)
+    assert np.abs(th - want).max() < 4e-16
+
+
+def test_gl_and_pr_argument_errors_before_device_work(nf):
+    assert nf.nufft2_gl_nodes(0)[0] == nf.NUFFT2_ERR_ARG
+    assert nf.nufft2_gl_plan(1, 24, 1)[0] == nf.NUFFT2_ERR_ARG       # not a power of two
+    assert nf.nufft2_gl_plan(1, 8, 1)[0] == nf.NUFFT2_ERR_ARG        # below 16
+    assert nf.nufft2_gl_plan(1, 2048, 1)[0] == nf.NUFFT2_ERR_ARG     # above 1024
+    assert nf.nufft2_gl_plan(2, 64, 0)[0] == nf.NUFFT2_ERR_ARG       # no fields
+    assert nf.nufft2_gl_exec(None, 0, 0) == nf.NUFFT2_ERR_ARG
+    assert nf.nufft2_gl_destroy(None) == nf.NUFFT2_OK
+    assert nf.nufft2_pr_plan(1, 4, 10, 1)[0] == nf.NUFFT2_ERR_ARG
+    assert nf.nufft2_pr_destroy(None) == nf.NUFFT2_OK
