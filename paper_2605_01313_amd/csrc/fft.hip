@@ -429,7 +429,8 @@ static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const 
                                  void *S, const ThetaJob *jobs, int n_members, hipStream_t s)
 {
     const int L = 1 << LOGL;
-    const int threads = L * fp.theta_batch / kElemsPerThread;
+    const int ept = fp.theta_ept == 8 ? 8 : kElemsPerThread;
+    const int threads = L * fp.theta_batch / ept;
     if (threads < 1 || threads > theta_max_threads<T>() || threads % fp.theta_batch != 0)
         return hipErrorInvalidConfiguration;
     const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(L) * fp.theta_batch + tw_lds_len(L)) +
@@ -437,12 +438,12 @@ static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const 
     const int ntiles = (fp.Kp + fp.theta_batch - 1) / fp.theta_batch;
     const int per = 2 * ntiles * fp.n_fields;
     if (jobs) {
-        auto kern = k_theta_group<T, LOGL, kElemsPerThread>;
+        auto kern = ept == 8 ? k_theta_group<T, LOGL, 8> : k_theta_group<T, LOGL, kElemsPerThread>;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, dim3(per * n_members), dim3(threads), lds, s, jobs, per);
     } else {
-        auto kern = k_theta_pass<T, LOGL, kElemsPerThread>;
+        auto kern = ept == 8 ? k_theta_pass<T, LOGL, 8> : k_theta_pass<T, LOGL, kElemsPerThread>;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, dim3(per), dim3(threads), lds, s, (const cplx<T> *)coeffs,
@@ -458,17 +459,18 @@ static hipError_t launch_phi_t(const FFTParams &fp, const void *S, const void *t
                                hipStream_t s)
 {
     const int N = 1 << LOGN;
-    const int threads = N * fp.phi_batch / kElemsPerThread;
+    const int ept = fp.phi_ept == 8 ? 8 : kElemsPerThread;
+    const int threads = N * fp.phi_batch / ept;
     if (threads < 1 || threads > 256) return hipErrorInvalidConfiguration;
     const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * fp.phi_batch + tw_lds_len(N));
     const int per = (fp.nft / fp.phi_batch) * fp.n_fields;
     if (jobs) {
-        auto kern = k_phi_group<T, LOGN, kElemsPerThread>;
+        auto kern = ept == 8 ? k_phi_group<T, LOGN, 8> : k_phi_group<T, LOGN, kElemsPerThread>;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, dim3(per * n_members), dim3(threads), lds, s, jobs, per);
     } else {
-        auto kern = k_phi_pass<T, LOGN, kElemsPerThread>;
+        auto kern = ept == 8 ? k_phi_pass<T, LOGN, 8> : k_phi_pass<T, LOGN, kElemsPerThread>;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, dim3(per), dim3(threads), lds, s, (const cplx<T> *)S, (const cplx<T> *)tw_p,

@@ -65,6 +65,7 @@ struct FFTParams {
     int32_t n_fields;
     int32_t theta_batch, log_theta_batch;   // columns per theta-pass workgroup
     int32_t phi_batch, log_phi_batch;       // rows per phi-pass workgroup
+    int32_t theta_ept, phi_ept;             // elements per thread in each pass: 8 or 16
 };
 
 // fac_t: complex [2][Kt]: corr_t[a], then corr_t[a] e^{2 pi i n / nft}

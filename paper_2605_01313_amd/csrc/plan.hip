@@ -29,6 +29,9 @@ constexpr int kDefaultTilePhi = 32;
 constexpr size_t kGatherLdsLimit = 65536;  // per staged field group
 constexpr size_t kFftLdsLimit = 155648;    // 152 KiB of the 160 KiB per workgroup
 constexpr int kGatherMaxFieldsPerPass = 4;
+// an FFT pass with fewer waves than this at 16 elements per thread (8 per
+// SIMD of the 256 CUs) runs with 8 elements per thread
+constexpr int64_t kSmallLaunchWaves = 8 * 256;
 
 }  // namespace
 
@@ -418,10 +421,17 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
         }
         fp.theta_batch = (int)b;
         fp.log_theta_batch = ilog2(b);
+        // small transforms: 8 elements per thread instead of 16, so that the
+        // launch has about twice the waves to hide LDS and memory latency
+        const int64_t waves16 = 2 * ((p->Kp + b - 1) / b) * (int64_t)n_fields * L * b / 16 / 64;
+        fp.theta_ept = (waves16 < kSmallLaunchWaves && L * b / 8 <= max_threads && L >= 64) ? 8 : 16;
     }
     {
-        // phi pass: rows per workgroup so that a workgroup transforms 4096 elements
-        int64_t b = 4096 / p->nfp;
+        // phi pass: rows per workgroup so that a workgroup transforms 4096
+        // elements (2048 with 8 elements per thread)
+        const int64_t waves16 = (int64_t)n_fields * (p->nft / 2) * p->nfp / 16 / 64;
+        fp.phi_ept = (waves16 < kSmallLaunchWaves && p->nfp >= 64) ? 8 : 16;
+        int64_t b = (fp.phi_ept == 8 ? 2048 : 4096) / p->nfp;
         if (b < 1) b = 1;
         if (b > p->nft) b = p->nft;
         fp.phi_batch = (int)b;

@@ -178,7 +178,50 @@ constexpr int kScanChunk = 8;
 // its own LDS banks
 __device__ constexpr int scan_slot(int e) { return e + e / kScanChunk; }
 
-__device__ inline void bin_scan_body(int32_t *__restrict__ bincount, int32_t *__restrict__ binstart,
+// One pass over PASS = CHUNK * 1024 bins starting at base (n of them):
+// in[k] is this thread's count of bin base + k * 1024 + threadIdx.x (zero
+// past the end).  Stages them in LDS, scans CHUNK consecutive counts per
+// thread, writes the starts (coalesced) and the non-empty bins.
+__device__ __attribute__((always_inline)) inline void scan_pass(const int (&in)[kScanChunk], int64_t base, int n, int *stage, int (*lds)[33],
+                                 int &carry, int &carry_ne, int32_t *__restrict__ binstart,
+                                 int32_t *__restrict__ binlist)
+{
+#pragma unroll
+    for (int k = 0; k < kScanChunk; ++k) stage[scan_slot(k * kScanThreads + (int)threadIdx.x)] = in[k];
+    __syncthreads();
+    int vals[kScanChunk];
+    int sum = 0, ne = 0;
+#pragma unroll
+    for (int c = 0; c < kScanChunk; ++c) {
+        vals[c] = stage[scan_slot((int)threadIdx.x * kScanChunk + c)];
+        sum += vals[c];
+        ne += vals[c] > 0 ? 1 : 0;
+    }
+    int total, ne_total;
+    int run = sum, pos = ne;
+    block_exclusive_scan2(run, pos, lds, total, ne_total);
+    run += carry;
+    pos += carry_ne;
+    const int first = (int)base + (int)threadIdx.x * kScanChunk;
+#pragma unroll
+    for (int c = 0; c < kScanChunk; ++c) {
+        stage[scan_slot((int)threadIdx.x * kScanChunk + c)] = run;
+        run += vals[c];
+        if (vals[c] > 0) binlist[pos++] = first + c;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += kScanThreads) binstart[base + e] = stage[scan_slot(e)];
+    __syncthreads();
+    carry += total;
+    carry_ne += ne_total;
+}
+
+// Passes whose counts are all loaded before the first scan (nbins up to
+// kScanHoist * PASS): the kernel then waits on global memory once.
+constexpr int kScanHoist = 4;
+constexpr int kMaxRowsPerScanThread = 4;  // nf <= 4096
+
+__device__ __attribute__((always_inline)) inline void bin_scan_body(int32_t *__restrict__ bincount, int32_t *__restrict__ binstart,
                                      int32_t *__restrict__ binlist, int64_t nbins, uint8_t *__restrict__ rowmark,
                                      uint8_t *__restrict__ rowtouched, int nft, int w,
                                      int32_t *__restrict__ flags)
@@ -186,66 +229,75 @@ __device__ inline void bin_scan_body(int32_t *__restrict__ bincount, int32_t *__
     __shared__ int lds[2][33];
     __shared__ int stage[kScanChunk * kScanThreads + kScanThreads];
     constexpr int PASS = kScanChunk * kScanThreads;
-    int carry = 0, carry_ne = 0;
-    for (int64_t base = 0; base < nbins; base += PASS) {
-        const int n = (int)((nbins - base) < PASS ? (nbins - base) : PASS);
-        for (int e = threadIdx.x; e < PASS; e += kScanThreads) {
-            int v = 0;
-            if (e < n) {
-                v = bincount[base + e];
-                bincount[base + e] = 0;
-            }
-            stage[scan_slot(e)] = v;
-        }
-        __syncthreads();
-        int vals[kScanChunk];
-        int sum = 0;
+    const int t = (int)threadIdx.x;
+    // the row marks and the non-finite accumulator are read with the counts
+    uint8_t mk[kMaxRowsPerScanThread];
 #pragma unroll
-        for (int c = 0; c < kScanChunk; ++c) {
-            vals[c] = stage[scan_slot(threadIdx.x * kScanChunk + c)];
-            sum += vals[c];
-        }
-        int ne = 0;
-#pragma unroll
-        for (int c = 0; c < kScanChunk; ++c) ne += vals[c] > 0 ? 1 : 0;
-        int total, ne_total;
-        int run = sum, pos = ne;
-        block_exclusive_scan2(run, pos, lds, total, ne_total);
-        run += carry;
-        pos += carry_ne;
-        const int first = (int)base + (int)threadIdx.x * kScanChunk;
-#pragma unroll
-        for (int c = 0; c < kScanChunk; ++c) {
-            stage[scan_slot(threadIdx.x * kScanChunk + c)] = run;
-            run += vals[c];
-            if (vals[c] > 0) binlist[pos++] = first + c;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < n; e += kScanThreads) binstart[base + e] = stage[scan_slot(e)];
-        __syncthreads();
-        carry += total;
-        carry_ne += ne_total;
+    for (int i = 0; i < kMaxRowsPerScanThread; ++i) {
+        const int l = t + i * kScanThreads;
+        mk[i] = l < nft ? rowmark[l] : (uint8_t)0;
     }
-    if (threadIdx.x == 0) {
+    const int flag0 = t == 0 ? flags[0] : 0;
+    int carry = 0, carry_ne = 0;
+    if (nbins <= (int64_t)kScanHoist * PASS) {
+        int h[kScanHoist][kScanChunk];
+#pragma unroll
+        for (int p = 0; p < kScanHoist; ++p)
+#pragma unroll
+            for (int k = 0; k < kScanChunk; ++k) {
+                const int64_t e = (int64_t)p * PASS + k * kScanThreads + t;
+                h[p][k] = e < nbins ? bincount[e] : 0;
+            }
+#pragma unroll
+        for (int p = 0; p < kScanHoist; ++p)
+#pragma unroll
+            for (int k = 0; k < kScanChunk; ++k) {
+                const int64_t e = (int64_t)p * PASS + k * kScanThreads + t;
+                if (e < nbins) bincount[e] = 0;
+            }
+#pragma unroll
+        for (int p = 0; p < kScanHoist; ++p) {
+            const int64_t base = (int64_t)p * PASS;
+            if (base < nbins)
+                scan_pass(h[p], base, (int)((nbins - base) < PASS ? (nbins - base) : PASS), stage, lds, carry,
+                          carry_ne, binstart, binlist);
+        }
+    } else {
+        for (int64_t base = 0; base < nbins; base += PASS) {
+            int h[kScanChunk];
+#pragma unroll
+            for (int k = 0; k < kScanChunk; ++k) {
+                const int64_t e = base + k * kScanThreads + t;
+                h[k] = e < nbins ? bincount[e] : 0;
+                if (e < nbins) bincount[e] = 0;
+            }
+            scan_pass(h, base, (int)((nbins - base) < PASS ? (nbins - base) : PASS), stage, lds, carry, carry_ne,
+                      binstart, binlist);
+        }
+    }
+    if (t == 0) {
         binstart[nbins] = carry;
         binlist[nbins] = carry_ne;
-        flags[1] = flags[0];
+        flags[1] = flag0;
         flags[0] = 0;
     }
     // A theta row l is read by the gather iff some point's first tap row is
-    // within w - 1 rows below it (cyclically).  The marks are staged in LDS
-    // (coalesced) so the w-wide window reads hit LDS, not global memory.
+    // within w - 1 rows below it (cyclically).  The marks go through LDS so
+    // the w-wide window reads hit LDS, not global memory.
     uint8_t *marks = reinterpret_cast<uint8_t *>(stage);
-    __syncthreads();
-    for (int l = threadIdx.x; l < nft; l += kScanThreads) {
-        marks[l] = rowmark[l];
-        rowmark[l] = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxRowsPerScanThread; ++i) {
+        const int l = t + i * kScanThreads;
+        if (l < nft) {
+            marks[l] = mk[i];
+            rowmark[l] = 0;
+        }
     }
     __syncthreads();
-    for (int l = threadIdx.x; l < nft; l += kScanThreads) {
-        uint8_t t = 0;
-        for (int a = 0; a < w; ++a) t |= marks[(l - a + nft) & (nft - 1)];
-        rowtouched[l] = t;
+    for (int l = t; l < nft; l += kScanThreads) {
+        uint8_t v = 0;
+        for (int a = 0; a < w; ++a) v |= marks[(l - a + nft) & (nft - 1)];
+        rowtouched[l] = v;
     }
 }
 
