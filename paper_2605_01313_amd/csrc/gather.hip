@@ -65,9 +65,8 @@ __device__ inline int column_rotation(int it, int ip) { return ((it >> 1) ^ (ip 
 // blk: this workgroup's index in the stage (8 * ceil(nbins / 8) of them).
 template <typename T, int W, int FG>
 __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, const PointRec<T> *__restrict__ rec,
-                                   const int32_t *__restrict__ perm, const int32_t *__restrict__ binstart,
-                                   const int32_t *__restrict__ binlist, void *__restrict__ out,
-                                   const GatherParams &gp)
+                                   const int32_t *__restrict__ perm, const int32_t *__restrict__ binlist,
+                                   void *__restrict__ out, const GatherParams &gp)
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *tiles = reinterpret_cast<cplx<T> *>(smem_raw);
@@ -83,10 +82,19 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
     const int k = blk >> 3;
     const int item = (blk & 7) * per + k;
     if (k >= per || item >= n_ne) return;
-    const int bin = binlist[item];
-    const int start = binstart[bin];
-    const int cnt = binstart[bin + 1] - start;
+    const int4 bi = bin_items(binlist, gp.nbins)[item];  // {bin, first record, count, 0}
+    const int bin = bi.x;
+    const int start = bi.y;
+    const int cnt = bi.z;
     if (cnt == 0) return;
+    // the first chunk's records and destinations are requested now, so that
+    // they arrive with the patch instead of after it
+    PointRec<T> q0{};
+    int d0 = 0;
+    if ((int)threadIdx.x < cnt) {
+        q0 = rec[start + (int)threadIdx.x];
+        d0 = perm[start + (int)threadIdx.x];
+    }
     const int bt = bin / gp.nbins_phi, bp = bin - bt * gp.nbins_phi;
     const int r0 = bt * gp.tile_t, c0 = bp * gp.tile_p;
     const int TR = gp.tile_t + W - 1, TC = gp.tile_p + W - 1;
@@ -98,6 +106,7 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
     constexpr int NK = lds_lane_group<T>();
     __shared__ int bucket[NK];  // per bank key: count, then start
     __shared__ short slot[kGatherThreads];  // lane -> point of the chunk (-1: none)
+    __shared__ int dsts[kGatherThreads];    // destination of each point of the chunk
     const int64_t field_stride = (int64_t)gp.nft * gp.nfp;
 
     // FG fields per pass; the last pass may hold fewer (fg)
@@ -148,7 +157,13 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
             __syncthreads();
             int key = 0, rank = 0;
             if (t < n) {
-                const PointRec<T> q = rec[start + base + t];
+                PointRec<T> q = q0;
+                int d = d0;
+                if (base > 0) {
+                    q = rec[start + base + t];
+                    d = perm[start + base + t];
+                }
+                dsts[t] = d;
                 const bool qbad = !(q.vt == q.vt) || !(q.vp == q.vp);
                 key = qbad ? 0 : ((q.it - r0) * TC + (q.ip - c0) + column_rotation(q.it, q.ip)) & (NK - 1);
                 rank = atomicAdd(&bucket[key], 1);
@@ -175,7 +190,7 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
             if (mine < 0) continue;
             const int r = base + mine;
             const PointRec<T> pr = rec[start + r];
-            const int dst = perm[start + r];
+            const int dst = dsts[mine];
             const bool bad = !(pr.vt == pr.vt) || !(pr.vp == pr.vp);
             const int lr = bad ? 0 : pr.it - r0;
             const int lc = bad ? 0 : pr.ip - c0;
@@ -233,11 +248,10 @@ template <typename T, int W, int FG>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(const cplx<T> *__restrict__ grid,
                                                            const PointRec<T> *__restrict__ rec,
                                                            const int32_t *__restrict__ perm,
-                                                           const int32_t *__restrict__ binstart,
                                                            const int32_t *__restrict__ binlist,
                                                            void *__restrict__ out, GatherParams gp)
 {
-    gather_body<T, W, FG>((int)blockIdx.x, grid, rec, perm, binstart, binlist, out, gp);
+    gather_body<T, W, FG>((int)blockIdx.x, grid, rec, perm, binlist, out, gp);
 }
 
 // Member j of a group class owns workgroups [j * per, (j + 1) * per); per is
@@ -248,15 +262,15 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_group(const GatherJob
     const int j = (int)blockIdx.x / per;
     const GatherJob J = jobs[j];
     gather_body<T, W, FG>((int)blockIdx.x - j * per, (const cplx<T> *)J.grid, (const PointRec<T> *)J.rec,
-                          J.perm, J.binstart, J.binlist, J.out, J.gp);
+                          J.perm, J.binlist, J.out, J.gp);
 }
 
 // jobs == nullptr: one plan (the pointer arguments); otherwise n_members
 // members of one group class described by jobs (device memory).
 template <typename T, int W, int FG>
 static hipError_t launch_wf(const GatherParams &gp, const void *grid, const void *rec,
-                            const int32_t *perm, const int32_t *binstart, const int32_t *binlist,
-                            void *out, const GatherJob *jobs, int n_members, hipStream_t s)
+                            const int32_t *perm, const int32_t *binlist, void *out, const GatherJob *jobs,
+                            int n_members, hipStream_t s)
 {
     const size_t lds = sizeof(cplx<T>) * (size_t)(gp.tile_t + W - 1) * (gp.tile_p + W - 1) * FG;
     const int per = (int)(8 * ((gp.nbins + 7) / 8));
@@ -270,32 +284,32 @@ static hipError_t launch_wf(const GatherParams &gp, const void *grid, const void
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, dim3((unsigned)per), dim3(kGatherThreads), lds, s, (const cplx<T> *)grid,
-                           (const PointRec<T> *)rec, perm, binstart, binlist, out, gp);
+                           (const PointRec<T> *)rec, perm, binlist, out, gp);
     }
     return hipGetLastError();
 }
 
 template <typename T, int W>
 static hipError_t launch_w(const GatherParams &gp, const void *grid, const void *rec, const int32_t *perm,
-                           const int32_t *binstart, const int32_t *binlist, void *out, const GatherJob *jobs,
+                           const int32_t *binlist, void *out, const GatherJob *jobs,
                            int n_members, hipStream_t s)
 {
     switch (gp.fields_per_pass) {
-    case 1: return launch_wf<T, W, 1>(gp, grid, rec, perm, binstart, binlist, out, jobs, n_members, s);
-    case 2: return launch_wf<T, W, 2>(gp, grid, rec, perm, binstart, binlist, out, jobs, n_members, s);
-    case 3: return launch_wf<T, W, 3>(gp, grid, rec, perm, binstart, binlist, out, jobs, n_members, s);
-    case 4: return launch_wf<T, W, 4>(gp, grid, rec, perm, binstart, binlist, out, jobs, n_members, s);
+    case 1: return launch_wf<T, W, 1>(gp, grid, rec, perm, binlist, out, jobs, n_members, s);
+    case 2: return launch_wf<T, W, 2>(gp, grid, rec, perm, binlist, out, jobs, n_members, s);
+    case 3: return launch_wf<T, W, 3>(gp, grid, rec, perm, binlist, out, jobs, n_members, s);
+    case 4: return launch_wf<T, W, 4>(gp, grid, rec, perm, binlist, out, jobs, n_members, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
 static hipError_t launch_t(const GatherParams &gp, const void *grid, const void *rec, const int32_t *perm,
-                           const int32_t *binstart, const int32_t *binlist, void *out, const GatherJob *jobs,
+                           const int32_t *binlist, void *out, const GatherJob *jobs,
                            int n_members, hipStream_t s)
 {
     switch (gp.w) {
-#define NUFFT2_W(X) case X: return launch_w<T, X>(gp, grid, rec, perm, binstart, binlist, out, jobs, n_members, s);
+#define NUFFT2_W(X) case X: return launch_w<T, X>(gp, grid, rec, perm, binlist, out, jobs, n_members, s);
         NUFFT2_W(2) NUFFT2_W(3) NUFFT2_W(4) NUFFT2_W(5) NUFFT2_W(6) NUFFT2_W(7) NUFFT2_W(8)
         NUFFT2_W(9) NUFFT2_W(10) NUFFT2_W(11) NUFFT2_W(12) NUFFT2_W(13) NUFFT2_W(14)
         NUFFT2_W(15) NUFFT2_W(16)
@@ -305,12 +319,11 @@ static hipError_t launch_t(const GatherParams &gp, const void *grid, const void 
 }
 
 hipError_t launch_gather(int prec, const GatherParams &gp, const void *grid, const void *rec,
-                         const int32_t *perm, const int32_t *binstart, const int32_t *binlist,
-                         void *out, hipStream_t s)
+                         const int32_t *perm, const int32_t *binlist, void *out, hipStream_t s)
 {
     if (gp.n_pts == 0) return hipSuccess;
-    if (prec == 1) return launch_t<float>(gp, grid, rec, perm, binstart, binlist, out, nullptr, 0, s);
-    return launch_t<double>(gp, grid, rec, perm, binstart, binlist, out, nullptr, 0, s);
+    if (prec == 1) return launch_t<float>(gp, grid, rec, perm, binlist, out, nullptr, 0, s);
+    return launch_t<double>(gp, grid, rec, perm, binlist, out, nullptr, 0, s);
 }
 
 // ---- vector rotation at the departure points (section 3, matrix Q) --------
@@ -362,8 +375,8 @@ hipError_t launch_gather_group(int prec, const GatherParams &gp, const GatherJob
                                hipStream_t s)
 {
     if (n_members < 1 || !jobs) return hipErrorInvalidValue;
-    if (prec == 1) return launch_t<float>(gp, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
-    return launch_t<double>(gp, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
+    if (prec == 1) return launch_t<float>(gp, nullptr, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
+    return launch_t<double>(gp, nullptr, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
 }
 
 }  // namespace nufft2

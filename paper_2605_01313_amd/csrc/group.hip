@@ -367,7 +367,6 @@ NUFFT2_API nufft2_status nufft2_group_exec(nufft2_group g, const void *const *co
             gj.grid = p->grid;
             gj.rec = p->rec;
             gj.perm = p->perm;
-            gj.binstart = p->binstart;
             gj.binlist = p->binlist;
             gj.out = out_dev[i];
             gj.gp = plan_gather_params(p);

@@ -32,6 +32,23 @@ struct SetptsParams {
     int64_t n;
 };
 
+// The bin list of a plan: nbins + 1 int32 (the non-empty bins in order, then
+// their number), padded to 16 bytes, then nbins int4 {bin, first record,
+// record count, 0} for the non-empty bins in the same order.
+__host__ __device__ inline int64_t bin_items_offset(int64_t nbins) { return (nbins + 1 + 3) & ~(int64_t)3; }
+__host__ __device__ inline int4 *bin_items(int32_t *binlist, int64_t nbins)
+{
+    return reinterpret_cast<int4 *>(binlist + bin_items_offset(nbins));
+}
+__host__ __device__ inline const int4 *bin_items(const int32_t *binlist, int64_t nbins)
+{
+    return reinterpret_cast<const int4 *>(binlist + bin_items_offset(nbins));
+}
+inline size_t binlist_bytes(int64_t nbins)
+{
+    return sizeof(int32_t) * (size_t)bin_items_offset(nbins) + sizeof(int4) * (size_t)nbins;
+}
+
 // ---- launchers (each returns the hipError_t of its launch) ----
 hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, const double *theta,
                          int32_t *bincount, int32_t *binstart, int32_t *binlist, int64_t nbins,
@@ -108,17 +125,17 @@ struct GatherParams {
     int32_t real_output;
 };
 
-// binstart has nbins + 1 entries; bin b holds records binstart[b] .. binstart[b+1]-1.
-// binlist holds the non-empty bins in increasing order, their number in entry nbins.
+// binlist holds the non-empty bins in increasing order and their number in
+// entry nbins; after it (16-byte aligned, see bin_items) one int4 per
+// non-empty bin in the same order: {bin, first record, record count, 0}.
 hipError_t launch_gather(int prec, const GatherParams &gp, const void *grid, const void *rec,
-                         const int32_t *perm, const int32_t *binstart, const int32_t *binlist,
-                         void *out, hipStream_t s);
+                         const int32_t *perm, const int32_t *binlist, void *out, hipStream_t s);
 
 // One member of a group class for the gather (device memory).  Members of a
 // class share every GatherParams field except n_pts.
 struct GatherJob {
     const void *grid, *rec;
-    const int32_t *perm, *binstart, *binlist;
+    const int32_t *perm, *binlist;
     void *out;
     GatherParams gp;
 };

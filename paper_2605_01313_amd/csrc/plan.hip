@@ -454,7 +454,7 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
               dev_alloc(p, &p->grid, cs * (size_t)p->F * p->nft * p->nfp) &&
               dev_alloc(p, (void **)&p->bincount, sizeof(int32_t) * (size_t)p->nbins) &&
               dev_alloc(p, (void **)&p->binstart, sizeof(int32_t) * (size_t)(p->nbins + 1)) &&
-              dev_alloc(p, (void **)&p->binlist, sizeof(int32_t) * (size_t)(p->nbins + 1)) &&
+              dev_alloc(p, (void **)&p->binlist, binlist_bytes(p->nbins)) &&
               dev_alloc(p, (void **)&p->rowmark, (size_t)p->nft) &&
               dev_alloc(p, (void **)&p->rowtouched, (size_t)p->nft) &&
               dev_alloc(p, (void **)&p->flags, sizeof(int32_t) * 4);
@@ -475,7 +475,7 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
             (e = hipMemsetAsync(p->rowmark, 0, (size_t)p->nft, ps)) != hipSuccess ||
             (e = hipMemsetAsync(p->bincount, 0, sizeof(int32_t) * (size_t)p->nbins, ps)) != hipSuccess ||
             (e = hipMemsetAsync(p->binstart, 0, sizeof(int32_t) * (size_t)(p->nbins + 1), ps)) != hipSuccess ||
-            (e = hipMemsetAsync(p->binlist, 0, sizeof(int32_t) * (size_t)(p->nbins + 1), ps)) != hipSuccess ||
+            (e = hipMemsetAsync(p->binlist, 0, binlist_bytes(p->nbins), ps)) != hipSuccess ||
             (e = hipMemsetAsync(p->flags, 0, sizeof(int32_t) * 4, ps)) != hipSuccess ||
             (e = hipStreamSynchronize(ps)) != hipSuccess)
             st = NUFFT2_ERR_HIP;
@@ -592,7 +592,7 @@ NUFFT2_API nufft2_status nufft2_exec(nufft2_handle p, const void *coeffs_dev, vo
     if (e != hipSuccess) return fail_hip(p, e);
     const GatherParams gp = plan_gather_params(p);
     slot = prof_begin(p, 3);
-    e = launch_gather(p->prec, gp, p->grid, p->rec, p->perm, p->binstart, p->binlist, out_dev,
+    e = launch_gather(p->prec, gp, p->grid, p->rec, p->perm, p->binlist, out_dev,
                       p->stream);
     prof_end(p, slot);
     if (e != hipSuccess) return fail_hip(p, e);

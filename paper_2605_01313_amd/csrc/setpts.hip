@@ -184,7 +184,7 @@ __device__ constexpr int scan_slot(int e) { return e + e / kScanChunk; }
 // thread, writes the starts (coalesced) and the non-empty bins.
 __device__ __attribute__((always_inline)) inline void scan_pass(const int (&in)[kScanChunk], int64_t base, int n, int *stage, int (*lds)[33],
                                  int &carry, int &carry_ne, int32_t *__restrict__ binstart,
-                                 int32_t *__restrict__ binlist)
+                                 int32_t *__restrict__ binlist, int4 *__restrict__ items)
 {
 #pragma unroll
     for (int k = 0; k < kScanChunk; ++k) stage[scan_slot(k * kScanThreads + (int)threadIdx.x)] = in[k];
@@ -206,8 +206,12 @@ __device__ __attribute__((always_inline)) inline void scan_pass(const int (&in)[
 #pragma unroll
     for (int c = 0; c < kScanChunk; ++c) {
         stage[scan_slot((int)threadIdx.x * kScanChunk + c)] = run;
+        if (vals[c] > 0) {
+            binlist[pos] = first + c;
+            items[pos] = make_int4(first + c, run, vals[c], 0);
+            ++pos;
+        }
         run += vals[c];
-        if (vals[c] > 0) binlist[pos++] = first + c;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < n; e += kScanThreads) binstart[base + e] = stage[scan_slot(e)];
@@ -238,6 +242,7 @@ __device__ __attribute__((always_inline)) inline void bin_scan_body(int32_t *__r
         mk[i] = l < nft ? rowmark[l] : (uint8_t)0;
     }
     const int flag0 = t == 0 ? flags[0] : 0;
+    int4 *items = bin_items(binlist, nbins);
     int carry = 0, carry_ne = 0;
     if (nbins <= (int64_t)kScanHoist * PASS) {
         int h[kScanHoist][kScanChunk];
@@ -260,7 +265,7 @@ __device__ __attribute__((always_inline)) inline void bin_scan_body(int32_t *__r
             const int64_t base = (int64_t)p * PASS;
             if (base < nbins)
                 scan_pass(h[p], base, (int)((nbins - base) < PASS ? (nbins - base) : PASS), stage, lds, carry,
-                          carry_ne, binstart, binlist);
+                          carry_ne, binstart, binlist, items);
         }
     } else {
         for (int64_t base = 0; base < nbins; base += PASS) {
@@ -272,7 +277,7 @@ __device__ __attribute__((always_inline)) inline void bin_scan_body(int32_t *__r
                 if (e < nbins) bincount[e] = 0;
             }
             scan_pass(h, base, (int)((nbins - base) < PASS ? (nbins - base) : PASS), stage, lds, carry, carry_ne,
-                      binstart, binlist);
+                      binstart, binlist, items);
         }
     }
     if (t == 0) {
