@@ -676,11 +676,13 @@ static hipError_t launch_analysis_t(const AnalysisParams &ap, const void *vals, 
         const hipError_t e = launch_analysis_rows_t<T, LOGN>(ap, vals, tws, A, s);
         if (e != hipSuccess) return e;
     }
-    // theta step: columns per workgroup so that a workgroup has 64..512 threads
+    // theta step: columns per workgroup so that a workgroup has 64..512
+    // threads and at most 80 KB of LDS (two workgroups per CU); wider tiles
+    // make longer row segments of A and of the output
     int cb = 1;
     while (N * cb / kElemsPerThread < 64) cb *= 2;
     while (cb < 16 && N * cb * 2 / kElemsPerThread <= 512 &&
-           sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * cb * 2 + tw_lds_len(N)) <= 65536)
+           sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * cb * 2 + tw_lds_len(N)) <= 80 * 1024)
         cb *= 2;
     int lcb = 0;
     while ((1 << lcb) < cb) ++lcb;

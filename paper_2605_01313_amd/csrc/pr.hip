@@ -159,9 +159,13 @@ __global__ __launch_bounds__(256) void k_pr_rhs(const C2<T> *__restrict__ e, dou
 // sin parts.  fac = [4 classes][3][N + 1 + kPrPad]: L(j, j-2), L(j, j-4),
 // 1 / D(j), zero outside the class range (so the chain runs over all j of
 // its parity and writes zeros there).  z is kept in rhs between the sweeps.
+// The loads do not depend on the recurrence, so each sweep reads a group of
+// kPrUnroll steps ahead of the group it computes.
+constexpr int kPrUnroll = 8;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_pr_solve(double *__restrict__ rhs, const double *__restrict__ fac,
-                                                  T *__restrict__ out, PrParams p)
+__global__ __launch_bounds__(64) void k_pr_solve(double *__restrict__ rhs, const double *__restrict__ fac,
+                                                 T *__restrict__ out, PrParams p)
 {
     const int64_t W = p.M + 1, H = p.N + 1;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -176,28 +180,94 @@ __global__ __launch_bounds__(256) void k_pr_solve(double *__restrict__ rhs, cons
     const double *DI = L2 + FL;
     double *rc = rhs + (int64_t)f * 2 * H * W + m;
     double *rs = rc + H * W;
-    double yc1 = 0, yc2 = 0, ys1 = 0, ys2 = 0;  // y at j - 2, j - 4
-    int j = par;
-    for (; j <= p.N; j += 2) {
-        const double l1 = L1[j], l2 = L2[j], di = DI[j];
-        const double yc = rc[(int64_t)j * W] - l1 * yc1 - l2 * yc2;
-        const double ys = rs[(int64_t)j * W] - l1 * ys1 - l2 * ys2;
-        rc[(int64_t)j * W] = yc * di;
-        rs[(int64_t)j * W] = ys * di;
-        yc2 = yc1; yc1 = yc;
-        ys2 = ys1; ys1 = ys;
+    const int nsteps = (p.N - par) / 2 + 1;  // j = par + 2 k, k < nsteps
+    constexpr int U = kPrUnroll;
+
+    // forward: y_j = r_j - L(j, j-2) y_{j-2} - L(j, j-4) y_{j-4};  z_j = y_j / D(j)
+    double yc1 = 0, yc2 = 0, ys1 = 0, ys2 = 0;
+    double ac[U], as[U], a1[U], a2[U], ad[U];
+    auto load_fwd = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u < nsteps ? k0 + u : nsteps - 1;
+            const int j = par + 2 * k;
+            ac[u] = rc[(int64_t)j * W];
+            as[u] = rs[(int64_t)j * W];
+            a1[u] = L1[j];
+            a2[u] = L2[j];
+            ad[u] = DI[j];
+        }
+    };
+    load_fwd(0);
+    for (int k0 = 0; k0 < nsteps; k0 += U) {
+        double bc[U], bs[U], b1[U], b2[U], bd[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            bc[u] = ac[u];
+            bs[u] = as[u];
+            b1[u] = a1[u];
+            b2[u] = a2[u];
+            bd[u] = ad[u];
+        }
+        if (k0 + U < nsteps) load_fwd(k0 + U);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k0 + u < nsteps) {
+                const int j = par + 2 * (k0 + u);
+                const double yc = bc[u] - b1[u] * yc1 - b2[u] * yc2;
+                const double ys = bs[u] - b1[u] * ys1 - b2[u] * ys2;
+                rc[(int64_t)j * W] = yc * bd[u];
+                rs[(int64_t)j * W] = ys * bd[u];
+                yc2 = yc1;
+                yc1 = yc;
+                ys2 = ys1;
+                ys1 = ys;
+            }
+        }
     }
+    // the forward stores and the backward loads are the same thread's
+    // addresses, so program order makes them visible
+
+    // backward: x_j = z_j - L(j+2, j) x_{j+2} - L(j+4, j) x_{j+4}
     T *oc = out + (int64_t)f * 2 * H * W + m;
     T *os = oc + H * W;
-    double xc1 = 0, xc2 = 0, xs1 = 0, xs2 = 0;  // x at j + 2, j + 4
-    for (j -= 2; j >= 0; j -= 2) {
-        const double l1 = L1[j + 2], l2 = L2[j + 4];
-        const double xc = rc[(int64_t)j * W] - l1 * xc1 - l2 * xc2;
-        const double xs = rs[(int64_t)j * W] - l1 * xs1 - l2 * xs2;
-        oc[(int64_t)j * W] = (T)xc;
-        os[(int64_t)j * W] = (T)(m == 0 ? 0.0 : xs);
-        xc2 = xc1; xc1 = xc;
-        xs2 = xs1; xs1 = xs;
+    double xc1 = 0, xc2 = 0, xs1 = 0, xs2 = 0;
+    auto load_bwd = [&](int k0) {  // steps k0, k0 - 1, ...
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 - u >= 0 ? k0 - u : 0;
+            const int j = par + 2 * k;
+            ac[u] = rc[(int64_t)j * W];
+            as[u] = rs[(int64_t)j * W];
+            a1[u] = L1[j + 2];
+            a2[u] = L2[j + 4];
+        }
+    };
+    load_bwd(nsteps - 1);
+    for (int k0 = nsteps - 1; k0 >= 0; k0 -= U) {
+        double bc[U], bs[U], b1[U], b2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            bc[u] = ac[u];
+            bs[u] = as[u];
+            b1[u] = a1[u];
+            b2[u] = a2[u];
+        }
+        if (k0 - U >= 0) load_bwd(k0 - U);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k0 - u >= 0) {
+                const int j = par + 2 * (k0 - u);
+                const double xc = bc[u] - b1[u] * xc1 - b2[u] * xc2;
+                const double xs = bs[u] - b1[u] * xs1 - b2[u] * xs2;
+                oc[(int64_t)j * W] = (T)xc;
+                os[(int64_t)j * W] = (T)(m == 0 ? 0.0 : xs);
+                xc2 = xc1;
+                xc1 = xc;
+                xs2 = xs1;
+                xs1 = xs;
+            }
+        }
     }
 }
 
@@ -268,7 +338,7 @@ template <typename T> hipError_t launch_solve(double *rhs, const double *fac, vo
                                               hipStream_t s)
 {
     const int threads = p.F * 2 * (p.M + 1);
-    hipLaunchKernelGGL(k_pr_solve<T>, dim3((threads + 255) / 256), dim3(256), 0, s, rhs, fac, (T *)out, p);
+    hipLaunchKernelGGL(k_pr_solve<T>, dim3((threads + 63) / 64), dim3(64), 0, s, rhs, fac, (T *)out, p);
     return hipGetLastError();
 }
 
