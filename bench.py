@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 METRIC = "departure-pt interps/s (points*fields) at eps 1e-6 FP32 vs 1e-12 FP64; p99 latency"
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # dense matrix-core peaks of the MI355X
+PROFILE_EVERY = 10   # timed steps per step with the dominant kernel bracketed by events
 STAGES = ("setpts", "theta_pass", "phi_pass", "gather")
 SINGLE_KERNEL_STAGES = ("theta_pass", "phi_pass", "gather")
 KERNEL_SOURCES = {"setpts": "setpts.hip", "theta_pass": "fft.hip", "phi_pass": "fft.hip",
@@ -116,11 +117,18 @@ class Runner:
         # chain of three small kernels (bin count, scan, scatter), each
         # shorter than any of the other stages' one kernel
         dominant = max(SINGLE_KERNEL_STAGES, key=avg.get)
-        # timed region: only the dominant kernel is bracketed
-        self.plan.profile(1 << STAGES.index(dominant))
+        # timed region: the dominant kernel is bracketed with HIP events on the
+        # plan's stream in every PROFILE_EVERY-th step (event records cost a
+        # few microseconds of a 50-microsecond step; a sample keeps the timed
+        # steps close to unobserved ones)
+        mask = 1 << STAGES.index(dominant)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for i in range(steps):
+            if i % PROFILE_EVERY == 0:
+                self.plan.profile(mask)
+            elif i % PROFILE_EVERY == 1:
+                self.plan.profile(0)
             self.step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -469,7 +477,7 @@ def upstream_bench(torch, prec, J=1024, F=3, reps=20):
     theta_d = torch.from_numpy(theta_a + rng.uniform(-0.05, 0.05, P)).to(dev)
     phi_a = torch.from_numpy(phi_a).to(dev)
     theta_a = torch.from_numpy(theta_a).to(dev)
-    plan = Plan(prec, 31, 31, n_fields=F, eps=1e-6 if prec == "fp32" else 1e-12)
+    plan = Plan(prec, K, K, n_fields=F, eps=1e-6 if prec == "fp32" else 1e-12)
     plan.setpts(phi_d, theta_d)
     out = torch.randn((F, P), dtype=cdt, device=dev, generator=gen)
     gl = GLAnalysis(prec, J, n_fields=F)
