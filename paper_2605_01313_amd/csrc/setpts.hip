@@ -178,13 +178,26 @@ constexpr int kScanChunk = 8;
 // its own LDS banks
 __device__ constexpr int scan_slot(int e) { return e + e / kScanChunk; }
 
+// Compacted entries of a pass: three arrays (bin, first record, count) of
+// kCmpLen ints; one padding slot every 32 entries, because the threads of a
+// wave write entries kScanChunk apart (without it they would share 4 of the
+// 32 banks).
+constexpr int kCmpLen = kScanChunk * kScanThreads + kScanChunk * kScanThreads / 32;
+__device__ constexpr int cmp_slot(int e) { return e + e / 32; }
+
 // One pass over PASS = CHUNK * 1024 bins starting at base (n of them):
 // in[k] is this thread's count of bin base + k * 1024 + threadIdx.x (zero
 // past the end).  Stages them in LDS, scans CHUNK consecutive counts per
-// thread, writes the starts (coalesced) and the non-empty bins.
-__device__ __attribute__((always_inline)) inline void scan_pass(const int (&in)[kScanChunk], int64_t base, int n, int *stage, int (*lds)[33],
-                                 int &carry, int &carry_ne, int32_t *__restrict__ binstart,
-                                 int32_t *__restrict__ binlist, int4 *__restrict__ items)
+// thread, and writes the starts (coalesced).  The pass's non-empty bins are
+// compacted in LDS (cmp: bin, first record, count) and written out by
+// consecutive threads: written from the scanning threads directly, each
+// store instruction would touch 64 cache lines (CHUNK entries apart), which
+// made the pass several times slower where most bins hold points.
+__device__ __attribute__((always_inline)) inline void scan_pass(const int (&in)[kScanChunk], int64_t base, int n,
+                                                              int *stage, int *cmp, int (*lds)[33], int &carry,
+                                                              int &carry_ne, int32_t *__restrict__ binstart,
+                                                              int32_t *__restrict__ binlist,
+                                                              int4 *__restrict__ items)
 {
 #pragma unroll
     for (int k = 0; k < kScanChunk; ++k) stage[scan_slot(k * kScanThreads + (int)threadIdx.x)] = in[k];
@@ -201,20 +214,27 @@ __device__ __attribute__((always_inline)) inline void scan_pass(const int (&in)[
     int run = sum, pos = ne;
     block_exclusive_scan2(run, pos, lds, total, ne_total);
     run += carry;
-    pos += carry_ne;
     const int first = (int)base + (int)threadIdx.x * kScanChunk;
 #pragma unroll
     for (int c = 0; c < kScanChunk; ++c) {
         stage[scan_slot((int)threadIdx.x * kScanChunk + c)] = run;
         if (vals[c] > 0) {
-            binlist[pos] = first + c;
-            items[pos] = make_int4(first + c, run, vals[c], 0);
+            const int q = cmp_slot(pos);
+            cmp[q] = first + c;
+            cmp[kCmpLen + q] = run;
+            cmp[2 * kCmpLen + q] = vals[c];
             ++pos;
         }
         run += vals[c];
     }
     __syncthreads();
     for (int e = threadIdx.x; e < n; e += kScanThreads) binstart[base + e] = stage[scan_slot(e)];
+    for (int e = threadIdx.x; e < ne_total; e += kScanThreads) {
+        const int q = cmp_slot(e);
+        const int b = cmp[q], s0 = cmp[kCmpLen + q], c0 = cmp[2 * kCmpLen + q];
+        binlist[carry_ne + e] = b;
+        items[carry_ne + e] = make_int4(b, s0, c0, 0);
+    }
     __syncthreads();
     carry += total;
     carry_ne += ne_total;
@@ -232,6 +252,7 @@ __device__ __attribute__((always_inline)) inline void bin_scan_body(int32_t *__r
 {
     __shared__ int lds[2][33];
     __shared__ int stage[kScanChunk * kScanThreads + kScanThreads];
+    __shared__ int cmp[3 * kCmpLen];  // compacted non-empty bins of a pass
     constexpr int PASS = kScanChunk * kScanThreads;
     const int t = (int)threadIdx.x;
     // the row marks and the non-finite accumulator are read with the counts
@@ -264,8 +285,8 @@ __device__ __attribute__((always_inline)) inline void bin_scan_body(int32_t *__r
         for (int p = 0; p < kScanHoist; ++p) {
             const int64_t base = (int64_t)p * PASS;
             if (base < nbins)
-                scan_pass(h[p], base, (int)((nbins - base) < PASS ? (nbins - base) : PASS), stage, lds, carry,
-                          carry_ne, binstart, binlist, items);
+                scan_pass(h[p], base, (int)((nbins - base) < PASS ? (nbins - base) : PASS), stage, cmp, lds,
+                          carry, carry_ne, binstart, binlist, items);
         }
     } else {
         for (int64_t base = 0; base < nbins; base += PASS) {
@@ -276,8 +297,8 @@ __device__ __attribute__((always_inline)) inline void bin_scan_body(int32_t *__r
                 h[k] = e < nbins ? bincount[e] : 0;
                 if (e < nbins) bincount[e] = 0;
             }
-            scan_pass(h, base, (int)((nbins - base) < PASS ? (nbins - base) : PASS), stage, lds, carry, carry_ne,
-                      binstart, binlist, items);
+            scan_pass(h, base, (int)((nbins - base) < PASS ? (nbins - base) : PASS), stage, cmp, lds, carry,
+                      carry_ne, binstart, binlist, items);
         }
     }
     if (t == 0) {
