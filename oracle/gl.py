@@ -11,7 +11,8 @@ Steps, in the paper's order:
      library step): g_m(theta_j) = (1/2J) sum_k f(phi_k, theta_j) e^{-i m phi_k},
      |m| <= J - 1 (the m = J Nyquist mode is dropped, as on Grid [0]);
   2. in latitude, for each m, the direct inversion of the latitude "DFT"
-     matrix with an LU factorisation (numpy.linalg.solve):  even m take the
+     matrix with an LU factorisation computed once per parity and applied to
+     every m of that parity (scipy.linalg.lu_factor / lu_solve):  even m take the
      cosine basis cos(n theta), n = 0 .. J-1; odd m the sine basis
      sin(n theta), n = 1 .. J (reading R22: the standard DFS parities of
      eq. std_dfs with as many basis functions as latitudes, so that the
@@ -72,21 +73,26 @@ def gl_analysis(values):
     F, J, L = values.shape
     if L != 2 * J:
         raise ValueError("values must be [F][J][2J]")
+    from scipy.linalg import lu_factor, lu_solve
     g = np.fft.fft(values, axis=2) / (2 * J)             # [F, J, 2J]: m mod 2J
     Ce, Co = gl_latitude_matrices(J)
+    lu = (lu_factor(Ce), lu_factor(Co))
     out = np.zeros((F, 2 * J + 1, 2 * J - 1), dtype=np.complex128)
-    for m in range(-(J - 1), J):
-        col = m + J - 1
-        rhs = g[:, :, m % (2 * J)].T                     # [J, F]
-        if m % 2 == 0:
-            a = np.linalg.solve(Ce, rhs)                 # cos(n theta), n = 0..J-1
-            out[:, J, col] = a[0]
-            for n in range(1, J):
-                out[:, J + n, col] = a[n] / 2
-                out[:, J - n, col] = a[n] / 2
-        else:
-            b = np.linalg.solve(Co, rhs)                 # sin(n theta), n = 1..J
-            for n in range(1, J + 1):
-                out[:, J + n, col] = -0.5j * b[n - 1]
-                out[:, J - n, col] = 0.5j * b[n - 1]
+    n = np.arange(1, J)
+    for parity in (0, 1):
+        ms = [m for m in range(-(J - 1), J) if m % 2 == parity]
+        cols = np.array(ms) + J - 1
+        rhs = g[:, :, np.array(ms) % (2 * J)]            # [F, J, #m]
+        rhs = np.moveaxis(rhs, 1, 0).reshape(J, -1)      # [J, F * #m]
+        x = lu_solve(lu[parity], rhs).reshape(J, F, len(ms))
+        if parity == 0:                                  # cos(n theta), n = 0..J-1
+            out[:, J, cols] = x[0]
+            half = np.moveaxis(x[1:], 0, 1) / 2          # [F, J-1, #m]
+            out[:, (J + n)[:, None], cols[None, :]] = half
+            out[:, (J - n)[:, None], cols[None, :]] = half
+        else:                                            # sin(n theta), n = 1..J
+            b = np.moveaxis(x, 0, 1)                     # [F, J, #m], row k <-> n = k + 1
+            nn = np.arange(1, J + 1)
+            out[:, (J + nn)[:, None], cols[None, :]] = -0.5j * b
+            out[:, (J - nn)[:, None], cols[None, :]] = 0.5j * b
     return out

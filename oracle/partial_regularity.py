@@ -151,16 +151,19 @@ def std_to_pr(fc, fs):
     N, M = fc.shape[0] - 1, fc.shape[1] - 1
     pc = np.zeros_like(fc)
     ps = np.zeros_like(fs)
-    systems = {}
-    for m in range(M + 1):
-        key = 0 if m == 0 else 1 if m == 1 else 2 + (m % 2)
-        if key not in systems:
-            systems[key] = normal_system(m, N)
-        G, R = systems[key]
-        lo, hi = pr_range(m, N)
-        pc[lo:hi + 1, m] = np.linalg.solve(G, R @ fc[:, m])
-        if m > 0:
-            ps[lo:hi + 1, m] = np.linalg.solve(G, R @ fs[:, m])
+    # the system depends only on the class of m (0, 1, even >= 2, odd >= 3):
+    # one LU factorisation per class, applied to all of its columns
+    from scipy.linalg import lu_factor, lu_solve
+    classes = {0: [0], 1: [1] if M >= 1 else [], 2: list(range(2, M + 1, 2)), 3: list(range(3, M + 1, 2))}
+    for key, ms in classes.items():
+        if not ms:
+            continue
+        G, R = normal_system(ms[0], N)
+        lu = lu_factor(G)
+        lo, hi = pr_range(ms[0], N)
+        pc[lo:hi + 1, ms] = lu_solve(lu, R @ fc[:, ms])
+        if key > 0:
+            ps[lo:hi + 1, ms] = lu_solve(lu, R @ fs[:, ms])
     return pc, ps
 
 

@@ -32,7 +32,7 @@ def torch_dev():
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
-@pytest.mark.parametrize("J,F", [(16, 1), (64, 3), (256, 2), (512, 1)])
+@pytest.mark.parametrize("J,F", [(16, 1), (64, 3), (256, 2), (512, 1), (1024, 1)])
 def test_gl_analysis_matches_oracle(torch_dev, oracle_mod, prec, tol, J, F):
     torch, dev = torch_dev
     from paper_2605_01313_amd import GLAnalysis

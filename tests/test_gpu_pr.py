@@ -67,7 +67,7 @@ def kappa_max(oracle_mod, N):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("N,M,F", [(15, 15, 1), (63, 63, 3), (100, 37, 2), (255, 255, 1)])
+@pytest.mark.parametrize("N,M,F", [(15, 15, 1), (63, 63, 3), (100, 37, 2), (255, 255, 1), (1023, 1023, 1)])
 def test_project_and_synthesize_match_oracle(torch_dev, oracle_mod, prec, N, M, F):
     torch, dev = torch_dev
     from paper_2605_01313_amd import PartialRegularity

@@ -137,9 +137,9 @@ def test_least_squares_fit_of_the_basis():
 PLANTS = [
     ("th = np.sort(np.arccos(z)).astype(np.longdouble)", "th = np.arccos(z).astype(np.longdouble)"),  # z order
     ("g = np.fft.fft(values, axis=2) / (2 * J)", "g = np.fft.fft(values, axis=2) / J"),
-    ("out[:, J + n, col] = -0.5j * b[n - 1]", "out[:, J + n, col] = 0.5j * b[n - 1]"),
+    ("out[:, (J + nn)[:, None], cols[None, :]] = -0.5j * b", "out[:, (J + nn)[:, None], cols[None, :]] = 0.5j * b"),
     ("np.sin(np.outer(th, n + 1))", "np.sin(np.outer(th, n))"),
-    ("if m % 2 == 0:\n            a = np.linalg.solve(Ce, rhs)", "if m % 2 == 1:\n            a = np.linalg.solve(Ce, rhs)"),
+    ("lu = (lu_factor(Ce), lu_factor(Co))", "lu = (lu_factor(Co), lu_factor(Ce))"),          # parities swapped
 ]
 
 
@@ -170,8 +170,11 @@ def test_planted_mistakes_are_caught():
     clean = {}
     exec(compile(src, "gl_clean", "exec"), clean)
     assert _gl_pins_hold(clean)
+    import warnings
     for a, b in PLANTS:
         assert a in src, a
         ns = {}
         exec(compile(src.replace(a, b, 1), "gl_planted", "exec"), ns)
-        assert not _gl_pins_hold(ns), f"planted mistake not caught: {b}"
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")         # a planted basis can be singular
+            assert not _gl_pins_hold(ns), f"planted mistake not caught: {b}"
