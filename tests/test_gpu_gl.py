@@ -4,9 +4,10 @@ the latitude inversion on the matrix cores) against the oracle
 
 Tolerance: the latitude matrices have condition numbers below 5 for every
 supported J, so the coefficients carry a few units of rounding of the plan
-precision times the length of the sums (log2(2J) for the FFT, J for the
-latitude product): 1e-13 (FP64) and 2e-6 (FP32, on FP32-rounded samples),
-relative to the largest coefficient.
+precision, growing like the square root of the length of the J-term
+latitude product (rounding errors of random sign): 1e-13 (FP64) and
+2e-6 max(1, sqrt(J / 256)) (FP32, on FP32-rounded samples), relative to the
+largest coefficient.
 """
 import sys
 
@@ -46,7 +47,9 @@ def test_gl_analysis_matches_oracle(torch_dev, oracle_mod, prec, tol, J, F):
     got = gl.exec(torch.from_numpy(vals).to(rdt).to(dev)).cpu().numpy()
     want = oracle_mod.gl_analysis(vals)
     err = np.abs(got - want).max() / np.abs(want).max()
-    say(f"  max err / max coeff {err:.2e}")
+    if prec == "fp32":
+        tol *= max(1.0, np.sqrt(J / 256))
+    say(f"  max err / max coeff {err:.2e} (tol {tol:.1e})")
     assert err <= tol
     # every entry is written: a second call into a buffer of NaNs gives the same
     cdt = torch.complex64 if prec == "fp32" else torch.complex128
