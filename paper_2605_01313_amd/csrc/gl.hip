@@ -37,19 +37,24 @@ template <> struct Acc<double> {
     static __device__ inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
-constexpr int kTileM = 64;  // coefficient rows per workgroup
-constexpr int kTileN = 64;  // real columns per workgroup (32 modes x re/im)
-constexpr int kTileK = 16;  // samples per LDS stage
+constexpr int kTileM = 64;   // coefficient rows per workgroup
+constexpr int kTileN = 128;  // real columns per workgroup (64 modes x re/im)
+constexpr int kTileK = 16;   // samples per LDS stage
+constexpr int kThreads = 256;
+constexpr int kALoads = kTileM * kTileK / kThreads;  // staged A elements per thread
+constexpr int kBLoads = kTileK * kTileN / kThreads;  // staged B elements per thread
 
-// One workgroup (4 waves) computes a 64 x 64 tile of C = inv[p] * B_p for
+// One workgroup (4 waves) computes a 64 x 128 tile of C = inv[p] * B_p for
 // field f and parity p, where B_p[j][2t + q] is part q (re, im) of the
 // phi-step sample A[f][j][c], c = 2t + 1 - p the t-th column of parity p
 // (c = m + J - 1 and J is even, so even m sit in odd c).  Wave w owns rows
-// 32 (w / 2) .. + 31 and columns 32 (w % 2) .. + 31 as 2 x 2 MFMA blocks.
+// 32 (w / 2) .. + 31 and columns 64 (w % 2) .. + 63 as 2 x 4 MFMA blocks, so
+// each k-step reads 2 + 4 operands from LDS for 8 MFMAs.  The next K-tile's
+// values are loaded into registers while the current one is multiplied.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gl_latitude(const T *__restrict__ inv, const T *__restrict__ A,
-                                                     T *__restrict__ out, int J, int tiles_m, int tiles_n0,
-                                                     int tiles_n1)
+__global__ __launch_bounds__(kThreads) void k_gl_latitude(const T *__restrict__ inv, const T *__restrict__ A,
+                                                          T *__restrict__ out, int J, int tiles_m, int tiles_n0,
+                                                          int tiles_n1)
 {
     __shared__ T As[kTileM][kTileK + 1];
     __shared__ T Bs[kTileK][kTileN + 2];
@@ -69,41 +74,59 @@ __global__ __launch_bounds__(256) void k_gl_latitude(const T *__restrict__ inv, 
     const T *Af = A + (size_t)f * J * K * 2;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 64;
     using V = typename Acc<T>::V;
-    V acc[2][2];
+    V acc[2][4];
+#pragma unroll
     for (int x = 0; x < 2; ++x)
-        for (int y = 0; y < 2; ++y) acc[x][y] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = V{0, 0, 0, 0};
 
-    for (int j0 = 0; j0 < J; j0 += kTileK) {
-        // stage inv rows i0..i0+63, samples j0..j0+15 and the matching B rows
-        for (int e = tid; e < kTileM * kTileK; e += 256) {
+    // global values of K-tile j0 for this thread's staging slots
+    T ra[kALoads], rb[kBLoads];
+    auto fetch = [&](int j0) {
+#pragma unroll
+        for (int u = 0; u < kALoads; ++u) {
+            const int e = tid + u * kThreads;
             const int r = e / kTileK, k = e - r * kTileK;
             const int i = i0 + r, j = j0 + k;
-            As[r][k] = (i < J && j < J) ? invp[(size_t)i * J + j] : (T)0;
+            ra[u] = (i < J && j < J) ? invp[(size_t)i * J + j] : (T)0;
         }
-        for (int e = tid; e < kTileK * kTileN; e += 256) {
+#pragma unroll
+        for (int u = 0; u < kBLoads; ++u) {
+            const int e = tid + u * kThreads;
             const int k = e / kTileN, cc = e - k * kTileN;
             const int j = j0 + k, col = col0 + cc;
             T v = (T)0;
-            if (j < J && col < ncols) {
-                const int c = (col & ~1) + 1 - p;
-                v = Af[((size_t)j * K + c) * 2 + (col & 1)];
-            }
-            Bs[k][cc] = v;
+            if (j < J && col < ncols) v = Af[((size_t)j * K + ((col & ~1) + 1 - p)) * 2 + (col & 1)];
+            rb[u] = v;
+        }
+    };
+    fetch(0);
+    for (int j0 = 0; j0 < J; j0 += kTileK) {
+#pragma unroll
+        for (int u = 0; u < kALoads; ++u) {
+            const int e = tid + u * kThreads;
+            As[e / kTileK][e % kTileK] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kBLoads; ++u) {
+            const int e = tid + u * kThreads;
+            Bs[e / kTileN][e % kTileN] = rb[u];
         }
         __syncthreads();
+        if (j0 + kTileK < J) fetch(j0 + kTileK);
 #pragma unroll
         for (int kk = 0; kk < kTileK; kk += 4) {
-            T a[2], bv[2];
+            T a[2], bv[4];
 #pragma unroll
             for (int x = 0; x < 2; ++x) a[x] = As[wr + 16 * x + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-            for (int y = 0; y < 2; ++y) bv[y] = Bs[kk + (lane >> 4)][wc + 16 * y + (lane & 15)];
+            for (int y = 0; y < 4; ++y) bv[y] = Bs[kk + (lane >> 4)][wc + 16 * y + (lane & 15)];
 #pragma unroll
             for (int x = 0; x < 2; ++x)
 #pragma unroll
-                for (int y = 0; y < 2; ++y) acc[x][y] = Acc<T>::mfma(a[x], bv[y], acc[x][y]);
+                for (int y = 0; y < 4; ++y) acc[x][y] = Acc<T>::mfma(a[x], bv[y], acc[x][y]);
         }
         __syncthreads();
     }
@@ -112,7 +135,7 @@ __global__ __launch_bounds__(256) void k_gl_latitude(const T *__restrict__ inv, 
     const T scale = (T)1 / (T)(2 * J);
     T *of = out + (size_t)f * (2 * J + 1) * K * 2;
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
+    for (int y = 0; y < 4; ++y) {
         const int col = col0 + wc + 16 * y + (lane & 15);
         if (col >= ncols) continue;
         const int q = col & 1;             // 0: real part of the coefficient, 1: imaginary
@@ -155,8 +178,8 @@ hipError_t launch_t(int J, int F, const void *inv, const void *A, void *out, hip
     const int tiles_n0 = (2 * (J - 1) + kTileN - 1) / kTileN;
     const int tiles_n1 = (2 * J + kTileN - 1) / kTileN;
     const int blocks = F * tiles_m * (tiles_n0 + tiles_n1);
-    hipLaunchKernelGGL(k_gl_latitude<T>, dim3(blocks), dim3(256), 0, s, (const T *)inv, (const T *)A, (T *)out, J,
-                       tiles_m, tiles_n0, tiles_n1);
+    hipLaunchKernelGGL(k_gl_latitude<T>, dim3(blocks), dim3(kThreads), 0, s, (const T *)inv, (const T *)A, (T *)out,
+                       J, tiles_m, tiles_n0, tiles_n1);
     return hipGetLastError();
 }
 
