@@ -58,6 +58,7 @@ bool same_class(const nufft2_plan_s *a, const nufft2_plan_s *b)
            a->fp.theta_ept == b->fp.theta_ept && a->fp.phi_ept == b->fp.phi_ept;
 }
 
+
 // What the tables depend on besides the fixed plan parameters: the call's
 // pointers and point counts, and the members' point workspaces (which
 // setpts may reallocate).
@@ -79,6 +80,20 @@ struct nufft2_group_s {
     size_t table_bytes = 0;
     hipError_t last_err = hipSuccess;
 };
+
+namespace {
+
+// The FFT launch shape of a class: its members' parameters, with the
+// elements per thread chosen for the launch of the whole class.
+FFTParams class_fft_params(const nufft2_group_s *g, const ExecClass &c)
+{
+    const nufft2_plan_s *p = g->m[c.members[0]];
+    FFTParams fp = p->fp;
+    fft_launch_shape(p, (int64_t)c.members.size(), fp);
+    return fp;
+}
+
+}  // namespace
 
 namespace {
 
@@ -345,6 +360,7 @@ NUFFT2_API nufft2_status nufft2_group_exec(nufft2_group g, const void *const *co
         std::vector<ThetaJob> th;
         std::vector<PhiJob> ph;
         std::vector<GatherJob> ga;
+        const FFTParams cfp = class_fft_params(g, c);
         for (int i : c.members) {
             nufft2_plan_s *p = g->m[i];
             ThetaJob tj{};
@@ -354,14 +370,14 @@ NUFFT2_API nufft2_status nufft2_group_exec(nufft2_group g, const void *const *co
             tj.tws = p->tw_t;
             tj.touched = p->rowtouched;
             tj.S = p->S;
-            tj.fp = p->fp;
+            tj.fp = cfp;
             th.push_back(tj);
             PhiJob pj{};
             pj.S = p->S;
             pj.tws = p->tw_p;
             pj.touched = p->rowtouched;
             pj.grid = p->grid;
-            pj.fp = p->fp;
+            pj.fp = cfp;
             ph.push_back(pj);
             GatherJob gj{};
             gj.grid = p->grid;
@@ -395,8 +411,9 @@ NUFFT2_API nufft2_status nufft2_group_exec(nufft2_group g, const void *const *co
             for (auto &c : g->classes) {
                 const nufft2_plan_s *p = g->m[c.members[0]];
                 const int k = (int)c.members.size();
-                hipError_t es = launch_theta_group(c.prec, p->fp, c.d_theta, k, g->stream);
-                if (es == hipSuccess) es = launch_phi_group(c.prec, p->fp, c.d_phi, k, g->stream);
+                const FFTParams cfp = class_fft_params(g, c);
+                hipError_t es = launch_theta_group(c.prec, cfp, c.d_theta, k, g->stream);
+                if (es == hipSuccess) es = launch_phi_group(c.prec, cfp, c.d_phi, k, g->stream);
                 if (es == hipSuccess) es = launch_gather_group(c.prec, plan_gather_params(p), c.d_gather, k, g->stream);
                 if (es != hipSuccess) return es;
             }

@@ -300,6 +300,28 @@ int choose_tile(int32_t requested, int dflt, int nf, bool *bad)
 
 }  // namespace
 
+// Elements per thread of the FFT passes and the phi pass's rows per
+// workgroup, for a launch of `members` plans of p's shape at once: a pass
+// that would launch fewer than kSmallLaunchWaves waves with 16 elements per
+// thread runs with 8, so that it has about twice the waves to hide LDS and
+// memory latency (theta pass: twice the threads per workgroup; phi pass:
+// 2048 instead of 4096 elements per workgroup).
+void nufft2::fft_launch_shape(const nufft2_plan_s *p, int64_t members, FFTParams &fp)
+{
+    const int64_t L = p->nft / 2;
+    const int64_t max_threads = p->prec == NUFFT2_FP32 ? 1024 : 512;
+    const int64_t b = fp.theta_batch;
+    const int64_t theta_waves16 = members * 2 * ((p->Kp + b - 1) / b) * (int64_t)p->F * L * b / 16 / 64;
+    fp.theta_ept = (theta_waves16 < kSmallLaunchWaves && L * b / 8 <= max_threads && L >= 64) ? 8 : 16;
+    const int64_t phi_waves16 = members * (int64_t)p->F * (p->nft / 2) * p->nfp / 16 / 64;
+    fp.phi_ept = (phi_waves16 < kSmallLaunchWaves && p->nfp >= 64) ? 8 : 16;
+    int64_t pb = (fp.phi_ept == 8 ? 2048 : 4096) / p->nfp;
+    if (pb < 1) pb = 1;
+    if (pb > p->nft) pb = p->nft;
+    fp.phi_batch = (int)pb;
+    fp.log_phi_batch = ilog2(pb);
+}
+
 NUFFT2_API const char *nufft2_strerror(nufft2_status s)
 {
     switch (s) {
@@ -421,22 +443,8 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
         }
         fp.theta_batch = (int)b;
         fp.log_theta_batch = ilog2(b);
-        // small transforms: 8 elements per thread instead of 16, so that the
-        // launch has about twice the waves to hide LDS and memory latency
-        const int64_t waves16 = 2 * ((p->Kp + b - 1) / b) * (int64_t)n_fields * L * b / 16 / 64;
-        fp.theta_ept = (waves16 < kSmallLaunchWaves && L * b / 8 <= max_threads && L >= 64) ? 8 : 16;
     }
-    {
-        // phi pass: rows per workgroup so that a workgroup transforms 4096
-        // elements (2048 with 8 elements per thread)
-        const int64_t waves16 = (int64_t)n_fields * (p->nft / 2) * p->nfp / 16 / 64;
-        fp.phi_ept = (waves16 < kSmallLaunchWaves && p->nfp >= 64) ? 8 : 16;
-        int64_t b = (fp.phi_ept == 8 ? 2048 : 4096) / p->nfp;
-        if (b < 1) b = 1;
-        if (b > p->nft) b = p->nft;
-        fp.phi_batch = (int)b;
-        fp.log_phi_batch = ilog2(b);
-    }
+    fft_launch_shape(p, 1, fp);
     {
         const size_t tile = p->csize * (size_t)(tt + w - 1) * (size_t)(tp + w - 1);
         int g = (int)(kGatherLdsLimit / tile);

@@ -61,5 +61,9 @@ nufft2_status plan_reserve_points(nufft2_plan_s *p, int64_t n);
 // Kernel parameters of the plan's setpts for n points and of its gather.
 SetptsParams plan_setpts_params(const nufft2_plan_s *p, int64_t n);
 GatherParams plan_gather_params(const nufft2_plan_s *p);
+// Elements per thread and phi-pass rows per workgroup (fp's theta_ept,
+// phi_ept, phi_batch, log_phi_batch) for `members` plans of p's shape
+// launched at once; fp's other fields are p's.
+void fft_launch_shape(const nufft2_plan_s *p, int64_t members, nufft2::FFTParams &fp);
 
 }  // namespace nufft2
