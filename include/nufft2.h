@@ -18,6 +18,18 @@
  *   3. a w x w "exponential of semicircle" kernel interpolation at each point.
  * The relative l2 error of each field against the exact sum is about eps.
  *
+ * Around the interpolation (declared further down):
+ *   nufft2_group_*     many plans of uneven size as one unit (an ensemble);
+ *   nufft2_autotune    kernel width and gather tiles measured for a problem;
+ *   nufft2_server_*    a request loop with continuous batching under an HBM
+ *                      budget (host buffers in and out);
+ *   nufft2_rotate_uv   the rotation Q of section 3 for interpolated (u, v);
+ *   nufft2_analysis_*  Grid [0] samples -> exp-form coefficients (section 4),
+ *                      with the zonal filter of section 4;
+ *   nufft2_pr_*        the partial-regularity expansion of section 4;
+ *   nufft2_gl_*        Gauss-Legendre grid samples -> exp-form coefficients
+ *                      (section 5, the interpolation for the SHT model).
+ *
  * Every entry point returns a status; arguments are checked before anything
  * is enqueued and nothing is enqueued when a call fails.  Work is enqueued on
  * the plan's HIP stream and is asynchronous with respect to the host.  A plan
