@@ -19,8 +19,9 @@
 // Doing theta first keeps the intermediate at nft x K_phi (half the size of
 // the other order's K_theta x nfp), and only reached rows enter the phi pass.
 //
-// Each transform is a radix-8 Stockham sequence (a radix-2 or -4 stage first
-// when log2 N is not a multiple of 3) with the length fixed at compile time.
+// Each transform is a Stockham sequence of radix-16 stages (radix 8 for
+// kernels with 8 elements per thread), a smaller radix first when log2 N is
+// not a multiple of 4 (3), with the length fixed at compile time.
 // The first stage reads straight from global memory into registers, the
 // middle stages go through LDS (one padding slot every 32 elements against
 // bank conflicts), the last stage writes straight to global memory; both are
@@ -81,18 +82,58 @@ template <typename C> __device__ inline void dft8(C *x)
     x[7] = csub(e3, w3);
 }
 
+// Radix 16 as 4 x 4: with r = 4a + b and q = c + 4d,
+// y_{c + 4d} = sum_b e^{2 pi i b d / 4} [e^{2 pi i b c / 16} sum_a x_{4a + b} e^{2 pi i a c / 4}].
+template <typename C> __device__ inline void dft16(C *x)
+{
+    using R = decltype(x[0].x);
+    const R c1 = (R)0.92387953251128675612818318939678828682;  // cos(pi / 8)
+    const R s1 = (R)0.38268343236508977172845998403039886676;  // sin(pi / 8)
+    const R h = (R)0.70710678118654752440084436210484903928;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) dft4(x[b], x[4 + b], x[8 + b], x[12 + b]);
+    // x[4c + b] *= e^{2 pi i b c / 16}; b c in {1, 2, 3, 4, 6, 9}
+    auto rot = [](C v, R cr, R ci) { return C{v.x * cr - v.y * ci, v.x * ci + v.y * cr}; };
+    auto rot2 = [h](C v) { return C{h * (v.x - v.y), h * (v.x + v.y)}; };    // e^{i pi / 4}
+    auto rot6 = [h](C v) { return C{-h * (v.x + v.y), h * (v.x - v.y)}; };   // e^{3 i pi / 4}
+    x[5] = rot(x[5], c1, s1);
+    x[6] = rot2(x[6]);
+    x[7] = rot(x[7], s1, c1);
+    x[9] = rot2(x[9]);
+    x[10] = cmuli(x[10]);
+    x[11] = rot6(x[11]);
+    x[13] = rot(x[13], s1, c1);
+    x[14] = rot6(x[14]);
+    x[15] = rot(x[15], -c1, -s1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dft4(x[4 * c], x[4 * c + 1], x[4 * c + 2], x[4 * c + 3]);
+    // y_{c + 4d} sits in x[4c + d]: transpose the 4 x 4 block
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int d = c + 1; d < 4; ++d) {
+            const C t = x[4 * c + d];
+            x[4 * c + d] = x[4 * d + c];
+            x[4 * d + c] = t;
+        }
+}
+
 template <int R, typename C> __device__ inline void dft(C *x)
 {
     if constexpr (R == 2) dft2(x);
     else if constexpr (R == 4) dft4(x);
-    else dft8(x);
+    else if constexpr (R == 8) dft8(x);
+    else dft16(x);
 }
 
-// Stage plan for N = 2^LOGN.
-template <int LOGN> struct StagePlan {
-    static constexpr int REM = LOGN % 3;
-    static constexpr int NST = LOGN / 3 + (REM ? 1 : 0);
-    static constexpr int radix(int s) { return (s == 0 && REM) ? (1 << REM) : 8; }
+// Stage plan for N = 2^LOGN with E elements per thread: radix-16 stages
+// when a thread holds 16 elements (one butterfly), else radix 8; a first
+// stage of the remaining smaller radix when log2 N is not a multiple.
+template <int LOGN, int E> struct StagePlan {
+    static constexpr int LR = E >= 16 ? 4 : 3;
+    static constexpr int REM = LOGN % LR;
+    static constexpr int NST = LOGN / LR + (REM ? 1 : 0);
+    static constexpr int radix(int s) { return (s == 0 && REM) ? (1 << REM) : (1 << LR); }
     static constexpr int ns(int s)
     {
         int v = 1;
@@ -115,13 +156,6 @@ template <typename C>
 __device__ inline C twiddle(const C *tw, int t)
 {
     return cmul(tw[t & (kTwLo - 1)], tw[kTwLo + (t >> kTwLoBits)]);
-}
-
-// Cooperative copy of the two tables (global layout = LDS layout) into LDS.
-template <typename C>
-__device__ inline void load_twiddles(C *dst, const C *__restrict__ src, int n)
-{
-    for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
 }
 
 // LDS slot of element i of a sequence: one padding slot every 32 elements.
@@ -158,14 +192,19 @@ __device__ inline void job_of(int q, int logB, int &j, int &b)
 // One Stockham stage: butterfly (j, b) takes elements j + r N/R, applies
 // W_{NS R}^{r k} (k = j mod NS), transforms, and writes element
 // ((j - k) R + k) + r NS.  The first stage takes element i of sequence b
-// from ld(i, b) (global memory) and then runs pro() (work that may share the
-// loads' memory round trip); the last hands element o to st(o, b, v).
+// from ld(i, b) (global memory); the last hands element o to st(o, b, v).
+// The first stage also runs the prologue in two halves: pro.fetch() issues
+// its small loads before the stage's data loads and pro.commit() stores
+// them to LDS after.  Vector loads complete in issue order, so waiting for
+// the prologue's loads then does not wait for the data as well (a loop of
+// loads and stores placed after the data loads costs one full memory round
+// trip per iteration).
 template <typename T, int LOGN, int S, int E, bool BFAST, class Loader, class Storer, class Pro>
 __device__ inline void stockham_stage(cplx<T> *s, int logB, int IS, int BS,
                                       const cplx<T> *__restrict__ tws, const Loader &ld,
                                       const Storer &st, const Pro &pro)
 {
-    using P = StagePlan<LOGN>;
+    using P = StagePlan<LOGN, E>;
     constexpr int N = 1 << LOGN;
     constexpr int R = P::radix(S), NS = P::ns(S);
     constexpr bool FIRST = S == 0, LAST = S == P::NST - 1;
@@ -173,6 +212,8 @@ __device__ inline void stockham_stage(cplx<T> *s, int logB, int IS, int BS,
     constexpr int NBF = N / R;
     cplx<T> v[E];
     int jj[Q], bb[Q];
+    typename Pro::Regs pre{};
+    if constexpr (FIRST) pre = pro.fetch();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         int j, b;
@@ -191,8 +232,14 @@ __device__ inline void stockham_stage(cplx<T> *s, int logB, int IS, int BS,
             for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], twiddle(tws, r * k * STRIDE));
         }
     }
-    if constexpr (FIRST) pro();
-    else __syncthreads();
+    if constexpr (FIRST) {
+        pro.commit(pre);
+        // a one-stage transform stores right away: what the prologue put in
+        // LDS (the theta pass's row flags) must be visible to every thread
+        if constexpr (LAST) __syncthreads();
+    } else {
+        __syncthreads();
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         dft<R>(&v[q * R]);
@@ -213,18 +260,33 @@ template <typename T, int LOGN, int S, int E, bool BFAST, class Loader, class St
 __device__ inline void fft_stages(cplx<T> *s, int logB, int IS, int BS, const cplx<T> *tws,
                                   const Loader &ld, const Storer &st, const Pro &pro)
 {
-    if constexpr (S < StagePlan<LOGN>::NST) {
+    if constexpr (S < StagePlan<LOGN, E>::NST) {
         stockham_stage<T, LOGN, S, E, BFAST>(s, logB, IS, BS, tws, ld, st, pro);
         fft_stages<T, LOGN, S + 1, E, BFAST>(s, logB, IS, BS, tws, ld, st, pro);
     }
 }
 
-// Prologue that copies the twiddle tables into LDS (needed from stage 1 on).
+// Prologue that copies the twiddle tables into LDS (needed from stage 1 on):
+// one entry per thread is fetched early, any beyond the block size (small
+// blocks only) are copied by a loop at commit.
 template <typename C> struct TwiddleCopy {
     C *dst;
     const C *src;
     int n;
-    __device__ void operator()() const { load_twiddles(dst, src, n); }
+    struct Regs {
+        C tw;
+    };
+    __device__ Regs fetch() const
+    {
+        const int e = threadIdx.x;
+        return Regs{src[e < n ? e : 0]};
+    }
+    __device__ void commit(const Regs &r) const
+    {
+        const int e = threadIdx.x;
+        if (e < n) dst[e] = r.tw;
+        for (int x = e + (int)blockDim.x; x < n; x += blockDim.x) dst[x] = src[x];
+    }
 };
 
 // Workgroup id -> work item, so that each XCD (workgroups are dealt to the 8
@@ -283,18 +345,55 @@ template <typename T> struct ThetaStore {
 };
 
 // Prologue of the theta pass: the twiddle tables and this parity's row flags
-// go to LDS while the first stage's loads are in flight.
-template <typename C> struct ThetaPro {
+// go to LDS, fetched ahead of the first stage's loads.  Flags travel four
+// rows at a time: chunk c holds touched[8c .. 8c + 7] (touched is allocated
+// 256-byte aligned and L is a multiple of 4), of which bytes parity,
+// 2 + parity, 4 + parity and 6 + parity are rows 4c .. 4c + 3 of this
+// parity.  A block has at least L / E threads, so E / 4 chunks per thread
+// cover the L / 4 chunks.
+template <typename C, int E> struct ThetaPro {
+    static constexpr int FC = E / 4;
     C *tw_dst;
     const C *tw_src;
     int tw_n;
     uint8_t *flags_dst;
     const uint8_t *touched;
     int L, parity;
-    __device__ void operator()() const
+    struct Regs {
+        C tw;
+        uint2 fl[FC];
+    };
+    __device__ Regs fetch() const
     {
-        load_twiddles(tw_dst, tw_src, tw_n);
-        for (int q = threadIdx.x; q < L; q += blockDim.x) flags_dst[q] = touched[2 * q + parity];
+        Regs r;
+        const int e = threadIdx.x;
+        r.tw = tw_src[e < tw_n ? e : 0];
+        const uint2 *src = reinterpret_cast<const uint2 *>(touched);
+        const int nc = L >> 2;
+#pragma unroll
+        for (int k = 0; k < FC; ++k) {
+            const int c = e + k * (int)blockDim.x;
+            r.fl[k] = k * (int)blockDim.x < nc ? src[c < nc ? c : 0] : make_uint2(0u, 0u);
+        }
+        return r;
+    }
+    __device__ void commit(const Regs &r) const
+    {
+        const int e = threadIdx.x;
+        if (e < tw_n) tw_dst[e] = r.tw;
+        for (int x = e + (int)blockDim.x; x < tw_n; x += blockDim.x) tw_dst[x] = tw_src[x];
+        const int nc = L >> 2;
+        const unsigned sh = 8u * (unsigned)parity;
+#pragma unroll
+        for (int k = 0; k < FC; ++k) {
+            const int c = e + k * (int)blockDim.x;
+            if (c < nc) {
+                const unsigned a = (r.fl[k].x >> sh) & 0x00ff00ffu;
+                const unsigned b = (r.fl[k].y >> sh) & 0x00ff00ffu;
+                const unsigned lo = (a | (a >> 8)) & 0xffffu, hi = (b | (b >> 8)) & 0xffffu;
+                reinterpret_cast<uint32_t *>(flags_dst)[c] = lo | (hi << 16);
+            }
+        }
     }
 };
 
@@ -328,7 +427,7 @@ __device__ inline void theta_body(int item, const cplx<T> *__restrict__ coeffs, 
     ThetaLoad<T> ld{coeffs + (int64_t)f * fp.Kt * fp.Kp, fac_t + parity * fp.Kt, cpm, fp.Kt, fp.Kp,
                     L, m0};
     ThetaStore<T> st{S + (int64_t)f * fp.nft * fp.Kp, flags, fp.Kp, m0, parity};
-    ThetaPro<cplx<T>> pro{tw, tws, tw_lds_len(L), flags, touched, L, parity};
+    ThetaPro<cplx<T>, E> pro{tw, tws, tw_lds_len(L), flags, touched, L, parity};
     fft_stages<T, LOGL, 0, E, true>(s, fp.log_theta_batch, fp.theta_batch, 1, tw, ld, st, pro);
 }
 
