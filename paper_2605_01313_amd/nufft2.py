@@ -447,29 +447,38 @@ class Plan:
         _check(st, "nufft2_get_info")
         return info.as_dict()
 
-    def setpts(self, phi, theta):
+    def _check_points(self, phi, theta):
         t = self._torch
         for x in (phi, theta):
             if x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous():
                 raise TypeError("points must be contiguous float64 device tensors")
         if phi.numel() != theta.numel():
             raise ValueError("phi and theta differ in length")
-        n = phi.numel()
-        _check(nufft2_setpts(self.handle, n, phi.data_ptr() if n else 0,
-                             theta.data_ptr() if n else 0), "nufft2_setpts")
-        self._pts = (phi, theta)   # keep alive until the stream has consumed them
-        self.n_pts = n
+        return phi.numel()
 
-    def exec(self, coeffs, out=None):
+    def _check_io(self, coeffs, out, n_pts):
         t = self._torch
         if coeffs.dtype != self.cdtype or not coeffs.is_cuda or not coeffs.is_contiguous():
             raise TypeError(f"coeffs must be a contiguous {self.cdtype} device tensor")
         if tuple(coeffs.shape) != self.shape and tuple(coeffs.shape) != self.shape[1:]:
             raise ValueError(f"coeffs shape {tuple(coeffs.shape)} != {self.shape}")
         F = self.shape[0]
+        dt = self.rdtype if self.real_output else self.cdtype
         if out is None:
-            dt = self.rdtype if self.real_output else self.cdtype
-            out = t.empty((F, max(self.n_pts, 0)), dtype=dt, device=coeffs.device)
+            return t.empty((F, max(n_pts, 0)), dtype=dt, device=coeffs.device)
+        if out.dtype != dt or not out.is_cuda or not out.is_contiguous() or out.numel() != F * max(n_pts, 0):
+            raise ValueError(f"out must be a contiguous {dt} device tensor of {F} x {max(n_pts, 0)} values")
+        return out
+
+    def setpts(self, phi, theta):
+        n = self._check_points(phi, theta)
+        _check(nufft2_setpts(self.handle, n, phi.data_ptr() if n else 0,
+                             theta.data_ptr() if n else 0), "nufft2_setpts")
+        self._pts = (phi, theta)   # keep alive until the stream has consumed them
+        self.n_pts = n
+
+    def exec(self, coeffs, out=None):
+        out = self._check_io(coeffs, out, self.n_pts)
         _check(nufft2_exec(self.handle, coeffs.data_ptr(), out.data_ptr() if out.numel() else 0),
                "nufft2_exec")
         return out

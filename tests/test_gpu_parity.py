@@ -256,6 +256,26 @@ def test_zero_points_and_exec_before_setpts(torch_dev):
     assert plan.check() == 0
 
 
+def test_binding_rejects_a_wrong_output_tensor(torch_dev):
+    """The binding checks the caller's output tensor before the library
+    writes F * n_pts values into it."""
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Plan
+    say("case wrong_out")
+    plan = Plan("fp32", 31, 31, n_fields=2, eps=1e-6)
+    pts = torch.linspace(0.1, 3.0, 100, dtype=torch.float64, device=dev)
+    plan.setpts(pts, pts)
+    c = torch.zeros((2, 31, 31), dtype=torch.complex64, device=dev)
+    for bad in (torch.empty((2, 99), dtype=torch.complex64, device=dev),
+                torch.empty((2, 100), dtype=torch.complex128, device=dev),
+                torch.empty((100, 2), dtype=torch.complex64, device=dev).t(),
+                torch.empty((2, 100), dtype=torch.complex64)):
+        with pytest.raises(ValueError):
+            plan.exec(c, bad)
+    assert plan.exec(c, torch.empty((2, 100), dtype=torch.complex64, device=dev)).shape == (2, 100)
+    plan.destroy()
+
+
 def test_nonfinite_points_give_nan_and_flag(torch_dev):
     torch, dev = torch_dev
     say("case nonfinite")
