@@ -12,6 +12,9 @@
 //                      the next call
 //   k_setpts_scatter   per point: recompute the split, write the packed
 //                      record at binstart[bin] + rank, and the permutation
+// For small plans (bins in one scan pass, points in one wave of 1024-thread
+// workgroups) k_setpts_scatter_scan replaces the last two: each workgroup
+// scans the counts itself (see there).
 //
 // The order of points inside a bin depends on atomic arbitration; the output
 // of an exec does not, because each point's sum is computed by one thread in a
@@ -197,7 +200,7 @@ __device__ __attribute__((always_inline)) inline void scan_pass(const int (&in)[
                                                               int *stage, int *cmp, int (*lds)[33], int &carry,
                                                               int &carry_ne, int32_t *__restrict__ binstart,
                                                               int32_t *__restrict__ binlist,
-                                                              int4 *__restrict__ items)
+                                                              int4 *__restrict__ items, bool write_out = true)
 {
 #pragma unroll
     for (int k = 0; k < kScanChunk; ++k) stage[scan_slot(k * kScanThreads + (int)threadIdx.x)] = in[k];
@@ -228,22 +231,57 @@ __device__ __attribute__((always_inline)) inline void scan_pass(const int (&in)[
         run += vals[c];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < n; e += kScanThreads) binstart[base + e] = stage[scan_slot(e)];
-    for (int e = threadIdx.x; e < ne_total; e += kScanThreads) {
-        const int q = cmp_slot(e);
-        const int b = cmp[q], s0 = cmp[kCmpLen + q], c0 = cmp[2 * kCmpLen + q];
-        binlist[carry_ne + e] = b;
-        items[carry_ne + e] = make_int4(b, s0, c0, 0);
+    if (write_out) {
+        for (int e = threadIdx.x; e < n; e += kScanThreads) binstart[base + e] = stage[scan_slot(e)];
+        for (int e = threadIdx.x; e < ne_total; e += kScanThreads) {
+            const int q = cmp_slot(e);
+            const int b = cmp[q], s0 = cmp[kCmpLen + q], c0 = cmp[2 * kCmpLen + q];
+            binlist[carry_ne + e] = b;
+            items[carry_ne + e] = make_int4(b, s0, c0, 0);
+        }
     }
     __syncthreads();
     carry += total;
     carry_ne += ne_total;
 }
 
+// The reached theta rows from this thread's row marks mk (rows t + i * 1024):
+// row l is read by the gather iff some point's first tap row is within
+// w - 1 rows below it (cyclically).  The marks go through LDS (marks, nft
+// bytes) so the w-wide window reads hit LDS, not global memory.  Also
+// publishes the non-finite flag (flag0: flags[0] as thread 0 read it) in
+// flags[1] and clears the marks and flags[0] for the next call.
+constexpr int kMaxRowsPerScanThread = 4;  // nf <= 4096
+__device__ __attribute__((always_inline)) inline void reached_rows(const uint8_t (&mk)[kMaxRowsPerScanThread],
+                                                                 int flag0, uint8_t *marks,
+                                                                 uint8_t *__restrict__ rowmark,
+                                                                 uint8_t *__restrict__ rowtouched, int nft, int w,
+                                                                 int32_t *__restrict__ flags)
+{
+    const int t = (int)threadIdx.x;
+    if (t == 0) {
+        flags[1] = flag0;
+        flags[0] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxRowsPerScanThread; ++i) {
+        const int l = t + i * kScanThreads;
+        if (l < nft) {
+            marks[l] = mk[i];
+            rowmark[l] = 0;
+        }
+    }
+    __syncthreads();
+    for (int l = t; l < nft; l += kScanThreads) {
+        uint8_t v = 0;
+        for (int a = 0; a < w; ++a) v |= marks[(l - a + nft) & (nft - 1)];
+        rowtouched[l] = v;
+    }
+}
+
 // Passes whose counts are all loaded before the first scan (nbins up to
 // kScanHoist * PASS): the kernel then waits on global memory once.
 constexpr int kScanHoist = 4;
-constexpr int kMaxRowsPerScanThread = 4;  // nf <= 4096
 
 __device__ __attribute__((always_inline)) inline void bin_scan_body(int32_t *__restrict__ bincount, int32_t *__restrict__ binstart,
                                      int32_t *__restrict__ binlist, int64_t nbins, uint8_t *__restrict__ rowmark,
@@ -304,27 +342,8 @@ __device__ __attribute__((always_inline)) inline void bin_scan_body(int32_t *__r
     if (t == 0) {
         binstart[nbins] = carry;
         binlist[nbins] = carry_ne;
-        flags[1] = flag0;
-        flags[0] = 0;
     }
-    // A theta row l is read by the gather iff some point's first tap row is
-    // within w - 1 rows below it (cyclically).  The marks go through LDS so
-    // the w-wide window reads hit LDS, not global memory.
-    uint8_t *marks = reinterpret_cast<uint8_t *>(stage);
-#pragma unroll
-    for (int i = 0; i < kMaxRowsPerScanThread; ++i) {
-        const int l = t + i * kScanThreads;
-        if (l < nft) {
-            marks[l] = mk[i];
-            rowmark[l] = 0;
-        }
-    }
-    __syncthreads();
-    for (int l = t; l < nft; l += kScanThreads) {
-        uint8_t v = 0;
-        for (int a = 0; a < w; ++a) v |= marks[(l - a + nft) & (nft - 1)];
-        rowtouched[l] = v;
-    }
+    reached_rows(mk, flag0, reinterpret_cast<uint8_t *>(stage), rowmark, rowtouched, nft, w, flags);
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_bin_scan(int32_t *__restrict__ bincount,
@@ -394,17 +413,102 @@ __global__ __launch_bounds__(256) void k_setpts_scatter_group(const SetptsJob *_
                             J.theta, J.sp, J.keyrank, J.binstart, (PointRec<T> *)J.rec, J.perm);
 }
 
+// Scatter with the bin scan folded in, for plans whose bins fit one scan pass
+// and whose points fit one wave of workgroups (kFusedMaxBlocks of 1024
+// threads): every workgroup scans all bin counts in LDS (the same pass as
+// k_bin_scan) and places its own points from those starts; workgroup 0 also
+// writes the starts, the non-empty bin list and its entries, workgroup
+// min(1, grid - 1) the reached rows and the non-finite flag, and the last
+// workgroup to finish clears the counters for the next call.  A workgroup
+// takes its ticket (flags[2]) after its counts went through its scan, so
+// the last one clears them after every read.  One launch boundary and one
+// single-workgroup kernel fewer than bin count -> scan -> scatter.
+constexpr int kFusedMaxBlocks = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_setpts_scatter_scan(
+    const double *__restrict__ phi, const double *__restrict__ theta, SetptsParams sp,
+    int32_t *__restrict__ bincount, int32_t *__restrict__ binstart, int32_t *__restrict__ binlist, int nbins,
+    const int2 *__restrict__ keyrank, uint8_t *__restrict__ rowmark, uint8_t *__restrict__ rowtouched, int nft,
+    int32_t *__restrict__ flags, PointRec<T> *__restrict__ rec, int32_t *__restrict__ perm)
+{
+    __shared__ int lds[2][33];
+    __shared__ int stage[kScanChunk * kScanThreads + kScanThreads];
+    __shared__ int cmp[3 * kCmpLen];
+    __shared__ int last;
+    const int t = (int)threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * kScanThreads + t;
+    const bool out_wg = blockIdx.x == 0;
+    const bool rows_wg = (int)blockIdx.x == (gridDim.x > 1 ? 1 : 0);
+    // every load of the workgroup first: its points, all counts, the marks
+    double ph = 0.0, th = 0.0;
+    int2 kr = make_int2(0, 0);
+    if (j < sp.n) {
+        ph = phi[j];
+        th = theta[j];
+        kr = keyrank[j];
+    }
+    int h[kScanChunk];
+#pragma unroll
+    for (int k = 0; k < kScanChunk; ++k) {
+        const int e = k * kScanThreads + t;
+        h[k] = e < nbins ? bincount[e] : 0;
+    }
+    uint8_t mk[kMaxRowsPerScanThread];
+    int flag0 = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxRowsPerScanThread; ++i) {
+        const int l = t + i * kScanThreads;
+        mk[i] = rows_wg && l < nft ? rowmark[l] : (uint8_t)0;
+    }
+    if (rows_wg && t == 0) flag0 = flags[0];
+    int4 *items = bin_items(binlist, nbins);
+    int carry = 0, carry_ne = 0;
+    scan_pass(h, 0, nbins, stage, cmp, lds, carry, carry_ne, binstart, binlist, items, out_wg);
+    // stage[scan_slot(b)] now holds the first record of bin b
+    if (out_wg && t == 0) {
+        binstart[nbins] = carry;
+        binlist[nbins] = carry_ne;
+    }
+    if (t == 0) last = atomicAdd(&flags[2], 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (last) {
+        for (int e = t; e < nbins; e += kScanThreads) bincount[e] = 0;
+        if (t == 0) flags[2] = 0;
+    }
+    if (j < sp.n) {
+        PointRec<T> r;
+        if (!isfinite(ph) || !isfinite(th)) {
+            r.it = 0;
+            r.ip = 0;
+            r.vt = (T)NAN;
+            r.vp = (T)NAN;
+        } else {
+            split_axis<T>(th, sp.th, sp.w, r.it, r.vt);
+            split_axis<T>(ph, sp.ph, sp.w, r.ip, r.vp);
+        }
+        const int32_t pos = stage[scan_slot(kr.x)] + kr.y;
+        rec[pos] = r;
+        perm[pos] = (int32_t)j;
+    }
+    if (rows_wg) reached_rows(mk, flag0, reinterpret_cast<uint8_t *>(cmp), rowmark, rowtouched, nft, sp.w, flags);
+}
+
 hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, const double *theta,
                          int32_t *bincount, int32_t *binstart, int32_t *binlist, int64_t nbins,
                          int2 *keyrank,
                          uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
                          int32_t *flags, hipStream_t s)
 {
-    // bincount, rowmark and flags[0] are zero on entry: the plan clears them
-    // once and every k_bin_scan leaves them cleared.
+    // bincount, rowmark, flags[0] and the ticket flags[2] are zero on entry:
+    // the plan clears them once and every scan (k_bin_scan or
+    // k_setpts_scatter_scan) leaves them cleared.
     hipError_t e;
     const int threads = 256;
     const int64_t blocks = (sp.n + threads - 1) / threads;
+    const int64_t fused_blocks = (sp.n + kScanThreads - 1) / kScanThreads;
+    const bool fused = sp.n > 0 && nbins <= (int64_t)kScanChunk * kScanThreads && fused_blocks <= kFusedMaxBlocks &&
+                       sp.th.nf <= kMaxRowsPerScanThread * kScanThreads;
     if (sp.n > 0) {
         if (prec == 1)
             hipLaunchKernelGGL(k_setpts_bin<float>, dim3((unsigned)blocks), dim3(threads), 0, s, phi,
@@ -413,6 +517,17 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
             hipLaunchKernelGGL(k_setpts_bin<double>, dim3((unsigned)blocks), dim3(threads), 0, s, phi,
                                theta, sp, bincount, keyrank, rowmark, flags);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (fused) {
+        if (prec == 1)
+            hipLaunchKernelGGL(k_setpts_scatter_scan<float>, dim3((unsigned)fused_blocks), dim3(kScanThreads), 0, s,
+                               phi, theta, sp, bincount, binstart, binlist, (int)nbins, keyrank, rowmark,
+                               rowtouched, sp.th.nf, flags, (PointRec<float> *)rec, perm);
+        else
+            hipLaunchKernelGGL(k_setpts_scatter_scan<double>, dim3((unsigned)fused_blocks), dim3(kScanThreads), 0, s,
+                               phi, theta, sp, bincount, binstart, binlist, (int)nbins, keyrank, rowmark,
+                               rowtouched, sp.th.nf, flags, (PointRec<double> *)rec, perm);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kScanThreads), 0, s, bincount, binstart, binlist, nbins,
                        rowmark, rowtouched, sp.th.nf, sp.w, flags);

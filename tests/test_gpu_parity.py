@@ -241,6 +241,40 @@ def test_largest_grid(torch_dev, oracle_mod, prec, eps, tol):
     assert max(errs) <= tol
 
 
+def test_setpts_paths_alternate_on_one_plan(torch_dev, oracle_mod):
+    """Point counts on both sides of the limit of the fused sort (at most 256
+    workgroups of 1024 points; above it the separate scan kernel runs) on one
+    plan, one after another: each leaves the counters, row marks and ticket
+    cleared for the next, so every call sorts and evaluates correctly."""
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Plan
+    rng = np.random.default_rng(31)
+    K = 63
+    coeffs = synth.dfs_field_coeffs(rng, K, K, synth.envelope_algebraic(K, K))[None]
+    plan = Plan("fp32", K, K, n_fields=1, eps=1e-6)
+    c = torch.from_numpy(coeffs.astype(np.complex64)).to(dev)
+    info = plan.info()
+    nb = info["n_bins"]
+    for n in (262144, 262145, 5000, 262144, 1):
+        say(f"case setpts_paths n={n}")
+        phi = rng.uniform(-7.0, 7.0, n)
+        theta = rng.uniform(0.05, 3.1, n)
+        plan.setpts(torch.from_numpy(phi).to(dev), torch.from_numpy(theta).to(dev))
+        got = plan.exec(c).cpu().numpy()
+        assert plan.check() == 0
+        perm = plan.debug_tensor(2, torch.int32, (n,)).cpu().numpy()
+        assert np.array_equal(np.sort(perm), np.arange(n))
+        starts_all = plan.debug_tensor(3, torch.int32, (nb + 1,)).cpu().numpy()
+        assert starts_all[0] == 0 and starts_all[-1] == n and np.all(np.diff(starts_all) >= 0)
+        check_binlist(plan, torch, starts_all)
+        sel = synth.sample_indices(n, 300)
+        ref = oracle_mod.dfs_eval(coeffs, phi[sel], theta[sel])
+        err = rel_l2(got[0, sel], ref[0])
+        say(f"  rel l2 {err:.2e}")
+        assert err <= 1e-6
+    plan.destroy()
+
+
 def test_zero_points_and_exec_before_setpts(torch_dev):
     torch, dev = torch_dev
     from paper_2605_01313_amd import Plan, nufft2
