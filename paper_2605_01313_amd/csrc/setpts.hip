@@ -470,12 +470,10 @@ __global__ __launch_bounds__(kScanThreads) void k_setpts_scatter_scan(
         binstart[nbins] = carry;
         binlist[nbins] = carry_ne;
     }
-    if (t == 0) last = atomicAdd(&flags[2], 1) == (int)gridDim.x - 1;
-    __syncthreads();
-    if (last) {
-        for (int e = t; e < nbins; e += kScanThreads) bincount[e] = 0;
-        if (t == 0) flags[2] = 0;
-    }
+    // the ticket goes out now (the scan has consumed every count this
+    // workgroup read); its answer is needed only at the end
+    int ticket = 0;
+    if (t == 0) ticket = atomicAdd(&flags[2], 1);
     if (j < sp.n) {
         PointRec<T> r;
         if (!isfinite(ph) || !isfinite(th)) {
@@ -492,6 +490,12 @@ __global__ __launch_bounds__(kScanThreads) void k_setpts_scatter_scan(
         perm[pos] = (int32_t)j;
     }
     if (rows_wg) reached_rows(mk, flag0, reinterpret_cast<uint8_t *>(cmp), rowmark, rowtouched, nft, sp.w, flags);
+    if (t == 0) last = ticket == (int)gridDim.x - 1;
+    __syncthreads();
+    if (last) {
+        for (int e = t; e < nbins; e += kScanThreads) bincount[e] = 0;
+        if (t == 0) flags[2] = 0;
+    }
 }
 
 hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, const double *theta,
