@@ -76,13 +76,21 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
     // columns their patches share come from that XCD's L2 (about 30% less
     // HBM traffic than plain bin order).  Only non-empty bins are dealt (the
     // points cover about half of the doubled torus), so the XCDs get equal
-    // shares.  The grid has 8 * ceil(nbins / 8) workgroups.
-    const int n_ne = binlist[gp.nbins];
-    const int per = (n_ne + 7) >> 3;
-    const int k = blk >> 3;
-    const int item = (blk & 7) * per + k;
-    if (k >= per || item >= n_ne) return;
-    const int4 bi = bin_items(binlist, gp.nbins)[item];  // {bin, first record, count, 0}
+    // shares.  The grid has 8 * ceil(nbins / 8) workgroups.  Up to
+    // kDealtMaxBins bins setpts wrote each workgroup's entry (zero count:
+    // nothing to do), so one load finds the bin; otherwise the entry's index
+    // follows from the number of non-empty bins.
+    int4 bi;  // {bin, first record, count, 0}
+    if (gp.nbins <= kDealtMaxBins) {
+        bi = bin_dealt(binlist, gp.nbins)[blk];
+    } else {
+        const int n_ne = binlist[gp.nbins];
+        const int per = (n_ne + 7) >> 3;
+        const int k = blk >> 3;
+        const int item = (blk & 7) * per + k;
+        if (k >= per || item >= n_ne) return;
+        bi = bin_items(binlist, gp.nbins)[item];
+    }
     const int bin = bi.x;
     const int start = bi.y;
     const int cnt = bi.z;
@@ -107,6 +115,7 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
     __shared__ int bucket[NK];  // per bank key: count, then start
     __shared__ short slot[kGatherThreads];  // lane -> point of the chunk (-1: none)
     __shared__ int dsts[kGatherThreads];    // destination of each point of the chunk
+    __shared__ PointRec<T> recs[kGatherThreads];  // record of each point of the chunk
     const int64_t field_stride = (int64_t)gp.nft * gp.nfp;
 
     // FG fields per pass; the last pass may hold fewer (fg)
@@ -164,6 +173,7 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
                     d = perm[start + base + t];
                 }
                 dsts[t] = d;
+                recs[t] = q;
                 const bool qbad = !(q.vt == q.vt) || !(q.vp == q.vp);
                 key = qbad ? 0 : ((q.it - r0) * TC + (q.ip - c0) + column_rotation(q.it, q.ip)) & (NK - 1);
                 rank = atomicAdd(&bucket[key], 1);
@@ -188,8 +198,7 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
             __syncthreads();
             const int mine = slot[t];
             if (mine < 0) continue;
-            const int r = base + mine;
-            const PointRec<T> pr = rec[start + r];
+            const PointRec<T> pr = recs[mine];
             const int dst = dsts[mine];
             const bool bad = !(pr.vt == pr.vt) || !(pr.vp == pr.vp);
             const int lr = bad ? 0 : pr.it - r0;

@@ -44,9 +44,19 @@ __host__ __device__ inline const int4 *bin_items(const int32_t *binlist, int64_t
 {
     return reinterpret_cast<const int4 *>(binlist + bin_items_offset(nbins));
 }
+// The gather launches one workgroup per slot, 8 * ceil(nbins / 8) of them.
+// Plans with at most kDealtMaxBins bins (one scan pass) also get the table
+// of entries per slot (bin_dealt).
+constexpr int64_t kDealtMaxBins = 8192;
+__host__ __device__ inline int64_t gather_slots(int64_t nbins) { return 8 * ((nbins + 7) / 8); }
+__host__ __device__ inline int4 *bin_dealt(int32_t *binlist, int64_t nbins) { return bin_items(binlist, nbins) + nbins; }
+__host__ __device__ inline const int4 *bin_dealt(const int32_t *binlist, int64_t nbins)
+{
+    return bin_items(binlist, nbins) + nbins;
+}
 inline size_t binlist_bytes(int64_t nbins)
 {
-    return sizeof(int32_t) * (size_t)bin_items_offset(nbins) + sizeof(int4) * (size_t)nbins;
+    return sizeof(int32_t) * (size_t)bin_items_offset(nbins) + sizeof(int4) * (size_t)(nbins + gather_slots(nbins));
 }
 
 // ---- launchers (each returns the hipError_t of its launch) ----
@@ -128,6 +138,12 @@ struct GatherParams {
 // binlist holds the non-empty bins in increasing order and their number in
 // entry nbins; after it (16-byte aligned, see bin_items) one int4 per
 // non-empty bin in the same order: {bin, first record, record count, 0}.
+// Gather workgroups are dealt to the 8 XCDs round-robin; workgroup blk
+// takes entry (blk & 7) * per + (blk >> 3), per = ceil(n / 8) for n
+// non-empty bins, so each XCD runs a contiguous eighth of them in bin
+// order.  With at most kDealtMaxBins bins, bin_dealt then holds one int4 per
+// workgroup: the entry it takes, or all zero (the scan writes it from LDS,
+// so the gather finds its bin with one load instead of two).
 hipError_t launch_gather(int prec, const GatherParams &gp, const void *grid, const void *rec,
                          const int32_t *perm, const int32_t *binlist, void *out, hipStream_t s);
 

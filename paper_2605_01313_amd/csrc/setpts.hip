@@ -187,6 +187,7 @@ __device__ constexpr int scan_slot(int e) { return e + e / kScanChunk; }
 // 32 banks).
 constexpr int kCmpLen = kScanChunk * kScanThreads + kScanChunk * kScanThreads / 32;
 __device__ constexpr int cmp_slot(int e) { return e + e / 32; }
+static_assert(kDealtMaxBins == kScanChunk * kScanThreads, "the per-slot table needs all entries of one pass");
 
 // One pass over PASS = CHUNK * 1024 bins starting at base (n of them):
 // in[k] is this thread's count of bin base + k * 1024 + threadIdx.x (zero
@@ -279,6 +280,25 @@ __device__ __attribute__((always_inline)) inline void reached_rows(const uint8_t
     }
 }
 
+// The gather's table of entries per workgroup (see bin_dealt) for a plan of
+// at most kDealtMaxBins bins, written by the scanning workgroup after its
+// single pass, from the n_ne entries that pass left compacted in cmp.
+__device__ __attribute__((always_inline)) inline void write_dealt(int4 *__restrict__ dealt, int64_t nbins, int n_ne,
+                                                                const int *cmp)
+{
+    const int per = (n_ne + 7) >> 3;
+    const int slots = (int)gather_slots(nbins);
+    for (int blk = threadIdx.x; blk < slots; blk += kScanThreads) {
+        const int k = blk >> 3, item = (blk & 7) * per + k;
+        int4 v = make_int4(0, 0, 0, 0);
+        if (k < per && item < n_ne) {
+            const int q = cmp_slot(item);
+            v = make_int4(cmp[q], cmp[kCmpLen + q], cmp[2 * kCmpLen + q], 0);
+        }
+        dealt[blk] = v;
+    }
+}
+
 // Passes whose counts are all loaded before the first scan (nbins up to
 // kScanHoist * PASS): the kernel then waits on global memory once.
 constexpr int kScanHoist = 4;
@@ -343,6 +363,7 @@ __device__ __attribute__((always_inline)) inline void bin_scan_body(int32_t *__r
         binstart[nbins] = carry;
         binlist[nbins] = carry_ne;
     }
+    if (nbins <= kDealtMaxBins) write_dealt(bin_dealt(binlist, nbins), nbins, carry_ne, cmp);
     reached_rows(mk, flag0, reinterpret_cast<uint8_t *>(stage), rowmark, rowtouched, nft, w, flags);
 }
 
@@ -466,9 +487,12 @@ __global__ __launch_bounds__(kScanThreads) void k_setpts_scatter_scan(
     int carry = 0, carry_ne = 0;
     scan_pass(h, 0, nbins, stage, cmp, lds, carry, carry_ne, binstart, binlist, items, out_wg);
     // stage[scan_slot(b)] now holds the first record of bin b
-    if (out_wg && t == 0) {
-        binstart[nbins] = carry;
-        binlist[nbins] = carry_ne;
+    if (out_wg) {
+        if (t == 0) {
+            binstart[nbins] = carry;
+            binlist[nbins] = carry_ne;
+        }
+        write_dealt(bin_dealt(binlist, nbins), nbins, carry_ne, cmp);
     }
     // the ticket goes out now (the scan has consumed every count this
     // workgroup read); its answer is needed only at the end
@@ -489,7 +513,11 @@ __global__ __launch_bounds__(kScanThreads) void k_setpts_scatter_scan(
         rec[pos] = r;
         perm[pos] = (int32_t)j;
     }
-    if (rows_wg) reached_rows(mk, flag0, reinterpret_cast<uint8_t *>(cmp), rowmark, rowtouched, nft, sp.w, flags);
+    if (rows_wg) {
+        // with one workgroup it also wrote the per-slot table from cmp above
+        if (out_wg) __syncthreads();
+        reached_rows(mk, flag0, reinterpret_cast<uint8_t *>(cmp), rowmark, rowtouched, nft, sp.w, flags);
+    }
     if (t == 0) last = ticket == (int)gridDim.x - 1;
     __syncthreads();
     if (last) {
