@@ -76,21 +76,14 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
     // columns their patches share come from that XCD's L2 (about 30% less
     // HBM traffic than plain bin order).  Only non-empty bins are dealt (the
     // points cover about half of the doubled torus), so the XCDs get equal
-    // shares.  The grid has 8 * ceil(nbins / 8) workgroups.  Up to
-    // kDealtMaxBins bins setpts wrote each workgroup's entry (zero count:
-    // nothing to do), so one load finds the bin; otherwise the entry's index
-    // follows from the number of non-empty bins.
-    int4 bi;  // {bin, first record, count, 0}
-    if (gp.nbins <= kDealtMaxBins) {
-        bi = bin_dealt(binlist, gp.nbins)[blk];
-    } else {
-        const int n_ne = binlist[gp.nbins];
-        const int per = (n_ne + 7) >> 3;
-        const int k = blk >> 3;
-        const int item = (blk & 7) * per + k;
-        if (k >= per || item >= n_ne) return;
-        bi = bin_items(binlist, gp.nbins)[item];
-    }
+    // shares.  The grid has 8 * ceil(nbins / 8) workgroups.  Every setpts
+    // with points writes each workgroup's entry (zero count: nothing to
+    // do), so one load finds the bin; the number of non-empty bins, read
+    // beside it, is zero after a setpts without points (whose table is not
+    // rewritten above kDealtMaxBins bins).
+    const int n_ne = binlist[gp.nbins];
+    const int4 bi = bin_dealt(binlist, gp.nbins)[blk];  // {bin, first record, count, 0}
+    if (n_ne == 0) return;
     const int bin = bi.x;
     const int start = bi.y;
     const int cnt = bi.z;

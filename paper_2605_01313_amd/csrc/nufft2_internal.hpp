@@ -45,8 +45,7 @@ __host__ __device__ inline const int4 *bin_items(const int32_t *binlist, int64_t
     return reinterpret_cast<const int4 *>(binlist + bin_items_offset(nbins));
 }
 // The gather launches one workgroup per slot, 8 * ceil(nbins / 8) of them.
-// Plans with at most kDealtMaxBins bins (one scan pass) also get the table
-// of entries per slot (bin_dealt).
+// kDealtMaxBins: the bins of one scan pass.
 constexpr int64_t kDealtMaxBins = 8192;
 __host__ __device__ inline int64_t gather_slots(int64_t nbins) { return 8 * ((nbins + 7) / 8); }
 __host__ __device__ inline int4 *bin_dealt(int32_t *binlist, int64_t nbins) { return bin_items(binlist, nbins) + nbins; }
@@ -141,9 +140,10 @@ struct GatherParams {
 // Gather workgroups are dealt to the 8 XCDs round-robin; workgroup blk
 // takes entry (blk & 7) * per + (blk >> 3), per = ceil(n / 8) for n
 // non-empty bins, so each XCD runs a contiguous eighth of them in bin
-// order.  With at most kDealtMaxBins bins, bin_dealt then holds one int4 per
-// workgroup: the entry it takes, or all zero (the scan writes it from LDS,
-// so the gather finds its bin with one load instead of two).
+// order.  bin_dealt then holds one int4 per workgroup: the entry it takes,
+// or all zero, so the gather finds its bin with one load instead of two.
+// The scan writes it from LDS for plans of at most kDealtMaxBins bins (one
+// pass), the scatter's threads for larger plans.
 hipError_t launch_gather(int prec, const GatherParams &gp, const void *grid, const void *rec,
                          const int32_t *perm, const int32_t *binlist, void *out, hipStream_t s);
 

@@ -412,6 +412,24 @@ __device__ inline void setpts_scatter_point(int64_t j, const double *__restrict_
     }
 }
 
+// Above kDealtMaxBins bins the gather's per-slot table (see bin_dealt) is
+// written here, by the scatter's threads (thread i of n: slots i, i + n,
+// ...), from the entries the scan published: one workgroup could not write
+// it fast enough.
+__device__ inline void scatter_dealt(int64_t i, int64_t n, int32_t *__restrict__ binlist, int64_t nbins)
+{
+    if (nbins <= kDealtMaxBins) return;
+    const int n_ne = binlist[nbins];
+    const int per = (n_ne + 7) >> 3;
+    const int4 *items = bin_items(binlist, nbins);
+    int4 *dealt = bin_dealt(binlist, nbins);
+    const int64_t slots = gather_slots(nbins);
+    for (int64_t blk = i; blk < slots; blk += n) {
+        const int k = (int)(blk >> 3), item = (int)(blk & 7) * per + k;
+        dealt[blk] = (k < per && item < n_ne) ? items[item] : make_int4(0, 0, 0, 0);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_setpts_scatter(const double *__restrict__ phi,
                                                         const double *__restrict__ theta,
@@ -419,10 +437,12 @@ __global__ __launch_bounds__(256) void k_setpts_scatter(const double *__restrict
                                                         const int2 *__restrict__ keyrank,
                                                         const int32_t *__restrict__ binstart,
                                                         PointRec<T> *__restrict__ rec,
-                                                        int32_t *__restrict__ perm)
+                                                        int32_t *__restrict__ perm,
+                                                        int32_t *__restrict__ binlist, int64_t nbins)
 {
-    setpts_scatter_point<T>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, phi, theta, sp, keyrank, binstart, rec,
-                            perm);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    setpts_scatter_point<T>(i, phi, theta, sp, keyrank, binstart, rec, perm);
+    scatter_dealt(i, (int64_t)gridDim.x * blockDim.x, binlist, nbins);
 }
 
 template <typename T>
@@ -430,8 +450,10 @@ __global__ __launch_bounds__(256) void k_setpts_scatter_group(const SetptsJob *_
                                                               const int32_t *__restrict__ job_of_block)
 {
     const SetptsJob J = jobs[job_of_block[blockIdx.x]];
-    setpts_scatter_point<T>((int64_t)((int)blockIdx.x - J.block_begin) * blockDim.x + threadIdx.x, J.phi,
-                            J.theta, J.sp, J.keyrank, J.binstart, (PointRec<T> *)J.rec, J.perm);
+    const int64_t i = (int64_t)((int)blockIdx.x - J.block_begin) * blockDim.x + threadIdx.x;
+    setpts_scatter_point<T>(i, J.phi, J.theta, J.sp, J.keyrank, J.binstart, (PointRec<T> *)J.rec, J.perm);
+    const int64_t member_threads = (J.sp.n + blockDim.x - 1) / blockDim.x * blockDim.x;
+    scatter_dealt(i, member_threads, J.binlist, J.nbins);
 }
 
 // Scatter with the bin scan folded in, for plans whose bins fit one scan pass
@@ -567,10 +589,10 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
     if (sp.n > 0) {
         if (prec == 1)
             hipLaunchKernelGGL(k_setpts_scatter<float>, dim3((unsigned)blocks), dim3(threads), 0, s,
-                               phi, theta, sp, keyrank, binstart, (PointRec<float> *)rec, perm);
+                               phi, theta, sp, keyrank, binstart, (PointRec<float> *)rec, perm, binlist, nbins);
         else
             hipLaunchKernelGGL(k_setpts_scatter<double>, dim3((unsigned)blocks), dim3(threads), 0, s,
-                               phi, theta, sp, keyrank, binstart, (PointRec<double> *)rec, perm);
+                               phi, theta, sp, keyrank, binstart, (PointRec<double> *)rec, perm, binlist, nbins);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
