@@ -46,6 +46,9 @@ constexpr int kGatherMaxFields = 4;
 
 constexpr int kGatherThreads = 256;
 constexpr int kLoadBatch = 4;
+// FP64 splits the rows of a point over two lanes when a chunk holds at most
+// half a workgroup's points (see gather_body).
+template <typename T> constexpr bool kSplitRows = sizeof(T) == 8;
 
 // Lanes the LDS serves in one cycle for reads of one complex element (128
 // bytes per cycle over 32 four-byte banks, measured on gfx950 with the
@@ -109,6 +112,7 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
     __shared__ short slot[kGatherThreads];  // lane -> point of the chunk (-1: none)
     __shared__ int dsts[kGatherThreads];    // destination of each point of the chunk
     __shared__ PointRec<T> recs[kGatherThreads];  // record of each point of the chunk
+    __shared__ T xsum[kSplitRows<T> ? kGatherThreads / 2 * 2 * FG : 1];  // partial sums of split points
     const int64_t field_stride = (int64_t)gp.nft * gp.nfp;
 
     // FG fields per pass; the last pass may hold fewer (fg)
@@ -189,11 +193,28 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
                 slot[(k % R) * NK + k / R] = (short)t;
             }
             __syncthreads();
-            const int mine = slot[t];
-            if (mine < 0) continue;
+            // In FP64 a bin of at most half a workgroup's points (one chunk,
+            // which the dealing put on the lower half of the lanes) is split
+            // by rows: lane t + 128 takes rows H1 .. w-1 of lane t's point
+            // and hands its partial sums over through LDS, so that all four
+            // waves work on the taps instead of two.  The choice depends on
+            // the bin's count only, never on which chunk a point fell in, so
+            // a point's sum stays independent of the order inside its bin.
+            constexpr int HALF = kGatherThreads / 2;
+            const bool split = kSplitRows<T> && cnt <= HALF;
+            const bool upper = split && t >= HALF;
+            const int mine = upper ? slot[t - HALF] : slot[t];
+            constexpr int H1 = (W + 1) / 2;
+            const int a_begin = upper ? H1 : 0, a_end = split && !upper ? H1 : W;
+            T ax[FG], ay[FG];
+#pragma unroll
+            for (int f = 0; f < FG; ++f) ax[f] = ay[f] = (T)0;
+            bool bad = true;
+            int dst = 0;
+            if (mine >= 0) {
             const PointRec<T> pr = recs[mine];
-            const int dst = dsts[mine];
-            const bool bad = !(pr.vt == pr.vt) || !(pr.vp == pr.vp);
+            dst = dsts[mine];
+            bad = !(pr.vt == pr.vt) || !(pr.vp == pr.vp);
             const int lr = bad ? 0 : pr.it - r0;
             const int lc = bad ? 0 : pr.ip - c0;
             // step b reads column (b + rot) mod w; wp[b] is that column's weight
@@ -203,14 +224,11 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
 #pragma unroll
             for (int b = 0; b < W - 1; ++b) wp[b] = es_kernel<T>(((T)(b + rot - H) - pr.vp) * inv_hw, kc);
             wp[W - 1] = es_kernel<T>(((T)(last - H) - pr.vp) * inv_hw, kc);
-            T ax[FG], ay[FG];
-#pragma unroll
-            for (int f = 0; f < FG; ++f) ax[f] = ay[f] = (T)0;
             // rows stay a loop (two per iteration in FP64): unrolling it fully
             // lets the compiler hoist all w*w*FG LDS loads and run out of
             // registers
 #pragma unroll RU
-            for (int a = 0; a < W; ++a) {
+            for (int a = a_begin; a < a_end; ++a) {
                 const T wt = es_kernel<T>(((T)(a - H) - pr.vt) * inv_hw, kc);
                 const cplx<T> *row = tiles + (lr + a) * TC + lc;
                 const cplx<T> *rrow = row + rot;
@@ -233,6 +251,25 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
                     ay[f] += wt * ry[f];
                 }
             }
+            }
+            if (split) {
+                if (upper && mine >= 0) {
+#pragma unroll
+                    for (int f = 0; f < FG; ++f) {
+                        xsum[(t - HALF) * 2 * FG + 2 * f] = ax[f];
+                        xsum[(t - HALF) * 2 * FG + 2 * f + 1] = ay[f];
+                    }
+                }
+                __syncthreads();
+                if (!upper && mine >= 0) {
+#pragma unroll
+                    for (int f = 0; f < FG; ++f) {
+                        ax[f] += xsum[t * 2 * FG + 2 * f];
+                        ay[f] += xsum[t * 2 * FG + 2 * f + 1];
+                    }
+                }
+            }
+            if (mine < 0 || upper) continue;
 #pragma unroll
             for (int f = 0; f < FG; ++f) {
                 if (f < fg) {
