@@ -7,13 +7,14 @@
 // One workgroup per bin (a tile_t x tile_p block of first-tap cells).  The
 // workgroup stages the (tile_t + w - 1) x (tile_p + w - 1) patch of up to
 // FG fields at once in LDS, then each thread sums the w x w taps of one
-// point for all staged fields (independent accumulators per field).  Points
-// are dealt to lanes so that the lanes the LDS serves together read different
-// banks (the chunk loop and column_rotation).  The column weights are
-// computed once per point and field group, the row weights on the fly.  The
-// tap order (rows a outer, columns inner in one of two orders fixed by the
-// point's own cell) does not depend on which lane or where in its bin the sort
-// placed the point.
+// point for all staged fields (independent accumulators per field; in FP64
+// a bin of at most 128 points gives each point two threads, one per half of
+// the rows).  Points are dealt to lanes so that the lanes the LDS serves
+// together read different banks (the chunk loop and column_rotation).  The
+// column weights are computed once per point and field group, the row
+// weights on the fly.  The tap order (rows a outer, columns inner in one of
+// two orders fixed by the point's own cell) does not depend on which lane or
+// where in its bin the sort placed the point.
 #include "nufft2_internal.hpp"
 
 namespace nufft2 {
