@@ -180,3 +180,40 @@ def test_group_argument_errors(torch_dev):
     st = nufft2.nufft2_group_exec(g.handle, [c.data_ptr(), 0], [c.data_ptr(), c.data_ptr()])
     assert st == nufft2.NUFFT2_ERR_ARG
     g.destroy()
+
+
+def test_large_member_emptied_and_refilled(torch_dev, oracle_mod):
+    """A member with more bins than one scan pass (its gather table is written
+    by the scatter, not the scan) runs with points, then without points (its
+    table is not rewritten; its gather must find nothing), then with other
+    points; the small member beside it is right every time."""
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Group, Plan
+    say("case group_large_member")
+    rng = np.random.default_rng(41)
+    big = Plan("fp32", 1025, 1025, n_fields=1, eps=1e-6)
+    small = Plan("fp32", 63, 63, n_fields=1, eps=1e-6)
+    assert big.info()["n_bins"] > 8192 and small.info()["n_bins"] <= 8192
+    g = Group([big, small])
+    cb = synth.random_complex(rng, (1, 1025, 1025)) * synth.envelope_algebraic(1025, 1025, 1.5)[None]
+    cs = synth.random_complex(rng, (1, 63, 63)) * synth.envelope_algebraic(63, 63, 1.5)[None]
+    cbd = torch.from_numpy(cb).to(dev).to(torch.complex64)
+    csd = torch.from_numpy(cs).to(dev).to(torch.complex64)
+    for round_, nb in enumerate((40000, 0, 25000)):
+        ns = 3000 + 500 * round_
+        pts = [(rng.uniform(0, 2 * np.pi, n), rng.uniform(0.0, np.pi, n)) for n in (nb, ns)]
+        g.setpts([torch.from_numpy(p).to(dev) for p, _ in pts], [torch.from_numpy(t).to(dev) for _, t in pts])
+        outs = g.exec([cbd, csd])
+        torch.cuda.synchronize()
+        assert outs[0].shape == (1, nb) and outs[1].shape == (1, ns)
+        for out, c, (phi, theta) in zip(outs, (cb, cs), pts):
+            if len(phi) == 0:
+                continue
+            sel = synth.sample_indices(len(phi), 300)
+            ref = oracle_mod.dfs_eval(c, phi[sel], theta[sel])
+            err = float(np.linalg.norm(out.cpu().numpy()[0, sel] - ref[0]) / np.linalg.norm(ref[0]))
+            say(f"  round {round_} n {len(phi)} rel l2 {err:.2e}")
+            assert err <= 1e-6
+    g.destroy()
+    big.destroy()
+    small.destroy()
