@@ -43,8 +43,6 @@ template <> __device__ inline double es_kernel<double>(double z, double k)
     return exp(k * (sqrt(t) - 1.0));
 }
 
-constexpr int kGatherMaxFields = 4;
-
 constexpr int kGatherThreads = 256;
 constexpr int kLoadBatch = 4;
 // FP64 splits the rows of a point over two lanes when a chunk holds at most

@@ -233,8 +233,8 @@ NUFFT2_API nufft2_status nufft2_group_create(const nufft2_handle *plans, int32_t
         group_free(g);
         return NUFFT2_ERR_ALLOC;
     }
-    for (auto &c : g->classes) g->exec_kernels += 3;
-    for (auto &s : g->sets) g->setpts_kernels += 3;
+    g->exec_kernels = 3 * (int)g->classes.size();
+    g->setpts_kernels = 3 * (int)g->sets.size();
     *out = g;
     return NUFFT2_OK;
 }
