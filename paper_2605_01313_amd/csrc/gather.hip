@@ -121,19 +121,39 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
         // Stage the patch: each thread issues the loads of up to kLoadBatch
         // elements (all fields) before it stores any of them, so that one
         // memory round trip serves the batch.
+        // A thread's elements of a batch are kGatherThreads apart.  In FP32
+        // their (row, column) in the patch follow from the first one by the
+        // fixed step (step_r rows, step_c columns, with a carry): one integer
+        // division per batch instead of one per element (3% of the gather at
+        // 256 x 512; in FP64, with two batches, the compiler's code for it
+        // measured 1% slower, so FP64 divides per element).
+        const int step_r = kGatherThreads / TC, step_c = kGatherThreads - step_r * TC;
         for (int e0 = 0; e0 < tile_elems; e0 += kLoadBatch * kGatherThreads) {
             cplx<T> buf[kLoadBatch][FG];
+            int rr = (e0 + (int)threadIdx.x) / TC;
+            int cc = e0 + (int)threadIdx.x - rr * TC;
 #pragma unroll
             for (int u = 0; u < kLoadBatch; ++u) {
                 const int e = e0 + u * kGatherThreads + (int)threadIdx.x;
-                const int ec = e < tile_elems ? e : 0;
-                const int rr = ec / TC, cc = ec - rr * TC;
-                const int64_t off =
-                    (int64_t)((r0 + rr) & (gp.nft - 1)) * gp.nfp + ((c0 + cc) & (gp.nfp - 1));
+                if constexpr (sizeof(T) == 8) {
+                    rr = (e < tile_elems ? e : 0) / TC;
+                    cc = (e < tile_elems ? e : 0) - rr * TC;
+                }
+                const bool live = e < tile_elems;
+                const int64_t off = live ? (int64_t)((r0 + rr) & (gp.nft - 1)) * gp.nfp + ((c0 + cc) & (gp.nfp - 1))
+                                         : (int64_t)(r0 & (gp.nft - 1)) * gp.nfp + (c0 & (gp.nfp - 1));
 #pragma unroll
                 for (int f = 0; f < FG; ++f) {
                     const int ff = f0 + (f < fg ? f : 0);
                     buf[u][f] = grid[(int64_t)ff * field_stride + off];
+                }
+                if constexpr (sizeof(T) == 4) {
+                    rr += step_r;
+                    cc += step_c;
+                    if (cc >= TC) {
+                        cc -= TC;
+                        ++rr;
+                    }
                 }
             }
 #pragma unroll
