@@ -63,7 +63,11 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
                          int32_t *bincount, int32_t *binstart, int32_t *binlist, int64_t nbins,
                          int2 *keyrank,
                          uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
-                         int32_t *flags, hipStream_t s);
+                         int32_t *flags, int4 *stage, int2 *passtot, int32_t *lstart, hipStream_t s);
+// Workspace of the side-by-side scan passes for plans of more than
+// kDealtMaxBins bins: stage holds nbins int4, lstart nbins int32, passtot
+// one int2 per pass.
+inline int64_t scan_passes(int64_t nbins) { return (nbins + kDealtMaxBins - 1) / kDealtMaxBins; }
 
 // One member of a group for the setpts kernels (device memory; the
 // pointers as in launch_setpts).  Its n_pts points are point blocks

@@ -152,7 +152,7 @@ void free_all(nufft2_plan_s *p)
 {
     void *ptrs[] = {p->corr_t, p->corr_p, p->tw_t,  p->tw_p,  p->twist_t,   p->S,     p->grid,
                     p->bincount, p->binstart, p->binlist, p->rowmark, p->rowtouched, p->flags, p->keyrank,
-                    p->rec,    p->perm};
+                    p->rec,    p->perm,   p->stage, p->passtot, p->lstart};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     p->corr_t = p->corr_p = p->tw_t = p->tw_p = p->twist_t = p->S = p->grid = nullptr;
@@ -160,6 +160,9 @@ void free_all(nufft2_plan_s *p)
     p->rowmark = p->rowtouched = nullptr;
     p->keyrank = nullptr;
     p->rec = nullptr;
+    p->stage = nullptr;
+    p->passtot = nullptr;
+    p->lstart = nullptr;
 }
 
 bool dev_alloc(nufft2_plan_s *p, void **ptr, size_t bytes)
@@ -470,7 +473,11 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
               dev_alloc(p, (void **)&p->binlist, binlist_bytes(p->nbins)) &&
               dev_alloc(p, (void **)&p->rowmark, (size_t)p->nft) &&
               dev_alloc(p, (void **)&p->rowtouched, (size_t)p->nft) &&
-              dev_alloc(p, (void **)&p->flags, sizeof(int32_t) * 4);
+              dev_alloc(p, (void **)&p->flags, sizeof(int32_t) * 4) &&
+              (p->nbins <= kDealtMaxBins ||
+               (dev_alloc(p, (void **)&p->stage, sizeof(int4) * (size_t)p->nbins) &&
+                dev_alloc(p, (void **)&p->lstart, sizeof(int32_t) * (size_t)p->nbins) &&
+                dev_alloc(p, (void **)&p->passtot, sizeof(int2) * (size_t)scan_passes(p->nbins))));
     if (!ok) {
         free_all(p);
         delete p;
@@ -580,8 +587,8 @@ NUFFT2_API nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const dou
     const SetptsParams sp = plan_setpts_params(p, n_pts);
     const int slot = prof_begin(p, 0);
     hipError_t e = launch_setpts(p->prec, sp, phi_dev, theta_dev, p->bincount, p->binstart, p->binlist, p->nbins,
-                                 p->keyrank, p->rowmark, p->rowtouched, p->rec, p->perm, p->flags,
-                                 p->stream);
+                                 p->keyrank, p->rowmark, p->rowtouched, p->rec, p->perm, p->flags, p->stage,
+                                 p->passtot, p->lstart, p->stream);
     prof_end(p, slot);
     if (e != hipSuccess) return fail_hip(p, e);
     p->n_pts = n_pts;

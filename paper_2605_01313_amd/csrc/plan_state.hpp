@@ -36,6 +36,9 @@ struct nufft2_plan_s {
     int32_t *binlist = nullptr;  // non-empty bins in order, their number last
     uint8_t *rowmark = nullptr, *rowtouched = nullptr;
     int32_t *flags = nullptr;
+    int4 *stage = nullptr;    // side-by-side scan passes (more bins than one pass)
+    int2 *passtot = nullptr;
+    int32_t *lstart = nullptr;
     // point workspaces (grown by setpts)
     int64_t pts_cap = 0;
     int2 *keyrank = nullptr;

@@ -14,7 +14,8 @@
 //                      record at binstart[bin] + rank, and the permutation
 // For small plans (bins in one scan pass, points in one wave of 1024-thread
 // workgroups) k_setpts_scatter_scan replaces the last two: each workgroup
-// scans the counts itself (see there).
+// scans the counts itself (see there).  Plans of several scan passes run the
+// passes side by side (k_bin_scan_passes, k_setpts_scatter_passes).
 //
 // The order of points inside a bin depends on atomic arbitration; the output
 // of an exec does not, because each point's sum is computed by one thread in a
@@ -237,7 +238,7 @@ __device__ __attribute__((always_inline)) inline void scan_pass(const int (&in)[
         for (int e = threadIdx.x; e < ne_total; e += kScanThreads) {
             const int q = cmp_slot(e);
             const int b = cmp[q], s0 = cmp[kCmpLen + q], c0 = cmp[2 * kCmpLen + q];
-            binlist[carry_ne + e] = b;
+            if (binlist) binlist[carry_ne + e] = b;
             items[carry_ne + e] = make_int4(b, s0, c0, 0);
         }
     }
@@ -548,15 +549,139 @@ __global__ __launch_bounds__(kScanThreads) void k_setpts_scatter_scan(
     }
 }
 
+// Plans with more bins than one scan pass: the passes run side by side, one
+// workgroup each (k_bin_scan_passes), instead of one after another in one
+// workgroup.  Pass workgroup b scans its bins into pass-local starts
+// (lstart; it clears its own counters once read), writes its non-empty
+// entries with pass-local first records to stage[b * PASS + i], and its
+// totals {points, non-empty bins} to passtot[b]; workgroup 0 also derives
+// the reached rows and publishes the non-finite flag.  The scatter
+// (k_setpts_scatter_passes) then adds the prefix of the pass totals: it
+// places the points, writes the global starts, the bin list, its entries and
+// the gather's table.
+constexpr int kScanPass = kScanChunk * kScanThreads;
+constexpr int kMaxScanPasses = 128;  // nbins <= 2^20
+
+__global__ __launch_bounds__(kScanThreads) void k_bin_scan_passes(int32_t *__restrict__ bincount, int64_t nbins,
+                                                                  int32_t *__restrict__ lstart,
+                                                                  int4 *__restrict__ stage, int2 *__restrict__ passtot,
+                                                                  uint8_t *__restrict__ rowmark,
+                                                                  uint8_t *__restrict__ rowtouched, int nft, int w,
+                                                                  int32_t *__restrict__ flags)
+{
+    __shared__ int lds[2][33];
+    __shared__ int stg[kScanChunk * kScanThreads + kScanThreads];
+    __shared__ int cmp[3 * kCmpLen];
+    const int t = (int)threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanPass;
+    const int n = (int)((nbins - base) < kScanPass ? (nbins - base) : kScanPass);
+    const bool rows_wg = blockIdx.x == 0;
+    int h[kScanChunk];
+#pragma unroll
+    for (int k = 0; k < kScanChunk; ++k) {
+        const int e = k * kScanThreads + t;
+        h[k] = e < n ? bincount[base + e] : 0;
+    }
+    uint8_t mk[kMaxRowsPerScanThread];
+#pragma unroll
+    for (int i = 0; i < kMaxRowsPerScanThread; ++i) {
+        const int l = t + i * kScanThreads;
+        mk[i] = rows_wg && l < nft ? rowmark[l] : (uint8_t)0;
+    }
+    const int flag0 = rows_wg && t == 0 ? flags[0] : 0;
+#pragma unroll
+    for (int k = 0; k < kScanChunk; ++k) {
+        const int e = k * kScanThreads + t;
+        if (e < n) bincount[base + e] = 0;
+    }
+    int carry = 0, carry_ne = 0;
+    // pass-local starts; entries to this pass's stage region
+    scan_pass(h, base, n, stg, cmp, lds, carry, carry_ne, lstart, nullptr, stage + base);
+    if (t == 0) passtot[blockIdx.x] = make_int2(carry, carry_ne);
+    if (rows_wg) reached_rows(mk, flag0, reinterpret_cast<uint8_t *>(stg), rowmark, rowtouched, nft, w, flags);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_setpts_scatter_passes(
+    const double *__restrict__ phi, const double *__restrict__ theta, SetptsParams sp,
+    const int2 *__restrict__ keyrank, const int32_t *__restrict__ lstart, const int4 *__restrict__ stage,
+    const int2 *__restrict__ passtot, int npass, int32_t *__restrict__ binstart, int32_t *__restrict__ binlist,
+    int64_t nbins, PointRec<T> *__restrict__ rec, int32_t *__restrict__ perm)
+{
+    __shared__ int2 pre[kMaxScanPasses + 1];  // exclusive prefix of the pass totals
+    const int t = (int)threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + t;
+    double ph = 0.0, th = 0.0;
+    int2 kr = make_int2(0, 0);
+    if (j < sp.n) {
+        ph = phi[j];
+        th = theta[j];
+        kr = keyrank[j];
+    }
+    if (t == 0) {
+        int a = 0, c = 0;
+        for (int b = 0; b < npass; ++b) {
+            const int2 v = passtot[b];
+            pre[b] = make_int2(a, c);
+            a += v.x;
+            c += v.y;
+        }
+        pre[npass] = make_int2(a, c);
+    }
+    __syncthreads();
+    if (j < sp.n) {
+        PointRec<T> r;
+        if (!isfinite(ph) || !isfinite(th)) {
+            r.it = 0;
+            r.ip = 0;
+            r.vt = (T)NAN;
+            r.vp = (T)NAN;
+        } else {
+            split_axis<T>(th, sp.th, sp.w, r.it, r.vt);
+            split_axis<T>(ph, sp.ph, sp.w, r.ip, r.vp);
+        }
+        const int32_t pos = lstart[kr.x] + pre[kr.x / kScanPass].x + kr.y;
+        rec[pos] = r;
+        perm[pos] = (int32_t)j;
+    }
+    // the tables, grid-stride over bins, entries and gather slots
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + t, gstride = (int64_t)gridDim.x * blockDim.x;
+    const int n_ne = pre[npass].y;
+    int4 *items = bin_items(binlist, nbins);
+    int4 *dealt = bin_dealt(binlist, nbins);
+    for (int64_t i = gid; i < nbins; i += gstride) binstart[i] = lstart[i] + pre[i / kScanPass].x;
+    // entry i of the global list: pass b with pre[b].y <= i < pre[b + 1].y
+    auto entry = [&](int i) {
+        int b = 0;
+        while (b + 1 < npass && pre[b + 1].y <= i) ++b;
+        const int4 e = stage[(int64_t)b * kScanPass + (i - pre[b].y)];
+        return make_int4(e.x, e.y + pre[b].x, e.z, 0);
+    };
+    for (int64_t i = gid; i < n_ne; i += gstride) {
+        const int4 e = entry((int)i);
+        binlist[i] = e.x;
+        items[i] = e;
+    }
+    const int per = (n_ne + 7) >> 3;
+    const int64_t slots = gather_slots(nbins);
+    for (int64_t blk = gid; blk < slots; blk += gstride) {
+        const int k = (int)(blk >> 3), item = (int)(blk & 7) * per + k;
+        dealt[blk] = (k < per && item < n_ne) ? entry(item) : make_int4(0, 0, 0, 0);
+    }
+    if (gid == 0) {
+        binstart[nbins] = pre[npass].x;
+        binlist[nbins] = n_ne;
+    }
+}
+
 hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, const double *theta,
                          int32_t *bincount, int32_t *binstart, int32_t *binlist, int64_t nbins,
                          int2 *keyrank,
                          uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
-                         int32_t *flags, hipStream_t s)
+                         int32_t *flags, int4 *stage, int2 *passtot, int32_t *lstart, hipStream_t s)
 {
     // bincount, rowmark, flags[0] and the ticket flags[2] are zero on entry:
-    // the plan clears them once and every scan (k_bin_scan or
-    // k_setpts_scatter_scan) leaves them cleared.
+    // the plan clears them once and every path below leaves them cleared.
     hipError_t e;
     const int threads = 256;
     const int64_t blocks = (sp.n + threads - 1) / threads;
@@ -581,6 +706,22 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
             hipLaunchKernelGGL(k_setpts_scatter_scan<double>, dim3((unsigned)fused_blocks), dim3(kScanThreads), 0, s,
                                phi, theta, sp, bincount, binstart, binlist, (int)nbins, keyrank, rowmark,
                                rowtouched, sp.th.nf, flags, (PointRec<double> *)rec, perm);
+        return hipGetLastError();
+    }
+    const int64_t npass = (nbins + kScanPass - 1) / kScanPass;
+    if (sp.n > 0 && npass > 1 && npass <= kMaxScanPasses && stage && passtot && lstart &&
+        sp.th.nf <= kMaxRowsPerScanThread * kScanThreads) {
+        hipLaunchKernelGGL(k_bin_scan_passes, dim3((unsigned)npass), dim3(kScanThreads), 0, s, bincount, nbins,
+                           lstart, stage, passtot, rowmark, rowtouched, sp.th.nf, sp.w, flags);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (prec == 1)
+            hipLaunchKernelGGL(k_setpts_scatter_passes<float>, dim3((unsigned)blocks), dim3(threads), 0, s, phi, theta,
+                               sp, keyrank, lstart, stage, passtot, (int)npass, binstart, binlist, nbins,
+                               (PointRec<float> *)rec, perm);
+        else
+            hipLaunchKernelGGL(k_setpts_scatter_passes<double>, dim3((unsigned)blocks), dim3(threads), 0, s, phi,
+                               theta, sp, keyrank, lstart, stage, passtot, (int)npass, binstart, binlist, nbins,
+                               (PointRec<double> *)rec, perm);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kScanThreads), 0, s, bincount, binstart, binlist, nbins,

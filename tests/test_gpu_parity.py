@@ -275,6 +275,43 @@ def test_setpts_paths_alternate_on_one_plan(torch_dev, oracle_mod):
     plan.destroy()
 
 
+def test_scan_passes_side_by_side_on_a_large_plan(torch_dev, oracle_mod):
+    """A plan of four scan passes (32768 bins): point sets with points use
+    the side-by-side passes, an empty one the one-workgroup scan; each call
+    leaves the counters cleared, so every sort is valid and every result
+    meets the oracle."""
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Plan
+    rng = np.random.default_rng(43)
+    K = 1025
+    coeffs = (synth.random_complex(rng, (1, K, K)) * synth.envelope_algebraic(K, K, 1.5)[None])
+    plan = Plan("fp32", K, K, n_fields=1, eps=1e-6)
+    info = plan.info()
+    nb = info["n_bins"]
+    assert nb > 3 * 8192
+    c = torch.from_numpy(coeffs.astype(np.complex64)).to(dev)
+    for n in (50000, 0, 30000, 300000):
+        say(f"case scan_passes n={n}")
+        phi = rng.uniform(-1.0, 7.0, n)
+        theta = rng.uniform(0.0, np.pi, n)
+        plan.setpts(torch.from_numpy(phi).to(dev), torch.from_numpy(theta).to(dev))
+        got = plan.exec(c).cpu().numpy()
+        assert plan.check() == 0
+        starts_all = plan.debug_tensor(3, torch.int32, (nb + 1,)).cpu().numpy()
+        assert starts_all[0] == 0 and starts_all[-1] == n and np.all(np.diff(starts_all) >= 0)
+        check_binlist(plan, torch, starts_all)
+        if n == 0:
+            continue
+        perm = plan.debug_tensor(2, torch.int32, (n,)).cpu().numpy()
+        assert np.array_equal(np.sort(perm), np.arange(n))
+        sel = synth.sample_indices(n, 200)
+        ref = oracle_mod.dfs_eval(coeffs, phi[sel], theta[sel])
+        err = rel_l2(got[0, sel], ref[0])
+        say(f"  rel l2 {err:.2e}")
+        assert err <= 1e-6
+    plan.destroy()
+
+
 def test_zero_points_and_exec_before_setpts(torch_dev):
     torch, dev = torch_dev
     from paper_2605_01313_amd import Plan, nufft2
