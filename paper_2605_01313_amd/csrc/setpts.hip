@@ -561,6 +561,7 @@ __global__ __launch_bounds__(kScanThreads) void k_setpts_scatter_scan(
 // the gather's table.
 constexpr int kScanPass = kScanChunk * kScanThreads;
 constexpr int kMaxScanPasses = 128;  // nbins <= 2^20
+static_assert(kMaxScanPasses <= 2 * 64, "the scatter scans the pass totals in its first two waves");
 
 __global__ __launch_bounds__(kScanThreads) void k_bin_scan_passes(int32_t *__restrict__ bincount, int64_t nbins,
                                                                   int32_t *__restrict__ lstart,
@@ -609,24 +610,36 @@ __global__ __launch_bounds__(256) void k_setpts_scatter_passes(
     int64_t nbins, PointRec<T> *__restrict__ rec, int32_t *__restrict__ perm)
 {
     __shared__ int2 pre[kMaxScanPasses + 1];  // exclusive prefix of the pass totals
+    __shared__ int2 half0;                    // totals of passes 0..63
     const int t = (int)threadIdx.x;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + t;
     double ph = 0.0, th = 0.0;
     int2 kr = make_int2(0, 0);
+    int2 inc = t < npass ? passtot[t] : make_int2(0, 0);
     if (j < sp.n) {
         ph = phi[j];
         th = theta[j];
         kr = keyrank[j];
     }
-    if (t == 0) {
-        int a = 0, c = 0;
-        for (int b = 0; b < npass; ++b) {
-            const int2 v = passtot[b];
-            pre[b] = make_int2(a, c);
-            a += v.x;
-            c += v.y;
+    // pass b's totals on thread b: inclusive scan in each of the first two
+    // waves, then the second adds the first's total
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int yx = __shfl_up(inc.x, d, 64), yy = __shfl_up(inc.y, d, 64);
+        if ((t & 63) >= d) {
+            inc.x += yx;
+            inc.y += yy;
         }
-        pre[npass] = make_int2(a, c);
+    }
+    if (t == 63) half0 = inc;
+    __syncthreads();
+    if (t < kMaxScanPasses) {
+        if (t >= 64) {
+            inc.x += half0.x;
+            inc.y += half0.y;
+        }
+        pre[t + 1] = inc;
+        if (t == 0) pre[0] = make_int2(0, 0);
     }
     __syncthreads();
     if (j < sp.n) {
@@ -650,10 +663,16 @@ __global__ __launch_bounds__(256) void k_setpts_scatter_passes(
     int4 *items = bin_items(binlist, nbins);
     int4 *dealt = bin_dealt(binlist, nbins);
     for (int64_t i = gid; i < nbins; i += gstride) binstart[i] = lstart[i] + pre[i / kScanPass].x;
-    // entry i of the global list: pass b with pre[b].y <= i < pre[b + 1].y
+    // entry i of the global list: the last pass b with pre[b].y <= i (then
+    // i < pre[b + 1].y; passes without entries share their prefix with the
+    // next one)
     auto entry = [&](int i) {
-        int b = 0;
-        while (b + 1 < npass && pre[b + 1].y <= i) ++b;
+        int b = 0, hi = npass - 1;
+        while (b < hi) {
+            const int mid = (b + hi + 1) >> 1;
+            if (pre[mid].y <= i) b = mid;
+            else hi = mid - 1;
+        }
         const int4 e = stage[(int64_t)b * kScanPass + (i - pre[b].y)];
         return make_int4(e.x, e.y + pre[b].x, e.z, 0);
     };
