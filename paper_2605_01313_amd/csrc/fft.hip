@@ -412,7 +412,8 @@ __device__ inline void theta_body(int item, const cplx<T> *__restrict__ coeffs, 
                                   const uint8_t *__restrict__ touched, cplx<T> *__restrict__ S,
                                   const FFTParams &fp)
 {
-    extern __shared__ unsigned char smem_raw[];
+    // 16-byte aligned whatever size the static LDS arrays have
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int L = 1 << LOGL;
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
     uint8_t *flags = reinterpret_cast<uint8_t *>(tw + tw_lds_len(L));
@@ -483,7 +484,7 @@ __device__ inline void phi_body(int blk, const cplx<T> *__restrict__ S, const cp
                                 const uint8_t *__restrict__ touched, cplx<T> *__restrict__ grid,
                                 const FFTParams &fp)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
     cplx<T> *s = tw + tw_lds_len(1 << LOGN);
     const int nrb = fp.nft / fp.phi_batch;
@@ -675,7 +676,7 @@ __global__ __launch_bounds__(256) void k_analysis_phi(const T *__restrict__ vals
                                                       const int32_t *__restrict__ cut, cplx<T> *__restrict__ A,
                                                       int J, int rows_per_wg, int log_rows_per_wg)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int N = 1 << LOGN;  // = 2J
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
     cplx<T> *s = tw + tw_lds_len(N);
@@ -727,7 +728,7 @@ __global__ __launch_bounds__(512) void k_analysis_theta(const cplx<T> *__restric
                                                         cplx<T> *__restrict__ out, int J, int cols_per_wg,
                                                         int log_cols_per_wg)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int N = 1 << LOGN;  // = 2J
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
     cplx<T> *s = tw + tw_lds_len(N);

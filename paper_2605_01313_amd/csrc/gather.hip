@@ -70,7 +70,11 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
                                    const int32_t *__restrict__ perm, const int32_t *__restrict__ binlist,
                                    void *__restrict__ out, const GatherParams &gp)
 {
-    extern __shared__ unsigned char smem_raw[];
+    // The dynamic region starts right after the static LDS arrays below;
+    // without the alignment a static array whose size is not a multiple of
+    // 16 bytes misaligns every 16-byte complex read of the patch (a 4-6x
+    // slower gather, measured).
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T> *tiles = reinterpret_cast<cplx<T> *>(smem_raw);
     // Workgroups are dealt to the 8 XCDs round-robin.  XCD x (= blk & 7)
     // takes the x-th eighth of the non-empty bins in bin order, so that the
