@@ -49,12 +49,14 @@ constexpr int kLoadBatch = 4;
 // half a workgroup's points (see gather_body).
 template <typename T> constexpr bool kSplitRows = sizeof(T) == 8;
 
-// Lanes the LDS serves in one cycle for reads of one complex element (128
-// bytes per cycle over 32 four-byte banks, measured on gfx950 with the
-// SQ_LDS_BANK_CONFLICT counter): 16 for FP32, 8 for FP64.  Lanes of such a
-// group whose patch offsets differ modulo this number never collide on a
-// bank, whatever tap they read.
-template <typename T> constexpr int lds_lane_group() { return 128 / (int)sizeof(cplx<T>); }
+// Lanes the LDS serves together for reads of one complex element: 16, in
+// FP32 (8-byte reads, 128 bytes) and in FP64 (16-byte reads, 256 bytes over
+// 64 four-byte banks).  A CPU model of the tap reads with these groups and
+// bank slots (element offset modulo 16) reproduces the conflict rates
+// measured on gfx950 with SQ_LDS_BANK_CONFLICT for the 2048^2 wind
+// workload.  Lanes of such a group whose patch offsets differ modulo 16
+// never collide on a bank, whatever tap they read.
+template <typename T> constexpr int lds_lane_group() { return 16; }
 
 // Departure points sit near a lattice of spacing 2 fine cells (the grid nodes
 // at upsampling factor 2), so the patch offsets of the points of a bin share
@@ -105,7 +107,11 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
     const int bt = bin / gp.nbins_phi, bp = bin - bt * gp.nbins_phi;
     const int r0 = bt * gp.tile_t, c0 = bp * gp.tile_p;
     const int TR = gp.tile_t + W - 1, TC = gp.tile_p + W - 1;
-    const int tile_elems = TR * TC;
+    const int tile_elems = TR * TC;  // patch elements of one field
+    // LDS row pitch (FP64 may pad rows; FP32 never does, so that a staged
+    // element's LDS index is its patch index) and LDS elements per field
+    const int TCP = sizeof(T) == 4 ? TC : gp.tile_pitch;
+    const int plane = TR * TCP;
     const T inv_hw = (T)2 / (T)W;
     const T kc = es_constant<T>(gp.beta);
     constexpr int H = W / 2;
@@ -134,6 +140,7 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
         const int step_r = kGatherThreads / TC, step_c = kGatherThreads - step_r * TC;
         for (int e0 = 0; e0 < tile_elems; e0 += kLoadBatch * kGatherThreads) {
             cplx<T> buf[kLoadBatch][FG];
+            int li[kLoadBatch];  // LDS index of each element (FP64)
             int rr = (e0 + (int)threadIdx.x) / TC;
             int cc = e0 + (int)threadIdx.x - rr * TC;
 #pragma unroll
@@ -142,6 +149,7 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
                 if constexpr (sizeof(T) == 8) {
                     rr = (e < tile_elems ? e : 0) / TC;
                     cc = (e < tile_elems ? e : 0) - rr * TC;
+                    li[u] = rr * TCP + cc;
                 }
                 const bool live = e < tile_elems;
                 const int64_t off = live ? (int64_t)((r0 + rr) & (gp.nft - 1)) * gp.nfp + ((c0 + cc) & (gp.nfp - 1))
@@ -164,8 +172,9 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
             for (int u = 0; u < kLoadBatch; ++u) {
                 const int e = e0 + u * kGatherThreads + (int)threadIdx.x;
                 if (e < tile_elems) {
+                    const int l = sizeof(T) == 4 ? e : li[u];
 #pragma unroll
-                    for (int f = 0; f < FG; ++f) tiles[f * tile_elems + e] = buf[u][f];
+                    for (int f = 0; f < FG; ++f) tiles[f * plane + l] = buf[u][f];
                 }
             }
         }
@@ -195,7 +204,7 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
                 dsts[t] = d;
                 recs[t] = q;
                 const bool qbad = !(q.vt == q.vt) || !(q.vp == q.vp);
-                key = qbad ? 0 : ((q.it - r0) * TC + (q.ip - c0) + column_rotation(q.it, q.ip)) & (NK - 1);
+                key = qbad ? 0 : ((q.it - r0) * TCP + (q.ip - c0) + column_rotation(q.it, q.ip)) & (NK - 1);
                 rank = atomicAdd(&bucket[key], 1);
             }
             __syncthreads();
@@ -253,7 +262,7 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
 #pragma unroll RU
             for (int a = a_begin; a < a_end; ++a) {
                 const T wt = es_kernel<T>(((T)(a - H) - pr.vt) * inv_hw, kc);
-                const cplx<T> *row = tiles + (lr + a) * TC + lc;
+                const cplx<T> *row = tiles + (lr + a) * TCP + lc;
                 const cplx<T> *rrow = row + rot;
                 T rx[FG], ry[FG];
 #pragma unroll
@@ -263,7 +272,7 @@ __device__ inline void gather_body(int blk, const cplx<T> *__restrict__ grid, co
 #pragma unroll
                     for (int f = 0; f < FG; ++f) {
                         // fields past fg read stale LDS; their sums are never stored
-                        const cplx<T> v = b < W - 1 ? rrow[f * tile_elems + b] : row[f * tile_elems + last];
+                        const cplx<T> v = b < W - 1 ? rrow[f * plane + b] : row[f * plane + last];
                         rx[f] += wp[b] * v.x;
                         ry[f] += wp[b] * v.y;
                     }
@@ -334,7 +343,9 @@ static hipError_t launch_wf(const GatherParams &gp, const void *grid, const void
                             const int32_t *perm, const int32_t *binlist, void *out, const GatherJob *jobs,
                             int n_members, hipStream_t s)
 {
-    const size_t lds = sizeof(cplx<T>) * (size_t)(gp.tile_t + W - 1) * (gp.tile_p + W - 1) * FG;
+    const int pitch = sizeof(T) == 4 ? gp.tile_p + W - 1 : gp.tile_pitch;
+    if (pitch < gp.tile_p + W - 1) return hipErrorInvalidValue;
+    const size_t lds = sizeof(cplx<T>) * (size_t)(gp.tile_t + W - 1) * pitch * FG;
     const int per = (int)(8 * ((gp.nbins + 7) / 8));
     if (jobs) {
         auto kern = k_gather_group<T, W, FG>;

@@ -134,6 +134,7 @@ struct GatherParams {
     double beta;
     int32_t n_fields;
     int32_t fields_per_pass;   // fields staged in LDS together (1..4)
+    int32_t tile_pitch;        // LDS row pitch of a staged patch, in elements (>= tile_p + w - 1)
     int64_t n_pts;
     int32_t real_output;
 };

@@ -21,6 +21,7 @@ struct nufft2_plan_s {
     int64_t nbins = 0;
     int real_output = 0;
     int fields_per_pass = 1;
+    int tile_pitch = 0;  // gather patch row pitch in LDS (elements)
     hipStream_t stream = nullptr;
     int device = 0;
     size_t csize = 0;  // bytes per complex
