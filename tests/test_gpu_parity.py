@@ -241,6 +241,28 @@ def test_largest_grid(torch_dev, oracle_mod, prec, eps, tol):
     assert max(errs) <= tol
 
 
+@pytest.mark.parametrize("tt,tp", [(16, 16), (32, 64), (128, 16)])
+def test_fp64_gather_tile_shapes(torch_dev, oracle_mod, tt, tp):
+    """FP64 gather patches with padded LDS rows (16 x 16: 28 -> 32 elements;
+    32 x 64: 76 -> 80) and with unpadded ones where the padded patch of a
+    field would pass the LDS limit (128 x 16: 140 rows of 28, not of 32), on
+    three fields and points around the whole torus."""
+    rng = np.random.default_rng(1000 + tt + tp)
+    K = 255
+    coeffs = synth.random_complex(rng, (3, K, K)) * synth.envelope_algebraic(K, K, 1.5)[None]
+    phi = rng.uniform(-1.0, 7.0, 3000)
+    theta = rng.uniform(-0.5, 2 * np.pi + 0.5, 3000)
+    say(f"case fp64_tiles tt={tt} tp={tp}")
+    plan, got = run_plan(torch_dev, "fp64", coeffs, phi, theta, 1e-12, tile_theta=tt, tile_phi=tp)
+    info = plan.info()
+    assert (info["tile_theta"], info["tile_phi"]) == (tt, tp) and plan.check() == 0
+    sel = synth.sample_indices(len(phi), 400)
+    errs = field_errors(got[:, sel], oracle_mod.dfs_eval(coeffs, phi[sel], theta[sel]))
+    say(f"  rel l2 {errs}")
+    assert max(errs) <= 1e-12
+    plan.destroy()
+
+
 def test_setpts_paths_alternate_on_one_plan(torch_dev, oracle_mod):
     """Point counts on both sides of the limit of the fused sort (at most 256
     workgroups of 1024 points; above it the separate scan kernel runs) on one
