@@ -241,6 +241,30 @@ def test_largest_grid(torch_dev, oracle_mod, prec, eps, tol):
     assert max(errs) <= tol
 
 
+@pytest.fixture(scope="module")
+def wind_large():
+    return synth.workload_large()
+
+
+@pytest.mark.parametrize("prec,eps,tol", [("fp32", 1e-6, 1e-6), ("fp64", 1e-12, 1e-12)])
+def test_wind_1024x2048_full_size_sampled(torch_dev, oracle_mod, wind_large, prec, eps, tol):
+    """The 1024 x 2048 workload at full size (2,097,152 wind departure points,
+    K = 2047, 3 fields, algebraically decaying spectra) in the default plan
+    configuration the bench times (side-by-side scan passes, 2048 x 2048
+    theta/phi transforms, 16 x 32 gather tiles): 512 sampled outputs per
+    field against the oracle."""
+    wl = wind_large
+    say(f"case wind1024 full size prec={prec}")
+    plan, got = run_plan(torch_dev, prec, wl.coeffs, wl.phi, wl.theta, eps)
+    info = plan.info()
+    assert plan.check() == 0 and info["n_pts"] == wl.n_pts and info["n_bins"] > 8192
+    sel = synth.sample_indices(wl.n_pts, 512)
+    errs = field_errors(got[:, sel], oracle_mod.dfs_eval(wl.coeffs, wl.phi[sel], wl.theta[sel]))
+    say(f"  rel l2 {errs}")
+    assert max(errs) <= tol
+    plan.destroy()
+
+
 @pytest.mark.parametrize("tt,tp", [(16, 16), (32, 64), (128, 16)])
 def test_fp64_gather_tile_shapes(torch_dev, oracle_mod, tt, tp):
     """FP64 gather patches with padded LDS rows (16 x 16: 28 -> 32 elements;
