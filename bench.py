@@ -10,7 +10,7 @@ headline value is the FP32 plan at eps = 1e-6 (w = 7), and the FP64 plan at
 eps = 1e-12 (w = 13) is reported beside it.  Inputs are resident in HBM
 before the timed region starts.
 
-Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -579,7 +579,7 @@ def main():
                     help="also run a plain 256 MiB device copy (counter scale for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
