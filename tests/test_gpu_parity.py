@@ -418,6 +418,39 @@ def test_nonfinite_points_give_nan_and_flag(torch_dev):
     assert plan.check() == 0
 
 
+@pytest.mark.parametrize("prec,eps,tol", [("fp32", 1e-6, 3e-6), ("fp64", 1e-12, 3e-12)])
+def test_nonfinite_points_on_a_large_plan(torch_dev, oracle_mod, prec, eps, tol):
+    """Non-finite coordinates on a plan whose scan passes run side by side
+    (K = 1025, more than 8192 bins): NaN outputs, the flag from check(), the
+    other points meet the oracle, and the next setpts with finite points
+    (through the same passes) clears the flag."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(81)
+    K, n = 1025, 40000
+    coeffs = synth.random_complex(rng, (2, K, K))
+    phi = rng.uniform(-1.0, 7.0, n)
+    theta = rng.uniform(-0.3, np.pi + 0.3, n)
+    bad_idx = [0, 17, 20000, n - 1]
+    phi[bad_idx[:2]] = [np.nan, -np.inf]
+    theta[bad_idx[2:]] = [np.inf, np.nan]
+    say(f"case nonfinite large plan prec={prec}")
+    plan, got = run_plan(torch_dev, prec, coeffs, phi, theta, eps)
+    assert plan.info()["n_bins"] > 8192
+    bad = np.zeros(n, bool)
+    bad[bad_idx] = True
+    assert np.all(np.isnan(got[:, bad])) and np.all(np.isfinite(got[:, ~bad]))
+    assert plan.check() == 5        # NUFFT2_ERR_NONFINITE
+    sel = np.where(~bad)[0][synth.sample_indices(n - len(bad_idx), 300)]
+    errs = field_errors(got[:, sel], oracle_mod.dfs_eval(coeffs, phi[sel], theta[sel]))
+    say(f"  rel l2 {errs}")
+    assert max(errs) <= tol         # white spectrum: 3 eps
+    phi2 = rng.uniform(0.0, 6.0, 30000)
+    theta2 = rng.uniform(0.0, 3.0, 30000)
+    plan.setpts(torch.from_numpy(phi2).to(dev), torch.from_numpy(theta2).to(dev))
+    assert plan.check() == 0
+    plan.destroy()
+
+
 def test_repeatable_and_fieldwise(torch_dev, oracle_mod):
     """Two execs give identical bits; multi-field equals fields run one by one."""
     torch, dev = torch_dev
