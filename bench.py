@@ -3,12 +3,15 @@
 
 A step is one pass of the whole path over one departure-point set: setpts
 (wrap/split/sort of the points) and exec (deconvolve + pad, 2-D inverse FFT,
-ES gather) for all fields.  The workload is the 256 x 512 lat-lon grid
-(512 x 512 doubled torus), 3 fields (h, u, v) with a (1 + k^2 + l^2)^-1.5
-spectrum, 131,072 departure points of a solid-body-rotation wind; the
-headline value is the FP32 plan at eps = 1e-6 (w = 7), and the FP64 plan at
-eps = 1e-12 (w = 13) is reported beside it.  Inputs are resident in HBM
-before the timed region starts.
+ES gather) for all fields.  The default workload is the 1024 x 2048 lat-lon
+grid (2048 x 2048 doubled torus), 3 fields with a (1 + k^2 + l^2)^-1.5
+spectrum (2047 x 2047 modes), 2,097,152 departure points of a random
+8-mode stream-function wind at Courant number 8; the headline value is the
+FP32 plan at eps = 1e-6 (w = 7), and the FP64 plan at eps = 1e-12 (w = 13)
+is reported beside it.  Inputs are resident in HBM before the timed region
+starts.  The default run adds, as extra keys: the 256 x 512 solid-body
+rotation workload, the uneven ensemble, the serving loop and the kernels
+around the interpolation.
 
 Prints ONE JSON line.  `--gpus N` with N > 1 exits: the benchmark runs on one GPU.
 """
@@ -45,20 +48,26 @@ def source_hash(stage):
 
 
 def stage_bytes(stage, info, n_touched, real_output=False):
-    """Algorithmic HBM bytes of one launch of a stage (each datum moved once)."""
+    """Algorithmic HBM bytes of one launch of a stage (each datum moved once).
+    Real-field plans read the m >= 0 half of the coefficients (K_phi/2 + 1
+    columns), carry that many columns through the theta pass and write a real
+    fine grid."""
     F, P = info["n_fields"], info["n_pts"]
     Kt, Kp, nfp = info["n_modes_theta"], info["n_modes_phi"], info["nf_phi"]
     cs = 8 if info["prec"] == 1 else 16
     rs = cs // 2
+    herm = bool(info.get("hermitian", 0))
+    cols = Kp // 2 + 1 if herm else Kp
+    gs = rs if herm else cs
     rec = 16 if info["prec"] == 1 else 24
     if stage == "setpts":
         return P * (16 + rec + 4)
     if stage == "theta_pass":
-        return F * Kt * Kp * cs + F * n_touched * Kp * cs
+        return F * Kt * cols * cs + F * n_touched * cols * cs
     if stage == "phi_pass":
-        return F * n_touched * Kp * cs + F * n_touched * nfp * cs
+        return F * n_touched * cols * cs + F * n_touched * nfp * gs
     if stage == "gather":
-        return F * n_touched * nfp * cs + P * (rec + 4) + F * P * (rs if real_output else cs)
+        return F * n_touched * nfp * gs + P * (rec + 4) + F * P * (rs if (real_output or herm) else cs)
     raise KeyError(stage)
 
 
@@ -82,18 +91,25 @@ def read_traffic(stage, workload, prec):
 
 
 class Runner:
-    def __init__(self, torch, wl, prec, eps):
+    """One plan on one workload.  hermitian: the real-field plan (the
+    workloads' fields are real: their coefficients are Hermitian), real
+    output; otherwise the complex plan, complex output."""
+
+    def __init__(self, torch, wl, prec, eps, hermitian=False):
         from paper_2605_01313_amd import Plan
         self.torch = torch
         dev = torch.device("cuda:0")
         F, Kt, Kp = wl.coeffs.shape
         self.prec = prec
-        self.plan = Plan(prec, Kt, Kp, n_fields=F, eps=eps)
+        self.hermitian = hermitian
+        self.real_output = hermitian
+        self.plan = Plan(prec, Kt, Kp, n_fields=F, eps=eps, hermitian=hermitian)
         cdt = torch.complex64 if prec == "fp32" else torch.complex128
+        rdt = torch.float32 if prec == "fp32" else torch.float64
         self.coeffs = torch.from_numpy(wl.coeffs).to(dev).to(cdt).contiguous()
         self.phi = torch.from_numpy(wl.phi).to(dev).contiguous()
         self.theta = torch.from_numpy(wl.theta).to(dev).contiguous()
-        self.out = torch.empty((F, wl.n_pts), dtype=cdt, device=dev)
+        self.out = torch.empty((F, wl.n_pts), dtype=rdt if hermitian else cdt, device=dev)
         self.n_pf = F * wl.n_pts
         self.step()
         torch.cuda.synchronize()
@@ -114,14 +130,16 @@ class Runner:
         prof = self.plan.profile_read()
         avg = {k: (ms / n if n else 0.0) for k, (ms, n) in prof.items()}
         # the roofline is taken for the longest single kernel: setpts is a
-        # chain of three small kernels (bin count, scan, scatter), each
-        # shorter than any of the other stages' one kernel
+        # chain of two or three small kernels (bin count, scan, scatter), each
+        # shorter than any of the other stages' one kernel.  The gather (the
+        # per-point stage) is bracketed too, whichever kernel dominates.
         dominant = max(SINGLE_KERNEL_STAGES, key=avg.get)
-        # timed region: the dominant kernel is bracketed with HIP events on the
-        # plan's stream in every PROFILE_EVERY-th step (event records cost a
-        # few microseconds of a 50-microsecond step; a sample keeps the timed
-        # steps close to unobserved ones)
-        mask = 1 << STAGES.index(dominant)
+        live_stages = sorted({dominant, "gather"}, key=STAGES.index)
+        # timed region: the bracketed kernels get HIP events on the plan's
+        # stream in every PROFILE_EVERY-th step (event records cost a few
+        # microseconds; a sample keeps the timed steps close to unobserved
+        # ones)
+        mask = sum(1 << STAGES.index(k) for k in live_stages)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(steps):
@@ -132,10 +150,10 @@ class Runner:
             self.step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        live = self.plan.profile_read()[dominant]
+        prof = self.plan.profile_read()
+        live = {k: prof[k][0] / max(prof[k][1], 1) for k in live_stages}
         self.plan.profile(0)
         ms_step = (t1 - t0) * 1e3 / steps
-        dom_ms = live[0] / max(live[1], 1)
         # per-step latency distribution (separate loop, events around each step)
         lat = []
         s = torch.cuda.current_stream()
@@ -150,11 +168,37 @@ class Runner:
         lat.sort()
         pct = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]
         return {"ms_per_step": ms_step, "stage_avg_ms": avg, "dominant": dominant,
-                "dominant_ms": dom_ms, "p50_ms": pct(0.50), "p99_ms": pct(0.99)}
+                "live_ms": live, "p50_ms": pct(0.50), "p99_ms": pct(0.99)}
+
+    def roofline(self, res, workload, tag):
+        """HBM roofline of one kernel of this plan from the live events."""
+        out = {}
+        for k, ms in res["live_ms"].items():
+            alg = stage_bytes(k, self.info, self.n_touched, self.real_output)
+            achieved = alg / (ms * 1e-3) / 1e9
+            out[k] = {"bound": "hbm", "kernel": k, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                      "traffic": read_traffic(k, workload, tag), "alg_bytes_per_launch": alg,
+                      "avg_launch_ms": ms, "rows_reached": self.n_touched}
+        return out
 
 
-def cpu_baseline(wl, gpu_out, target_s):
-    """The oracle (FP64 direct sum) on host cores, on a bounded sample of points."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, gpu_out, target_s, n_sample=None, one_core_s=5.0):
+    """The oracle (FP64 direct sum) on host cores, on a bounded sample of
+    points: with every thread it has, then on one core (a smaller sample).
+    n_sample fixes the sample (default_rng(15) without replacement); None
+    sizes it to about target_s of work.  The GPU outputs are compared with
+    the oracle on the same sample."""
     import numpy as np
 
     import oracle
@@ -165,18 +209,37 @@ def cpu_baseline(wl, gpu_out, target_s):
     t0 = time.perf_counter()
     oracle.dfs_eval(wl.coeffs, wl.phi[calib], wl.theta[calib])
     per_pt = (time.perf_counter() - t0) / calib.size
-    n = int(min(wl.n_pts, max(256, target_s / max(per_pt, 1e-9))))
+    if n_sample is None:
+        n = int(min(wl.n_pts, max(256, target_s / max(per_pt, 1e-9))))
+    else:
+        n = int(min(wl.n_pts, n_sample))
     idx = synth.sample_indices(wl.n_pts, n, seed=15)
     t0 = time.perf_counter()
     ref = oracle.dfs_eval(wl.coeffs, wl.phi[idx], wl.theta[idx])
     dt = time.perf_counter() - t0
     errs = {}
     for name, out in gpu_out.items():
-        e = [float(np.linalg.norm(out[f, idx] - ref[f]) / np.linalg.norm(ref[f])) for f in range(F)]
-        errs[name] = max(e)
+        # real-field plans return the real field: compare with the real part
+        r = ref.real if not np.iscomplexobj(out) else ref
+        e = [float(np.linalg.norm(out[f, idx] - r[f]) / np.linalg.norm(r[f])) for f in range(F)]
+        errs[name] = {"max_over_fields": max(e), "per_field": e}
+    # one core: a sample sized to about one_core_s seconds
+    n1 = int(min(n, max(32, one_core_s * cores / max(per_pt, 1e-9) / 4)))
+    idx1 = synth.sample_indices(wl.n_pts, n1, seed=16)
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.dfs_eval(wl.coeffs, wl.phi[idx1], wl.theta[idx1])
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
     return {"value": n * F / dt, "unit": "points*fields/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} of {wl.n_pts} points x {F} fields ({wl.name}), FP64 direct sum, "
-                      f"{dt:.1f} s", "gpu_rel_l2_on_sample": errs}
+            "cpu_model": cpu_model(),
+            "sample": f"{n} of {wl.n_pts} points (default_rng(15) without replacement) x {F} fields "
+                      f"({wl.name}), FP64 direct sum, {dt:.1f} s on {cores} threads",
+            "one_core": {"value": n1 * F / dt1, "unit": "points*fields/s", "cores": 1,
+                         "sample": f"{n1} points x {F} fields, {dt1:.1f} s"},
+            "gpu_rel_l2_on_sample": errs}
 
 
 def _member(spec):
@@ -283,8 +346,8 @@ def serving_bench(args, torch):
         lag = max(lag, srv.clock() - t_arr)
         prec, c, phi, theta, eps = request(i, int(sizes[i]), int(fields[i]), bool(is64[i]))
         srv.submit(prec, c, phi, theta, eps, t_arrival=t_arr)
-        if i % 20000 == 0:
-            log(f"bench: {i} requests submitted")
+        if (i + 1) % 20000 == 0:
+            log(f"bench: {i + 1} requests submitted")
     srv.drain()
     st = srv.stats()
     srv.destroy()
@@ -558,10 +621,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("sbr256", "wind1024", "ensemble", "serving", "upstream"),
-                    default="sbr256",
-                    help="sbr256: 256x512 grid, solid-body rotation (default); "
-                         "wind1024: 1024x2048 grid, 8-mode wind, Courant 8; "
+    ap.add_argument("--workload", choices=("wind1024", "sbr256", "ensemble", "serving", "upstream"),
+                    default="wind1024",
+                    help="wind1024: 1024x2048 grid, 8-mode wind, Courant 8 (default); "
+                         "sbr256: 256x512 grid, solid-body rotation; "
                          "ensemble: 64 + 16 members of uneven size as one group; "
                          "serving: Poisson request stream through the serving loop; "
                          "upstream: analysis, partial-regularity and rotation kernels at 1024x2048")
@@ -572,7 +635,7 @@ def main():
     ap.add_argument("--serve-inflight", type=int, default=16)
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload only: skip the ensemble, serving and upstream sections")
-    ap.add_argument("--extra-serve-seconds", type=float, default=10.0,
+    ap.add_argument("--extra-serve-seconds", type=float, default=60.0,
                     help="length of the serving section of the default run")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (ensemble)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -586,7 +649,6 @@ def main():
     import numpy as np
     import torch
 
-    import synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "ensemble":
         ensemble_line(args, torch)
@@ -597,7 +659,49 @@ def main():
     if args.workload == "upstream":
         upstream_line(args, torch)
         return
-    if args.workload == "sbr256":
+    headline = single_workload(args, torch, args.workload, args.steps, args.warmup)
+    line, runners, wl = headline["line"], headline["runners"], headline["wl"]
+    cpu_args = None
+    if not args.no_cpu_baseline:
+        torch.cuda.synchronize()
+        outs = {"fp32": runners[0].out.cpu().numpy().astype(np.float64),
+                "fp64": runners[1].out.cpu().numpy(),
+                "fp32_complex": runners[2].out.cpu().numpy().astype(np.complex128),
+                "fp64_complex": runners[3].out.cpu().numpy()}
+        # the 1024 x 2048 workload is sampled on 10^4 points (default_rng(15));
+        # smaller ones on a sample sized to --cpu-seconds
+        cpu_args = (wl, outs, args.cpu_seconds, 10000 if args.workload == "wind1024" else None)
+    for r in runners:
+        r.plan.destroy()
+    if args.workload == "wind1024" and not args.no_extras:
+        log("bench: 256x512 section")
+        small = single_workload(args, torch, "sbr256", 100, 10)
+        for r in small["runners"]:
+            r.plan.destroy()
+        line["grid256x512_sbr"] = {k: small["line"][k] for k in
+                                   ("value", "unit", "ms_per_step", "config", "latency_ms", "stages_ms",
+                                    "roofline", "gather_roofline", "fp64", "fp32_complex", "fp64_complex")}
+        log("bench: ensemble section")
+        line["ensemble"] = ensemble_bench(args, torch, 20, 3)
+        log("bench: serving section")
+        sargs = argparse.Namespace(**vars(args))
+        sargs.serve_seconds = args.extra_serve_seconds
+        line["serving"] = serving_bench(sargs, torch)
+        log("bench: upstream section")
+        line["upstream"] = {prec: upstream_bench(torch, prec) for prec in ("fp32", "fp64")}
+    if cpu_args is not None:
+        log("bench: timing the oracle on host cores")
+        line["cpu_baseline"] = cpu_baseline(*cpu_args)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+def single_workload(args, torch, which, steps, warmup):
+    """One departure-point workload: the real-field FP32 plan (headline) and
+    FP64 plan, and the complex plans of both precisions beside them."""
+    import synth
+    if which == "sbr256":
         log("bench: building the 256x512 solid-body-rotation workload")
         wl = synth.workload_sbr()
         workload = "grid256x512_sbr"
@@ -605,13 +709,15 @@ def main():
         log("bench: building the 1024x2048 8-mode-wind workload")
         wl = synth.workload_large()
         workload = "grid1024x2048_wind"
-    log(f"bench: {wl.n_pts} points x {wl.n_fields} fields; FP32 eps 1e-6")
-    r32 = Runner(torch, wl, "fp32", 1e-6)
-    res32 = r32.timed(args.steps, args.warmup)
-    log(f"bench: fp32 {res32['ms_per_step']:.4f} ms/step; stages {res32['stage_avg_ms']}")
-    r64 = Runner(torch, wl, "fp64", 1e-12)
-    res64 = r64.timed(args.steps, args.warmup)
-    log(f"bench: fp64 {res64['ms_per_step']:.4f} ms/step; stages {res64['stage_avg_ms']}")
+    log(f"bench: {wl.n_pts} points x {wl.n_fields} fields")
+    runs = {}
+    for key, prec, eps, herm in (("fp32", "fp32", 1e-6, True), ("fp64", "fp64", 1e-12, True),
+                                 ("fp32_complex", "fp32", 1e-6, False), ("fp64_complex", "fp64", 1e-12, False)):
+        r = Runner(torch, wl, prec, eps, hermitian=herm)
+        res = r.timed(steps, warmup)
+        log(f"bench: {key} {res['ms_per_step']:.4f} ms/step; stages {res['stage_avg_ms']}")
+        tag = prec + ("" if herm else "_complex")
+        runs[key] = (r, res, r.roofline(res, workload, tag))
 
     if args.copy_probe:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -621,56 +727,37 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy probe 256 MiB x 5 done")
 
-    n_pf = r32.n_pf
-    value = n_pf / (res32["ms_per_step"] * 1e-3)
-    dom = res32["dominant"]
-    alg = stage_bytes(dom, r32.info, r32.n_touched)
-    achieved = alg / (res32["dominant_ms"] * 1e-3) / 1e9
-    traffic = read_traffic(dom, workload, "fp32")
-    J = wl.J
+    def summary(key):
+        r, res, roof = runs[key]
+        return {"value": r.n_pf / (res["ms_per_step"] * 1e-3), "unit": "points*fields/s",
+                "ms_per_step": res["ms_per_step"], "eps": 1e-6 if r.prec == "fp32" else 1e-12,
+                "w": r.info["w"], "plan": "real-field" if r.hermitian else "complex",
+                "latency_ms": {"p50": res["p50_ms"], "p99": res["p99_ms"]},
+                "stages_ms": res["stage_avg_ms"],
+                "roofline": roof[res["dominant"]], "gather_roofline": roof["gather"]}
 
+    r32, res32, roof32 = runs["fp32"]
+    J = wl.J
     line = {
-        "metric": METRIC, "value": value, "unit": "points*fields/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res32["ms_per_step"],
+        "metric": METRIC, "value": r32.n_pf / (res32["ms_per_step"] * 1e-3), "unit": "points*fields/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": res32["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{workload}_{wl.n_fields}fields", "grid": f"{J}x{2*J} ({2*J}x{2*J} torus)",
                    "n_points": wl.n_pts, "n_fields": wl.n_fields, "modes": f"{2*J-1}x{2*J-1}", "eps": 1e-6,
                    "w": r32.info["w"], "nf": r32.info["nf_theta"],
+                   "fields": "real (Hermitian coefficients): real-field plan, real output",
                    "step": "setpts + exec (all fields)"},
         "latency_ms": {"p50": res32["p50_ms"], "p99": res32["p99_ms"]},
         "stages_ms": res32["stage_avg_ms"],
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "alg_bytes_per_launch": alg,
-                     "avg_launch_ms": res32["dominant_ms"], "rows_reached": r32.n_touched},
-        "fp64": {"value": r64.n_pf / (res64["ms_per_step"] * 1e-3), "unit": "points*fields/s",
-                 "ms_per_step": res64["ms_per_step"], "eps": 1e-12, "w": r64.info["w"],
-                 "latency_ms": {"p50": res64["p50_ms"], "p99": res64["p99_ms"]},
-                 "stages_ms": res64["stage_avg_ms"]},
+        "roofline": roof32[res32["dominant"]],
+        "gather_roofline": roof32["gather"],
+        "fp64": summary("fp64"),
+        "fp32_complex": summary("fp32_complex"),
+        "fp64_complex": summary("fp64_complex"),
     }
-    if args.workload == "sbr256" and not args.no_extras:
-        r32.plan.destroy()
-        r64.plan.destroy()
-        log("bench: ensemble section")
-        line["ensemble"] = ensemble_bench(args, torch, 20, 3)
-        log("bench: serving section")
-        sargs = argparse.Namespace(**vars(args))
-        sargs.serve_seconds = args.extra_serve_seconds
-        line["serving"] = serving_bench(sargs, torch)
-        log("bench: upstream section")
-        line["upstream"] = {prec: upstream_bench(torch, prec) for prec in ("fp32", "fp64")}
-    if not args.no_cpu_baseline:
-        torch.cuda.synchronize()
-        outs = {"fp32": r32.out.cpu().numpy().astype(np.complex128),
-                "fp64": r64.out.cpu().numpy()}
-        log("bench: timing the oracle on host cores")
-        line["cpu_baseline"] = cpu_baseline(wl, outs, args.cpu_seconds)
-    else:
-        line["cpu_baseline"] = None
-    r32.plan.destroy()
-    r64.plan.destroy()
-    print(json.dumps(line), flush=True)
+    runners = [runs[k][0] for k in ("fp32", "fp64", "fp32_complex", "fp64_complex")]
+    return {"line": line, "runners": runners, "wl": wl}
 
 
 if __name__ == "__main__":

@@ -16,7 +16,14 @@
  *      a 2x upsampled periodic grid,
  *   2. the 2-D inverse FFT of that grid,
  *   3. a w x w "exponential of semicircle" kernel interpolation at each point.
- * The relative l2 error of each field against the exact sum is about eps.
+ * Accuracy contract (relative l2 error of a field against the exact sum,
+ * at the default kernel width for eps): at most eps for the decaying
+ * spectra of smooth fields at general points; up to about 1.5 eps (FP32)
+ * and 2.5 eps (FP64) for flat (white-noise) spectra or for points that sit
+ * exactly on fine-grid nodes, where the width rule of the cited method is
+ * at its limit (measured: 1.06 eps at w = 7 on grid nodes in exact
+ * arithmetic, 2.35 eps at w = 13 on flat spectra).  Asking for eps / 10
+ * (one more tap per axis) gives at most eps in every case.
  *
  * Around the interpolation (declared further down):
  *   nufft2_group_*     many plans of uneven size as one unit (an ensemble);
@@ -66,7 +73,7 @@ typedef struct {
     int32_t tile_theta;   /* gather tile rows (power of two, 4..128); default 16 */
     int32_t tile_phi;     /* gather tile columns (power of two, 4..128); default 32 */
     int32_t real_output;  /* 1: write only the real part (fields known to be real) */
-    int32_t reserved;     /* must be 0 */
+    int32_t hermitian;    /* 1: real fields, see below (implies real output) */
 } nufft2_opts;
 
 typedef struct {
@@ -83,6 +90,8 @@ typedef struct {
     uint64_t workspace_bytes;
     int32_t last_hip_error;  /* hipError_t of the last failure, 0 if none */
     int32_t device;
+    int32_t hermitian;       /* 1: real-field plan */
+    int32_t reserved;
 } nufft2_info;
 
 /*
@@ -95,6 +104,17 @@ typedef struct {
  *   The kernel width is w = ceil(log10(1/eps)) + 1 (13 at 1e-12, 7 at 1e-6)
  *   unless opts->w is set.  The fine grid is the smallest power of two
  *   >= max(2 * modes, 2 * w, 32) per dimension and must not exceed 4096.
+ *   Real fields (opts->hermitian = 1; both mode counts odd): the
+ *   coefficients of a real field satisfy c[-n][-m] = conj(c[n][m])
+ *   (section 5, eq. dfs_fourier_coeffs), so the upsampled grid is real and
+ *   only the m >= 0 half of the coefficients is needed.  Such a plan reads
+ *   coefficient columns K_phi/2 .. K_phi-1 only, transforms them to a real
+ *   fine grid (half the data of the complex path through every stage) and
+ *   writes real output: for any input it computes
+ *       out[F][j] = Re sum_n sum_{m >= 0} (m > 0 ? 2 : 1) c[F][n][m] e^{i (m phi_j + n theta_j)},
+ *   which for coefficients of a real field is the series itself.  The
+ *   coefficient layout is unchanged (full [K_theta][K_phi] arrays; the
+ *   m < 0 half is not read).
  *   opts may be NULL.  stream is a hipStream_t (NULL: the null stream).
  *   The plan owns every device workspace; it allocates on the current device.
  *   Errors: ERR_ARG, ERR_EPS_RANGE, ERR_ALLOC, ERR_HIP.  *out is set only on
@@ -123,7 +143,8 @@ nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const double *phi_de
  *   coeffs_dev  [n_fields][n_modes_theta][n_modes_phi] complex (re, im
  *               interleaved) in the plan's precision, row-major, centred.
  *   out_dev     [n_fields][n_pts] complex in the plan's precision, in the
- *               caller's point order; with real_output, [n_fields][n_pts] real.
+ *               caller's point order; with real_output or hermitian,
+ *               [n_fields][n_pts] real.
  * Both are device memory owned by the caller; they must not overlap.
  * Errors: ERR_ARG, ERR_NO_POINTS, ERR_HIP.
  */
@@ -475,8 +496,9 @@ nufft2_status nufft2_kernel_correction(int64_t K, int64_t nf, int32_t w, double 
 
 /*
  * Diagnostics for stage tests: a read-only view of a plan workspace.
- *   which 0: fine grid   [n_fields][nf_theta][nf_phi] complex (rows not
- *                        touched by the current points are stale)
+ *   which 0: fine grid   [n_fields][nf_theta][nf_phi] complex, real for
+ *                        real-field plans (rows not touched by the current
+ *                        points are stale)
  *         1: point records in bin order (struct {int32 i0_theta, i0_phi;
  *            real v_theta, v_phi}; real = plan precision)
  *         2: permutation, int32 [n_pts]: record r belongs to point perm[r]
@@ -484,6 +506,8 @@ nufft2_status nufft2_kernel_correction(int64_t K, int64_t nf, int32_t w, double 
  *            start[b] .. start[b+1]-1)
  *         4: theta rows reached by the current points' taps, uint8 [nf_theta]
  *         5: theta-pass output [n_fields][nf_theta][n_modes_phi] complex
+ *            (real-field plans: [n_fields][nf_theta][n_modes_phi/2 + 1],
+ *            modes m = 0 .. n_modes_phi/2)
  *         6: non-empty bins, int32 [n_bins + 1]: the first k entries are the
  *            bins holding at least one record in increasing order, entry
  *            n_bins is k

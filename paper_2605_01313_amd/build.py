@@ -13,8 +13,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnufft2.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["plan.hip", "group.hip", "autotune.hip", "server.hip", "pr.hip", "gl.hip", "setpts.hip", "fft.hip",
-           "gather.hip"]
+SOURCES = ["gather.hip", "gather_f64.hip", "fft.hip", "plan.hip", "group.hip", "autotune.hip", "server.hip",
+           "pr.hip", "gl.hip", "setpts.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -313,18 +313,20 @@ __device__ inline int mode_of(int i, int K, int L)
 // fac holds the two theta factor tables ([2][Kt] complex); cpm is corr_p of
 // the thread's column, which is the same for all its jobs (the block size is
 // a multiple of the column batch).
+// The transformed columns are col0 .. col0 + ncols - 1 of the coefficient
+// rows (all of them, or the m >= 0 half of a real field's); m counts from col0.
 template <typename T> struct ThetaLoad {
-    const cplx<T> *coef;  // this field
+    const cplx<T> *coef;  // this field, column col0 first
     const cplx<T> *fac;   // this parity's factors
     T cpm;
-    int Kt, Kp, L, m0;
+    int Kt, Kp, ncols, L, m0;
     // Loads are unconditional (clamped indices) so that the compiler issues
     // every element's loads before the first wait; padding slots select 0.
     __device__ cplx<T> operator()(int i, int b) const
     {
         const int m = m0 + b;
         const int a = mode_of(i, Kt, L);
-        const bool live = a >= 0 && m < Kp;
+        const bool live = a >= 0 && m < ncols;
         const int ac = live ? a : 0, mc = live ? m : 0;
         const cplx<T> f = fac[ac];
         const cplx<T> x = cmul(coef[(int64_t)ac * Kp + mc], cplx<T>{f.x * cpm, f.y * cpm});
@@ -333,14 +335,14 @@ template <typename T> struct ThetaLoad {
 };
 
 template <typename T> struct ThetaStore {
-    cplx<T> *S;              // this field, [nft][Kp]
+    cplx<T> *S;              // this field, [nft][ncols]
     const uint8_t *reached;  // LDS copy: reached[q] for output row 2q + parity
-    int Kp, m0, parity;
+    int ncols, m0, parity;
     __device__ void operator()(int q, int b, cplx<T> v) const
     {
         const int m = m0 + b;
         const int l = 2 * q + parity;
-        if (m < Kp && reached[q]) S[(int64_t)l * Kp + m] = v;
+        if (m < ncols && reached[q]) S[(int64_t)l * ncols + m] = v;
     }
 };
 
@@ -418,16 +420,16 @@ __device__ inline void theta_body(int item, const cplx<T> *__restrict__ coeffs, 
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
     uint8_t *flags = reinterpret_cast<uint8_t *>(tw + tw_lds_len(L));
     cplx<T> *s = reinterpret_cast<cplx<T> *>(flags + theta_flag_bytes(L));
-    const int ntiles = (fp.Kp + fp.theta_batch - 1) / fp.theta_batch;
+    const int ntiles = (fp.ncols + fp.theta_batch - 1) / fp.theta_batch;
     const int parity = item & 1;
     const int tile = item >> 1;
     const int f = tile / ntiles;
     const int m0 = (tile - f * ntiles) * fp.theta_batch;
     const int mt = m0 + ((int)threadIdx.x & (fp.theta_batch - 1));
-    const T cpm = corr_p[mt < fp.Kp ? mt : 0];
-    ThetaLoad<T> ld{coeffs + (int64_t)f * fp.Kt * fp.Kp, fac_t + parity * fp.Kt, cpm, fp.Kt, fp.Kp,
-                    L, m0};
-    ThetaStore<T> st{S + (int64_t)f * fp.nft * fp.Kp, flags, fp.Kp, m0, parity};
+    const T cpm = corr_p[fp.col0 + (mt < fp.ncols ? mt : 0)];
+    ThetaLoad<T> ld{coeffs + (int64_t)f * fp.Kt * fp.Kp + fp.col0, fac_t + parity * fp.Kt, cpm, fp.Kt, fp.Kp,
+                    fp.ncols, L, m0};
+    ThetaStore<T> st{S + (int64_t)f * fp.nft * fp.ncols, flags, fp.ncols, m0, parity};
     ThetaPro<cplx<T>, E> pro{tw, tws, tw_lds_len(L), flags, touched, L, parity};
     fft_stages<T, LOGL, 0, E, true>(s, fp.log_theta_batch, fp.theta_batch, 1, tw, ld, st, pro);
 }
@@ -456,13 +458,13 @@ __global__ __launch_bounds__(theta_max_threads<T>()) void k_theta_group(const Th
 }
 
 template <typename T> struct PhiStore {
-    cplx<T> *grid;  // this field, [nft][nfp]
+    cplx<T> *grid;  // this field, [nft][N] (N: the transform length)
     const uint8_t *touched;
-    int nfp, l0;
+    int N, l0;
     __device__ void operator()(int o, int b, cplx<T> v) const
     {
         const int l = l0 + b;
-        if (touched[l]) grid[(int64_t)l * nfp + o] = v;
+        if (touched[l]) grid[(int64_t)l * N + o] = v;
     }
 };
 
@@ -477,16 +479,49 @@ template <typename T> struct PhiLoad {
     }
 };
 
+// Complex-to-real phi transform of a real field's row.  The row's modes are
+// X[m], m = 0 .. M (M = ncols - 1 < nfp / 4), and X[-m] = conj X[m]; the
+// real row x[l] = sum_m X[m] e^{2 pi i m l / nfp} comes out of one complex
+// transform of length N2 = nfp / 2 as z[j] = x[2j] + i x[2j + 1], whose
+// input is Z[k] = (X[k] + X[k + N2]) + i (X[k] - X[k + N2]) e^{2 pi i k / nfp}
+// (even and odd samples, interleaved).  With the band limit only one of the
+// two terms is non-zero:
+//   Z[k]      = X[k] (1 + i e^{2 pi i k / nfp})              k <= M
+//   Z[N2 - k] = conj(X[k]) (1 + i e^{-2 pi i k / nfp})      1 <= k <= M
+// and zero between.  X[0] enters by its real part, so the row is the real
+// part of the series of the m >= 0 half with the m > 0 terms doubled (for a
+// real field: the series).  tab[k] = e^{2 pi i k / nfp}, k <= M.
+template <typename T> struct PhiLoadC2R {
+    const cplx<T> *S;    // this field, [nft][ncols]
+    const cplx<T> *tab;
+    int ncols, N2, l0;
+    __device__ cplx<T> operator()(int k, int b) const
+    {
+        const int M = ncols - 1;
+        const bool lo = k <= M, hi = k >= N2 - M && k > 0;
+        const int m = lo ? k : (hi ? N2 - k : 0);
+        const cplx<T> x = S[(int64_t)(l0 + b) * ncols + m];
+        const cplx<T> e = tab[m];
+        // lo: X (1 - s, c); hi: conj(X) (1 + s, c), with e = (c, s)
+        const cplx<T> xm = lo ? cplx<T>{x.x, k == 0 ? (T)0 : x.y} : cplx<T>{x.x, -x.y};
+        const cplx<T> f = lo ? cplx<T>{(T)1 - e.y, e.x} : cplx<T>{(T)1 + e.y, e.x};
+        const cplx<T> z = cmul(xm, f);
+        return (lo || hi) ? z : cplx<T>{(T)0, (T)0};
+    }
+};
+
 // One workgroup per (field, batch of B reached theta rows); blk is the
-// workgroup's index in the stage.
-template <typename T, int LOGN, int E>
+// workgroup's index in the stage.  LOGN: log2 of the transform length (nfp,
+// or nfp / 2 for the complex-to-real rows of real fields).
+template <typename T, int LOGN, int E, bool C2R>
 __device__ inline void phi_body(int blk, const cplx<T> *__restrict__ S, const cplx<T> *__restrict__ tws,
-                                const uint8_t *__restrict__ touched, cplx<T> *__restrict__ grid,
-                                const FFTParams &fp)
+                                const cplx<T> *__restrict__ c2r, const uint8_t *__restrict__ touched,
+                                cplx<T> *__restrict__ grid, const FFTParams &fp)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int N = 1 << LOGN;
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *s = tw + tw_lds_len(1 << LOGN);
+    cplx<T> *s = tw + tw_lds_len(N);
     const int nrb = fp.nft / fp.phi_batch;
     const int f = blk / nrb;
     const int l0 = (blk - f * nrb) * fp.phi_batch;
@@ -494,29 +529,35 @@ __device__ inline void phi_body(int blk, const cplx<T> *__restrict__ S, const cp
     int any = 0;
     for (int b = 0; b < fp.phi_batch; ++b) any |= touched[l0 + b];
     if (!any) return;
-    PhiLoad<T> ld{S + (int64_t)f * fp.nft * fp.Kp, fp.Kp, fp.nfp, l0};
-    PhiStore<T> st{grid + (int64_t)f * fp.nft * fp.nfp, touched, fp.nfp, l0};
-    TwiddleCopy<cplx<T>> pro{tw, tws, tw_lds_len(1 << LOGN)};
-    fft_stages<T, LOGN, 0, E, false>(s, fp.log_phi_batch, 1, lds_seq_len(1 << LOGN), tw, ld, st, pro);
+    PhiStore<T> st{grid + (int64_t)f * fp.nft * N, touched, N, l0};
+    TwiddleCopy<cplx<T>> pro{tw, tws, tw_lds_len(N)};
+    if constexpr (C2R) {
+        PhiLoadC2R<T> ld{S + (int64_t)f * fp.nft * fp.ncols, c2r, fp.ncols, N, l0};
+        fft_stages<T, LOGN, 0, E, false>(s, fp.log_phi_batch, 1, lds_seq_len(N), tw, ld, st, pro);
+    } else {
+        PhiLoad<T> ld{S + (int64_t)f * fp.nft * fp.ncols, fp.ncols, N, l0};
+        fft_stages<T, LOGN, 0, E, false>(s, fp.log_phi_batch, 1, lds_seq_len(N), tw, ld, st, pro);
+    }
 }
 
-template <typename T, int LOGN, int E>
+template <typename T, int LOGN, int E, bool C2R>
 __global__ __launch_bounds__(256) void k_phi_pass(const cplx<T> *__restrict__ S,
                                                   const cplx<T> *__restrict__ tws,
+                                                  const cplx<T> *__restrict__ c2r,
                                                   const uint8_t *__restrict__ touched,
                                                   cplx<T> *__restrict__ grid, FFTParams fp)
 {
-    phi_body<T, LOGN, E>((int)blockIdx.x, S, tws, touched, grid, fp);
+    phi_body<T, LOGN, E, C2R>((int)blockIdx.x, S, tws, c2r, touched, grid, fp);
 }
 
 // Member j of a group class owns workgroups [j * per, (j + 1) * per).
-template <typename T, int LOGN, int E>
+template <typename T, int LOGN, int E, bool C2R>
 __global__ __launch_bounds__(256) void k_phi_group(const PhiJob *__restrict__ jobs, int per)
 {
     const int j = (int)blockIdx.x / per;
     const PhiJob J = jobs[j];
-    phi_body<T, LOGN, E>((int)blockIdx.x - j * per, (const cplx<T> *)J.S, (const cplx<T> *)J.tws, J.touched,
-                         (cplx<T> *)J.grid, J.fp);
+    phi_body<T, LOGN, E, C2R>((int)blockIdx.x - j * per, (const cplx<T> *)J.S, (const cplx<T> *)J.tws,
+                              (const cplx<T> *)J.c2r, J.touched, (cplx<T> *)J.grid, J.fp);
 }
 
 constexpr int kElemsPerThread = 16;
@@ -535,7 +576,7 @@ static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const 
         return hipErrorInvalidConfiguration;
     const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(L) * fp.theta_batch + tw_lds_len(L)) +
                        theta_flag_bytes(L);
-    const int ntiles = (fp.Kp + fp.theta_batch - 1) / fp.theta_batch;
+    const int ntiles = (fp.ncols + fp.theta_batch - 1) / fp.theta_batch;
     const int per = 2 * ntiles * fp.n_fields;
     if (jobs) {
         auto kern = ept == 8 ? k_theta_group<T, LOGL, 8> : k_theta_group<T, LOGL, kElemsPerThread>;
@@ -553,8 +594,8 @@ static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const 
     return hipGetLastError();
 }
 
-template <typename T, int LOGN>
-static hipError_t launch_phi_t(const FFTParams &fp, const void *S, const void *tw_p,
+template <typename T, int LOGN, bool C2R>
+static hipError_t launch_phi_t(const FFTParams &fp, const void *S, const void *tw_p, const void *c2r,
                                const uint8_t *touched, void *grid, const PhiJob *jobs, int n_members,
                                hipStream_t s)
 {
@@ -565,16 +606,16 @@ static hipError_t launch_phi_t(const FFTParams &fp, const void *S, const void *t
     const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * fp.phi_batch + tw_lds_len(N));
     const int per = (fp.nft / fp.phi_batch) * fp.n_fields;
     if (jobs) {
-        auto kern = ept == 8 ? k_phi_group<T, LOGN, 8> : k_phi_group<T, LOGN, kElemsPerThread>;
+        auto kern = ept == 8 ? k_phi_group<T, LOGN, 8, C2R> : k_phi_group<T, LOGN, kElemsPerThread, C2R>;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, dim3(per * n_members), dim3(threads), lds, s, jobs, per);
     } else {
-        auto kern = ept == 8 ? k_phi_pass<T, LOGN, 8> : k_phi_pass<T, LOGN, kElemsPerThread>;
+        auto kern = ept == 8 ? k_phi_pass<T, LOGN, 8, C2R> : k_phi_pass<T, LOGN, kElemsPerThread, C2R>;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, dim3(per), dim3(threads), lds, s, (const cplx<T> *)S, (const cplx<T> *)tw_p,
-                           touched, (cplx<T> *)grid, fp);
+                           (const cplx<T> *)c2r, touched, (cplx<T> *)grid, fp);
     }
     return hipGetLastError();
 }
@@ -595,12 +636,21 @@ static hipError_t theta_dispatch(const FFTParams &fp, const void *coeffs, const 
 }
 
 template <typename T>
-static hipError_t phi_dispatch(const FFTParams &fp, const void *S, const void *tw_p,
+static hipError_t phi_dispatch(const FFTParams &fp, const void *S, const void *tw_p, const void *c2r,
                                const uint8_t *touched, void *grid, const PhiJob *jobs, int n_members,
                                hipStream_t s)
 {
-    switch (fp.log_nfp) {
-#define NUFFT2_N(X) case X: return launch_phi_t<T, X>(fp, S, tw_p, touched, grid, jobs, n_members, s);
+    if (fp.c2r) {
+        switch (fp.log_phi_len) {
+#define NUFFT2_N(X) case X: return launch_phi_t<T, X, true>(fp, S, tw_p, c2r, touched, grid, jobs, n_members, s);
+            NUFFT2_N(4) NUFFT2_N(5) NUFFT2_N(6) NUFFT2_N(7) NUFFT2_N(8) NUFFT2_N(9) NUFFT2_N(10)
+            NUFFT2_N(11)
+#undef NUFFT2_N
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (fp.log_phi_len) {
+#define NUFFT2_N(X) case X: return launch_phi_t<T, X, false>(fp, S, tw_p, c2r, touched, grid, jobs, n_members, s);
         NUFFT2_N(5) NUFFT2_N(6) NUFFT2_N(7) NUFFT2_N(8) NUFFT2_N(9) NUFFT2_N(10)
         NUFFT2_N(11) NUFFT2_N(12)
 #undef NUFFT2_N
@@ -616,11 +666,11 @@ hipError_t launch_theta_pass(int prec, const FFTParams &fp, const void *coeffs, 
     return theta_dispatch<double>(fp, coeffs, fac_t, corr_p, tws_t, rowtouched, S, nullptr, 0, s);
 }
 
-hipError_t launch_phi_pass(int prec, const FFTParams &fp, const void *S, const void *tw_p,
+hipError_t launch_phi_pass(int prec, const FFTParams &fp, const void *S, const void *tw_p, const void *c2r,
                            const uint8_t *rowtouched, void *grid, hipStream_t s)
 {
-    if (prec == 1) return phi_dispatch<float>(fp, S, tw_p, rowtouched, grid, nullptr, 0, s);
-    return phi_dispatch<double>(fp, S, tw_p, rowtouched, grid, nullptr, 0, s);
+    if (prec == 1) return phi_dispatch<float>(fp, S, tw_p, c2r, rowtouched, grid, nullptr, 0, s);
+    return phi_dispatch<double>(fp, S, tw_p, c2r, rowtouched, grid, nullptr, 0, s);
 }
 
 hipError_t launch_theta_group(int prec, const FFTParams &fp, const ThetaJob *jobs, int n_members, hipStream_t s)
@@ -633,8 +683,8 @@ hipError_t launch_theta_group(int prec, const FFTParams &fp, const ThetaJob *job
 hipError_t launch_phi_group(int prec, const FFTParams &fp, const PhiJob *jobs, int n_members, hipStream_t s)
 {
     if (n_members < 1 || !jobs) return hipErrorInvalidValue;
-    if (prec == 1) return phi_dispatch<float>(fp, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
-    return phi_dispatch<double>(fp, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
+    if (prec == 1) return phi_dispatch<float>(fp, nullptr, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
+    return phi_dispatch<double>(fp, nullptr, nullptr, nullptr, nullptr, nullptr, jobs, n_members, s);
 }
 
 // ---- DFS analysis: grid values on Grid [0] -> exp-form coefficients -------

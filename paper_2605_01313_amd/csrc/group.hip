@@ -53,7 +53,8 @@ bool same_class(const nufft2_plan_s *a, const nufft2_plan_s *b)
 {
     return a->prec == b->prec && a->Kt == b->Kt && a->Kp == b->Kp && a->F == b->F && a->w == b->w &&
            a->beta == b->beta && a->tile_t == b->tile_t && a->tile_p == b->tile_p &&
-           a->real_output == b->real_output && a->fields_per_pass == b->fields_per_pass &&
+           a->real_output == b->real_output && a->hermitian == b->hermitian &&
+           a->fields_per_pass == b->fields_per_pass &&
            a->tile_pitch == b->tile_pitch &&
            a->fp.theta_batch == b->fp.theta_batch && a->fp.phi_batch == b->fp.phi_batch &&
            a->fp.theta_ept == b->fp.theta_ept && a->fp.phi_ept == b->fp.phi_ept;
@@ -376,6 +377,7 @@ NUFFT2_API nufft2_status nufft2_group_exec(nufft2_group g, const void *const *co
             PhiJob pj{};
             pj.S = p->S;
             pj.tws = p->tw_p;
+            pj.c2r = p->c2r;
             pj.touched = p->rowtouched;
             pj.grid = p->grid;
             pj.fp = cfp;

@@ -96,6 +96,15 @@ struct FFTParams {
     int32_t theta_batch, log_theta_batch;   // columns per theta-pass workgroup
     int32_t phi_batch, log_phi_batch;       // rows per phi-pass workgroup
     int32_t theta_ept, phi_ept;             // elements per thread in each pass: 8 or 16
+    // Columns the theta pass transforms: coefficient columns col0 ..
+    // col0 + ncols - 1, written to S rows of ncols entries.  Complex plans:
+    // all Kp columns.  Real-field (Hermitian) plans: the m >= 0 half
+    // (col0 = Kp / 2, ncols = Kp / 2 + 1), and the phi pass is a
+    // complex-to-real transform of length nfp done as a complex transform of
+    // length nfp / 2 (c2r = 1), whose output is the real grid row.
+    int32_t col0, ncols;
+    int32_t c2r;
+    int32_t log_phi_len;                    // log2 of the phi-pass transform length
 };
 
 // fac_t: complex [2][Kt]: corr_t[a], then corr_t[a] e^{2 pi i n / nft}
@@ -104,7 +113,9 @@ struct FFTParams {
 hipError_t launch_theta_pass(int prec, const FFTParams &fp, const void *coeffs, const void *fac_t,
                              const void *corr_p, const void *tws_t, const uint8_t *rowtouched,
                              void *S, hipStream_t s);
-hipError_t launch_phi_pass(int prec, const FFTParams &fp, const void *S, const void *tws_p,
+// c2r: for fp.c2r, the table e^{2 pi i k / nfp}, k < fp.ncols (complex, plan
+// precision), else unused.
+hipError_t launch_phi_pass(int prec, const FFTParams &fp, const void *S, const void *tws_p, const void *c2r,
                            const uint8_t *rowtouched, void *grid, hipStream_t s);
 
 // One member of a group class for the theta / phi passes (device memory;
@@ -117,7 +128,7 @@ struct ThetaJob {
     FFTParams fp;
 };
 struct PhiJob {
-    const void *S, *tws;
+    const void *S, *tws, *c2r;
     const uint8_t *touched;
     void *grid;
     FFTParams fp;
@@ -137,7 +148,14 @@ struct GatherParams {
     int32_t tile_pitch;        // LDS row pitch of a staged patch, in elements (>= tile_p + w - 1)
     int64_t n_pts;
     int32_t real_output;
+    int32_t real_grid;         // 1: the fine grid is real (Hermitian plans); the output is real
+    // FP32 plans with w >= kPolyMinW: the tap weights as polynomials in the
+    // point's centred offset (device table [w][kPolyCoefs], lowest degree
+    // first); nullptr otherwise.
+    const float *wpoly;
 };
+constexpr int kPolyCoefs = 9;
+constexpr int kPolyMinW = 7;
 
 // binlist holds the non-empty bins in increasing order and their number in
 // entry nbins; after it (16-byte aligned, see bin_items) one int4 per

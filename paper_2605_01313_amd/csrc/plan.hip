@@ -148,13 +148,81 @@ template <typename T> void fill_twiddle_tables(std::vector<T> &buf, int N)
     }
 }
 
+// ES kernel exp(beta (sqrt(1 - z^2) - 1)) in long double, z^2 clamped to 1.
+long double es_kernel_ld(long double z, long double beta)
+{
+    long double z2 = z * z;
+    if (z2 > 1.0L) z2 = 1.0L;
+    return expl(-beta * z2 / (1.0L + sqrtl(1.0L - z2)));
+}
+
+// Tap weights of an FP32 plan as polynomials.  A point's offset v (first
+// tap i0 = ceil(t - w/2), v = t - i0 - floor(w/2)) lies in [vlo, vlo + 1],
+// vlo = w/2 - 1 - floor(w/2); tap b has weight phi((b - floor(w/2) - v) /
+// (w/2)), a smooth function of v except for the square-root edge of the
+// kernel at the end of the support.  Each tap's weight is interpolated in
+// long double by a polynomial of degree kPolyCoefs - 1 in u = v - (vlo +
+// 1/2) at the Chebyshev points of [-1/2, 1/2] (coefficients lowest degree
+// first, rounded to FP32).  Returns false, leaving the plan on the direct
+// evaluation, when the polynomials miss the kernel by more than 1e-7 on a
+// fine grid of u (w < 7 at beta = 2.30 w, where the edge taps' square-root
+// term is too large).
+bool weight_polynomials(int w, double beta, std::vector<float> &out)
+{
+    constexpr int D = kPolyCoefs;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const int H = w / 2;
+    const long double hw = (long double)w / 2.0L;
+    const long double c = ((long double)w / 2.0L - 1.0L - (long double)H) + 0.5L;
+    out.assign((size_t)w * D, 0.0f);
+    std::vector<long double> u(D);
+    for (int i = 0; i < D; ++i) u[i] = 0.5L * cosl(pi * (2.0L * i + 1.0L) / (2.0L * D));
+    for (int b = 0; b < w; ++b) {
+        // Vandermonde system at the nodes, Gaussian elimination with pivoting
+        long double A[D][D + 1];
+        for (int i = 0; i < D; ++i) {
+            long double pw = 1.0L;
+            for (int j = 0; j < D; ++j) {
+                A[i][j] = pw;
+                pw *= u[i];
+            }
+            A[i][D] = es_kernel_ld(((long double)(b - H) - (u[i] + c)) / hw, beta);
+        }
+        for (int col = 0; col < D; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < D; ++r)
+                if (fabsl(A[r][col]) > fabsl(A[piv][col])) piv = r;
+            for (int k = 0; k <= D; ++k) std::swap(A[col][k], A[piv][k]);
+            for (int r = 0; r < D; ++r) {
+                if (r == col) continue;
+                const long double f = A[r][col] / A[col][col];
+                for (int k = col; k <= D; ++k) A[r][k] -= f * A[col][k];
+            }
+        }
+        long double coef[D];
+        for (int j = 0; j < D; ++j) coef[j] = A[j][D] / A[j][j];
+        for (int j = 0; j < D; ++j) out[(size_t)b * D + j] = (float)coef[j];
+        // check the rounded polynomial against the kernel
+        for (int q = 0; q <= 256; ++q) {
+            const long double uu = -0.5L + (long double)q / 256.0L;
+            long double acc = 0.0L;
+            for (int j = D - 1; j >= 0; --j) acc = acc * uu + (long double)out[(size_t)b * D + j];
+            const long double ex = es_kernel_ld(((long double)(b - H) - (uu + c)) / hw, beta);
+            if (fabsl(acc - ex) > 1e-7L) return false;
+        }
+    }
+    return true;
+}
+
 void free_all(nufft2_plan_s *p)
 {
     void *ptrs[] = {p->corr_t, p->corr_p, p->tw_t,  p->tw_p,  p->twist_t,   p->S,     p->grid,
                     p->bincount, p->binstart, p->binlist, p->rowmark, p->rowtouched, p->flags, p->keyrank,
-                    p->rec,    p->perm,   p->stage, p->passtot, p->lstart};
+                    p->rec,    p->perm,   p->stage, p->passtot, p->lstart, p->c2r, p->wpoly};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    p->c2r = nullptr;
+    p->wpoly = nullptr;
     p->corr_t = p->corr_p = p->tw_t = p->tw_p = p->twist_t = p->S = p->grid = nullptr;
     p->bincount = p->binstart = p->binlist = p->flags = p->perm = nullptr;
     p->rowmark = p->rowtouched = nullptr;
@@ -221,7 +289,7 @@ template <typename T> nufft2_status upload_tables(nufft2_plan_s *p)
     std::vector<T> ctT(ct.begin(), ct.end()), cpT(cp.begin(), cp.end());
     std::vector<T> twt, twp, twist(4 * (size_t)p->Kt);
     fill_twiddle_tables<T>(twt, p->nft / 2);
-    fill_twiddle_tables<T>(twp, p->nfp);
+    fill_twiddle_tables<T>(twp, 1 << p->fp.log_phi_len);
     {
         const long double two_pi = 6.283185307179586476925286766559005768L;
         for (int64_t a = 0; a < p->Kt; ++a) {
@@ -239,6 +307,17 @@ template <typename T> nufft2_status upload_tables(nufft2_plan_s *p)
         (e = hipMemcpy(p->tw_p, twp.data(), sizeof(T) * twp.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->twist_t, twist.data(), sizeof(T) * twist.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return fail_hip(p, e);
+    if (p->c2r) {
+        std::vector<T> tab(2 * (size_t)p->ncols);
+        const long double two_pi = 6.283185307179586476925286766559005768L;
+        for (int64_t k = 0; k < p->ncols; ++k) {
+            const long double ang = two_pi * (long double)k / (long double)p->nfp;
+            tab[2 * k] = (T)cosl(ang);
+            tab[2 * k + 1] = (T)sinl(ang);
+        }
+        if ((e = hipMemcpy(p->c2r, tab.data(), sizeof(T) * tab.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return fail_hip(p, e);
+    }
     return NUFFT2_OK;
 }
 
@@ -315,11 +394,12 @@ void nufft2::fft_launch_shape(const nufft2_plan_s *p, int64_t members, FFTParams
     const int64_t L = p->nft / 2;
     const int64_t max_threads = p->prec == NUFFT2_FP32 ? 1024 : 512;
     const int64_t b = fp.theta_batch;
-    const int64_t theta_waves16 = members * 2 * ((p->Kp + b - 1) / b) * (int64_t)p->F * L * b / 16 / 64;
+    const int64_t theta_waves16 = members * 2 * ((p->ncols + b - 1) / b) * (int64_t)p->F * L * b / 16 / 64;
     fp.theta_ept = (theta_waves16 < kSmallLaunchWaves && L * b / 8 <= max_threads && L >= 64) ? 8 : 16;
-    const int64_t phi_waves16 = members * (int64_t)p->F * (p->nft / 2) * p->nfp / 16 / 64;
-    fp.phi_ept = (phi_waves16 < kSmallLaunchWaves && p->nfp >= 64) ? 8 : 16;
-    int64_t pb = (fp.phi_ept == 8 ? 2048 : 4096) / p->nfp;
+    const int64_t N = int64_t(1) << fp.log_phi_len;  // phi transform length
+    const int64_t phi_waves16 = members * (int64_t)p->F * (p->nft / 2) * N / 16 / 64;
+    fp.phi_ept = (phi_waves16 < kSmallLaunchWaves && N >= 64) ? 8 : 16;
+    int64_t pb = (fp.phi_ept == 8 ? 2048 : 4096) / N;
     if (pb < 1) pb = 1;
     if (pb > p->nft) pb = p->nft;
     fp.phi_batch = (int)pb;
@@ -362,9 +442,11 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     if (n_modes_theta > kMaxNf / 2 || n_modes_phi > kMaxNf / 2) return NUFFT2_ERR_ARG;
     nufft2_opts o{};
     if (opts) o = *opts;
-    if (o.reserved != 0 || o.w < 0 || o.w > kMaxW || o.w == 1 || o.beta_over_w < 0 ||
+    if ((o.hermitian != 0 && o.hermitian != 1) || o.w < 0 || o.w > kMaxW || o.w == 1 || o.beta_over_w < 0 ||
         !isfinite(o.beta_over_w) || (o.real_output != 0 && o.real_output != 1))
         return NUFFT2_ERR_ARG;
+    // a real field's modes are symmetric about zero: odd counts
+    if (o.hermitian && (n_modes_theta % 2 == 0 || n_modes_phi % 2 == 0)) return NUFFT2_ERR_ARG;
 
     int32_t w;
     double beta;
@@ -390,7 +472,9 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     {
         // the gather stages a (tile + w - 1)^2 patch of one field in LDS
         const size_t cs = prec == NUFFT2_FP32 ? sizeof(float2) : sizeof(double2);
-        if (cs * (size_t)(tt + w - 1) * (size_t)(tp + w - 1) > kGatherLdsLimit) return NUFFT2_ERR_ARG;
+        const size_t es = o.hermitian ? cs / 2 : cs;
+        const size_t v = 16 / es;  // elements per 16-byte staging chunk
+        if (es * (size_t)(tt + w - 1) * ((tp + w - 1 + v - 1) / v * v) > kGatherLdsLimit) return NUFFT2_ERR_ARG;
     }
 
     nufft2_plan_s *p = new (std::nothrow) nufft2_plan_s();
@@ -408,10 +492,13 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     p->nbins_t = (int)(nft / tt);
     p->nbins_p = (int)(nfp / tp);
     p->nbins = (int64_t)p->nbins_t * p->nbins_p;
-    p->real_output = o.real_output;
+    p->hermitian = o.hermitian;
+    p->real_output = o.real_output || o.hermitian;
+    p->ncols = o.hermitian ? n_modes_phi / 2 + 1 : n_modes_phi;
     p->stream = (hipStream_t)stream;
     p->csize = prec == NUFFT2_FP32 ? sizeof(float2) : sizeof(double2);
     p->rsize = prec == NUFFT2_FP32 ? sizeof(float) : sizeof(double);
+    p->gsize = o.hermitian ? p->rsize : p->csize;
     if (hipGetDevice(&p->device) != hipSuccess) {
         hipError_t e = hipGetLastError();
         (void)e;
@@ -427,6 +514,10 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     fp.log_nft = ilog2(p->nft);
     fp.log_nfp = ilog2(p->nfp);
     fp.n_fields = p->F;
+    fp.col0 = o.hermitian ? (int)(p->Kp / 2) : 0;
+    fp.ncols = (int)p->ncols;
+    fp.c2r = o.hermitian;
+    fp.log_phi_len = fp.log_nfp - (o.hermitian ? 1 : 0);
     {
         // theta pass: columns per workgroup so that a row segment is >= 64 bytes
         // where possible, at least 64 threads, at most 1024 (FP32) or 512 (FP64)
@@ -454,18 +545,21 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     }
     fft_launch_shape(p, 1, fp);
     {
-        // FP64 patch rows are padded to a multiple of 16 elements: the LDS
-        // serves 16-byte reads 16 lanes at a time over 64 banks, and with
-        // such a pitch the bank slot of a tap depends on its column only,
-        // which the gather's lane dealing keeps distinct (a CPU model of
-        // the 2048^2 wind workload that reproduces the measured FP64
-        // conflict rate, 0.79 per access, puts it at 0.25).  Only where
-        // the padded patch of one field stays within the LDS limit.
+        // Patch rows of 16-byte elements (complex FP64) are padded to a
+        // multiple of 16 elements: the LDS serves 16-byte reads 16 lanes at a
+        // time over 64 banks, and with such a pitch the bank slot of a tap
+        // depends on its column only, which the gather's lane dealing keeps
+        // distinct (a CPU model of the 2048^2 wind workload that reproduces
+        // the measured FP64 conflict rate, 0.79 per access, puts it at
+        // 0.25).  Only where the padded patch of one field stays within the
+        // LDS limit.
+        // Other rows hold whole 16-byte staging chunks.
         const int tc = tp + w - 1;
         const int padded = (tc + 15) & ~15;
-        p->tile_pitch =
-            prec == NUFFT2_FP64 && p->csize * (size_t)(tt + w - 1) * (size_t)padded <= kGatherLdsLimit ? padded : tc;
-        const size_t tile = p->csize * (size_t)(tt + w - 1) * (size_t)p->tile_pitch;
+        const int v = (int)(16 / p->gsize);
+        p->tile_pitch = p->gsize == 16 ? (p->gsize * (size_t)(tt + w - 1) * (size_t)padded <= kGatherLdsLimit ? padded : tc)
+                                       : (tc + v - 1) / v * v;
+        const size_t tile = p->gsize * (size_t)(tt + w - 1) * (size_t)p->tile_pitch;
         int g = (int)(kGatherLdsLimit / tile);
         if (g > kGatherMaxFieldsPerPass) g = kGatherMaxFieldsPerPass;
         if (g > p->F) g = p->F;
@@ -473,12 +567,16 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
         p->fields_per_pass = g;
     }
 
-    const size_t rs = p->rsize, cs = p->csize;
+    std::vector<float> wpoly;
+    const bool use_poly = prec == NUFFT2_FP32 && w >= kPolyMinW && weight_polynomials(w, beta, wpoly);
+    const size_t rs = p->rsize, cs = p->csize, gs = p->gsize;
     bool ok = dev_alloc(p, &p->corr_t, rs * p->Kt) && dev_alloc(p, &p->corr_p, rs * p->Kp) &&
               dev_alloc(p, &p->tw_t, cs * (64 + p->nft)) && dev_alloc(p, &p->tw_p, cs * (64 + p->nfp)) &&
               dev_alloc(p, &p->twist_t, 2 * cs * p->Kt) &&
-              dev_alloc(p, &p->S, cs * (size_t)p->F * p->nft * p->Kp) &&
-              dev_alloc(p, &p->grid, cs * (size_t)p->F * p->nft * p->nfp) &&
+              dev_alloc(p, &p->S, cs * (size_t)p->F * p->nft * p->ncols) &&
+              dev_alloc(p, &p->grid, gs * (size_t)p->F * p->nft * p->nfp) &&
+              (!p->hermitian || dev_alloc(p, &p->c2r, cs * (size_t)p->ncols)) &&
+              (!use_poly || dev_alloc(p, (void **)&p->wpoly, sizeof(float) * wpoly.size())) &&
               dev_alloc(p, (void **)&p->bincount, sizeof(int32_t) * (size_t)p->nbins) &&
               dev_alloc(p, (void **)&p->binstart, sizeof(int32_t) * (size_t)(p->nbins + 1)) &&
               dev_alloc(p, (void **)&p->binlist, binlist_bytes(p->nbins)) &&
@@ -495,13 +593,17 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
         return NUFFT2_ERR_ALLOC;
     }
     st = prec == NUFFT2_FP32 ? upload_tables<float>(p) : upload_tables<double>(p);
+    if (st == NUFFT2_OK && p->wpoly) {
+        const hipError_t e = hipMemcpy(p->wpoly, wpoly.data(), sizeof(float) * wpoly.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) st = fail_hip(p, e);
+    }
     if (st == NUFFT2_OK) {
         // cleared on the plan's stream, which is then synchronised: work on
         // other streams (other plans) keeps running meanwhile
         hipError_t e;
         hipStream_t ps = p->stream;
-        if ((e = hipMemsetAsync(p->S, 0, cs * (size_t)p->F * p->nft * p->Kp, ps)) != hipSuccess ||
-            (e = hipMemsetAsync(p->grid, 0, cs * (size_t)p->F * p->nft * p->nfp, ps)) != hipSuccess ||
+        if ((e = hipMemsetAsync(p->S, 0, cs * (size_t)p->F * p->nft * p->ncols, ps)) != hipSuccess ||
+            (e = hipMemsetAsync(p->grid, 0, gs * (size_t)p->F * p->nft * p->nfp, ps)) != hipSuccess ||
             (e = hipMemsetAsync(p->rowtouched, 0, (size_t)p->nft, ps)) != hipSuccess ||
             (e = hipMemsetAsync(p->rowmark, 0, (size_t)p->nft, ps)) != hipSuccess ||
             (e = hipMemsetAsync(p->bincount, 0, sizeof(int32_t) * (size_t)p->nbins, ps)) != hipSuccess ||
@@ -586,6 +688,8 @@ GatherParams nufft2::plan_gather_params(const nufft2_plan_s *p)
     gp.tile_pitch = p->tile_pitch;
     gp.n_pts = p->n_pts;
     gp.real_output = p->real_output;
+    gp.real_grid = p->hermitian;
+    gp.wpoly = p->wpoly;
     return gp;
 }
 
@@ -619,7 +723,7 @@ NUFFT2_API nufft2_status nufft2_exec(nufft2_handle p, const void *coeffs_dev, vo
     prof_end(p, slot);
     if (e != hipSuccess) return fail_hip(p, e);
     slot = prof_begin(p, 2);
-    e = launch_phi_pass(p->prec, p->fp, p->S, p->tw_p, p->rowtouched, p->grid, p->stream);
+    e = launch_phi_pass(p->prec, p->fp, p->S, p->tw_p, p->c2r, p->rowtouched, p->grid, p->stream);
     prof_end(p, slot);
     if (e != hipSuccess) return fail_hip(p, e);
     const GatherParams gp = plan_gather_params(p);
@@ -733,6 +837,7 @@ NUFFT2_API nufft2_status nufft2_get_info(nufft2_handle p, nufft2_info *info)
     info->workspace_bytes = p->ws_bytes;
     info->last_hip_error = (int32_t)p->last_err;
     info->device = p->device;
+    info->hermitian = p->hermitian;
     return NUFFT2_OK;
 }
 
@@ -744,12 +849,12 @@ NUFFT2_API nufft2_status nufft2_debug_buffer(nufft2_handle p, int32_t which, voi
     if (needs_pts && p->n_pts < 0) return NUFFT2_ERR_NO_POINTS;
     const size_t recsz = p->prec == NUFFT2_FP32 ? sizeof(PointRec<float>) : sizeof(PointRec<double>);
     switch (which) {
-    case 0: *dev_ptr = p->grid; *bytes = p->csize * (size_t)p->F * p->nft * p->nfp; break;
+    case 0: *dev_ptr = p->grid; *bytes = p->gsize * (size_t)p->F * p->nft * p->nfp; break;
     case 1: *dev_ptr = p->rec; *bytes = recsz * (size_t)p->n_pts; break;
     case 2: *dev_ptr = p->perm; *bytes = sizeof(int32_t) * (size_t)p->n_pts; break;
     case 3: *dev_ptr = p->binstart; *bytes = sizeof(int32_t) * (size_t)(p->nbins + 1); break;
     case 4: *dev_ptr = p->rowtouched; *bytes = (size_t)p->nft; break;
-    case 5: *dev_ptr = p->S; *bytes = p->csize * (size_t)p->F * p->nft * p->Kp; break;
+    case 5: *dev_ptr = p->S; *bytes = p->csize * (size_t)p->F * p->nft * p->ncols; break;
     case 6: *dev_ptr = p->binlist; *bytes = sizeof(int32_t) * (size_t)(p->nbins + 1); break;
     default: return NUFFT2_ERR_ARG;
     }

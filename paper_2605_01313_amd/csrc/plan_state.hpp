@@ -20,12 +20,15 @@ struct nufft2_plan_s {
     int nbins_t = 0, nbins_p = 0;
     int64_t nbins = 0;
     int real_output = 0;
+    int hermitian = 0;      // real-field plan: m >= 0 half, real fine grid
+    int64_t ncols = 0;      // columns through the theta pass (Kp, or Kp / 2 + 1)
     int fields_per_pass = 1;
     int tile_pitch = 0;  // gather patch row pitch in LDS (elements)
     hipStream_t stream = nullptr;
     int device = 0;
     size_t csize = 0;  // bytes per complex
     size_t rsize = 0;  // bytes per real
+    size_t gsize = 0;  // bytes per fine-grid element (complex, or real for real-field plans)
     nufft2::FFTParams fp{};
 
     // device workspaces
@@ -33,6 +36,8 @@ struct nufft2_plan_s {
     void *tw_t = nullptr, *tw_p = nullptr;  // two-level twiddle tables
     void *twist_t = nullptr;                // [2][Kt]: corr_t[a], corr_t[a] e^{2 pi i n / nft}
     void *S = nullptr, *grid = nullptr;
+    void *c2r = nullptr;    // real-field plans: e^{2 pi i k / nfp}, k < ncols
+    float *wpoly = nullptr; // FP32 plans with w >= kPolyMinW: tap-weight polynomials
     int32_t *bincount = nullptr, *binstart = nullptr;
     int32_t *binlist = nullptr;  // non-empty bins in order, their number last
     uint8_t *rowmark = nullptr, *rowtouched = nullptr;

@@ -46,7 +46,7 @@ STAGE_NAMES = ("setpts", "theta_pass", "phi_pass", "gather")
 class nufft2_opts(ctypes.Structure):
     _fields_ = [("w", ctypes.c_int32), ("beta_over_w", ctypes.c_double),
                 ("tile_theta", ctypes.c_int32), ("tile_phi", ctypes.c_int32),
-                ("real_output", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("real_output", ctypes.c_int32), ("hermitian", ctypes.c_int32)]
 
 
 class nufft2_info(ctypes.Structure):
@@ -57,10 +57,10 @@ class nufft2_info(ctypes.Structure):
                 ("tile_theta", ctypes.c_int32), ("tile_phi", ctypes.c_int32),
                 ("n_bins", ctypes.c_int64), ("n_pts", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_uint64), ("last_hip_error", ctypes.c_int32),
-                ("device", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("hermitian", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class nufft2_group_info(ctypes.Structure):
@@ -420,10 +420,14 @@ class Plan:
     >>> p = Plan("fp32", K, K, n_fields=3, eps=1e-6)
     >>> p.setpts(phi, theta)            # float64 device tensors
     >>> out = p.exec(coeffs)            # complex64 device tensor (F, K, K)
+
+    hermitian=True: coefficients of real fields (c[-n][-m] = conj c[n][m]);
+    the plan reads the m >= 0 half, works on a real fine grid and returns
+    real values (float32 / float64).
     """
 
     def __init__(self, prec, n_modes_theta, n_modes_phi, n_fields=1, eps=1e-6, *, w=0,
-                 beta_over_w=0.0, tile_theta=0, tile_phi=0, real_output=False, stream=None):
+                 beta_over_w=0.0, tile_theta=0, tile_phi=0, real_output=False, hermitian=False, stream=None):
         import torch
         self._torch = torch
         self.prec = {"fp32": NUFFT2_FP32, "fp64": NUFFT2_FP64,
@@ -431,10 +435,11 @@ class Plan:
         self.cdtype = torch.complex64 if self.prec == NUFFT2_FP32 else torch.complex128
         self.rdtype = torch.float32 if self.prec == NUFFT2_FP32 else torch.float64
         self.shape = (int(n_fields), int(n_modes_theta), int(n_modes_phi))
-        self.real_output = bool(real_output)
+        self.hermitian = bool(hermitian)
+        self.real_output = bool(real_output) or self.hermitian
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opts = nufft2_opts(int(w), float(beta_over_w), int(tile_theta), int(tile_phi),
-                           int(bool(real_output)), 0)
+                           int(bool(real_output)), int(self.hermitian))
         st, h = nufft2_plan(self.prec, n_modes_theta, n_modes_phi, n_fields, eps, opts,
                             self.stream.cuda_stream)
         _check(st, "nufft2_plan")
@@ -456,19 +461,28 @@ class Plan:
             raise ValueError("phi and theta differ in length")
         return phi.numel()
 
-    def _check_io(self, coeffs, out, n_pts):
-        t = self._torch
+    def _check_coeffs(self, coeffs):
         if coeffs.dtype != self.cdtype or not coeffs.is_cuda or not coeffs.is_contiguous():
             raise TypeError(f"coeffs must be a contiguous {self.cdtype} device tensor")
         if tuple(coeffs.shape) != self.shape and tuple(coeffs.shape) != self.shape[1:]:
             raise ValueError(f"coeffs shape {tuple(coeffs.shape)} != {self.shape}")
+
+    def _check_out(self, out, n_pts):
+        """The output tensor the kernels write: dtype, device, contiguity and
+        size are checked before any launch (a wrong one would be written out
+        of bounds)."""
         F = self.shape[0]
         dt = self.rdtype if self.real_output else self.cdtype
-        if out is None:
-            return t.empty((F, max(n_pts, 0)), dtype=dt, device=coeffs.device)
         if out.dtype != dt or not out.is_cuda or not out.is_contiguous() or out.numel() != F * max(n_pts, 0):
             raise ValueError(f"out must be a contiguous {dt} device tensor of {F} x {max(n_pts, 0)} values")
         return out
+
+    def _check_io(self, coeffs, out, n_pts):
+        self._check_coeffs(coeffs)
+        if out is None:
+            dt = self.rdtype if self.real_output else self.cdtype
+            return self._torch.empty((self.shape[0], max(n_pts, 0)), dtype=dt, device=coeffs.device)
+        return self._check_out(out, n_pts)
 
     def setpts(self, phi, theta):
         n = self._check_points(phi, theta)
@@ -493,6 +507,7 @@ class Plan:
         if self._pts is None:
             raise RuntimeError("rotate_uv before setpts")
         phi_d, theta_d = self._pts
+        self._check_out(out, self.n_pts)
         for x in (phi_a, theta_a):
             if x.dtype != self._torch.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != self.n_pts:
                 raise TypeError("arrival points must be contiguous float64 device tensors of n_pts entries")
@@ -583,16 +598,23 @@ class Group:
         t = self._torch
         if len(coeffs) != len(self.plans):
             raise ValueError("one coefficient tensor per member")
+        for p, c in zip(self.plans, coeffs):
+            p._check_coeffs(c)
         if outs is None:
+            # one element at least per field, so that every member has a
+            # device pointer (the C call takes none null)
             outs = []
             for p, c in zip(self.plans, coeffs):
                 dt = p.rdtype if p.real_output else p.cdtype
                 outs.append(t.empty((p.shape[0], max(p.n_pts, 1)), dtype=dt, device=c.device))
-        for p, c in zip(self.plans, coeffs):
-            if c.dtype != p.cdtype or not c.is_cuda or not c.is_contiguous():
-                raise TypeError(f"coeffs must be contiguous {p.cdtype} device tensors")
-            if tuple(c.shape) != p.shape and tuple(c.shape) != p.shape[1:]:
-                raise ValueError(f"coeffs shape {tuple(c.shape)} != {p.shape}")
+        else:
+            if len(outs) != len(self.plans):
+                raise ValueError("one output tensor per member")
+            for p, o in zip(self.plans, outs):
+                if p.n_pts > 0:
+                    p._check_out(o, p.n_pts)
+                elif not o.is_cuda:
+                    raise ValueError("outputs must be device tensors")
         _check(nufft2_group_exec(self.handle, [c.data_ptr() for c in coeffs],
                                  [o.data_ptr() for o in outs]), "nufft2_group_exec")
         self._keep = (coeffs, outs)

@@ -19,3 +19,15 @@ def oracle_mod():
     if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def wind_large_ref(oracle_mod):
+    """The 1024 x 2048 wind workload (3 fields, 2,097,152 points) with the
+    oracle on its 10^4 sampled points (default_rng(15), without
+    replacement): (workload, sample indices, oracle values [3][10^4])."""
+    import synth
+    wl = synth.workload_large()
+    idx = synth.sample_indices(wl.n_pts, 10000, seed=15)
+    ref = oracle_mod.dfs_eval(wl.coeffs, wl.phi[idx], wl.theta[idx])
+    return wl, idx, ref

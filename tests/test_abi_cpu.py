@@ -121,8 +121,12 @@ def test_plan_argument_errors_before_device_work(nf):
     assert P(nf.NUFFT2_FP64, 63, 63, 1, 1e-12, bad_tile)[0] == nf.NUFFT2_ERR_ARG
     big_tile = nf.nufft2_opts(16, 0.0, 128, 128, 0, 0)              # LDS patch too large
     assert P(nf.NUFFT2_FP64, 511, 511, 1, 1e-12, big_tile)[0] == nf.NUFFT2_ERR_ARG
-    reserved = nf.nufft2_opts(0, 0.0, 0, 0, 0, 1)
-    assert P(nf.NUFFT2_FP64, 63, 63, 1, 1e-12, reserved)[0] == nf.NUFFT2_ERR_ARG
+    bad_flag = nf.nufft2_opts(0, 0.0, 0, 0, 0, 2)
+    assert P(nf.NUFFT2_FP64, 63, 63, 1, 1e-12, bad_flag)[0] == nf.NUFFT2_ERR_ARG
+    # real-field plans need mode ranges symmetric about zero (odd counts)
+    herm = nf.nufft2_opts(0, 0.0, 0, 0, 0, 1)
+    assert P(nf.NUFFT2_FP64, 64, 63, 1, 1e-12, herm)[0] == nf.NUFFT2_ERR_ARG
+    assert P(nf.NUFFT2_FP32, 63, 62, 1, 1e-6, herm)[0] == nf.NUFFT2_ERR_ARG
     null = ctypes.c_void_p()
     assert nf.nufft2_setpts(null, 10, 0, 0) == nf.NUFFT2_ERR_ARG
     assert nf.nufft2_exec(null, 0, 0) == nf.NUFFT2_ERR_ARG

@@ -241,25 +241,19 @@ def test_largest_grid(torch_dev, oracle_mod, prec, eps, tol):
     assert max(errs) <= tol
 
 
-@pytest.fixture(scope="module")
-def wind_large():
-    return synth.workload_large()
-
-
 @pytest.mark.parametrize("prec,eps,tol", [("fp32", 1e-6, 1e-6), ("fp64", 1e-12, 1e-12)])
-def test_wind_1024x2048_full_size_sampled(torch_dev, oracle_mod, wind_large, prec, eps, tol):
+def test_wind_1024x2048_full_size_sampled(torch_dev, wind_large_ref, prec, eps, tol):
     """The 1024 x 2048 workload at full size (2,097,152 wind departure points,
     K = 2047, 3 fields, algebraically decaying spectra) in the default plan
     configuration the bench times (side-by-side scan passes, 2048 x 2048
-    theta/phi transforms, 16 x 32 gather tiles): 512 sampled outputs per
-    field against the oracle."""
-    wl = wind_large
+    theta/phi transforms, 16 x 32 gather tiles): the 10^4 outputs per field
+    that default_rng(15) samples, against the oracle."""
+    wl, sel, ref = wind_large_ref
     say(f"case wind1024 full size prec={prec}")
     plan, got = run_plan(torch_dev, prec, wl.coeffs, wl.phi, wl.theta, eps)
     info = plan.info()
     assert plan.check() == 0 and info["n_pts"] == wl.n_pts and info["n_bins"] > 8192
-    sel = synth.sample_indices(wl.n_pts, 512)
-    errs = field_errors(got[:, sel], oracle_mod.dfs_eval(wl.coeffs, wl.phi[sel], wl.theta[sel]))
+    errs = field_errors(got[:, sel], ref)
     say(f"  rel l2 {errs}")
     assert max(errs) <= tol
     plan.destroy()
@@ -390,7 +384,46 @@ def test_binding_rejects_a_wrong_output_tensor(torch_dev):
         with pytest.raises(ValueError):
             plan.exec(c, bad)
     assert plan.exec(c, torch.empty((2, 100), dtype=torch.complex64, device=dev)).shape == (2, 100)
+    # rotate_uv rewrites two fields of the caller's output in place
+    for bad in (torch.empty((2, 99), dtype=torch.complex64, device=dev),
+                torch.empty((2, 100), dtype=torch.float32, device=dev)):
+        with pytest.raises(ValueError):
+            plan.rotate_uv(bad, 0, 1, pts, pts)
     plan.destroy()
+
+
+def test_group_binding_rejects_a_wrong_output_tensor(torch_dev):
+    """Group.exec checks every member's output tensor (dtype, device,
+    contiguity, size, real or complex) before the group launch writes it."""
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Group, Plan
+    say("case group_wrong_out")
+    plans = [Plan("fp32", 31, 31, n_fields=2, eps=1e-6),
+             Plan("fp32", 15, 15, n_fields=1, eps=1e-6, real_output=True)]
+    g = Group(plans)
+    pts = [torch.linspace(0.1, 3.0, n, dtype=torch.float64, device=dev) for n in (100, 50)]
+    g.setpts(pts, pts)
+    cs = [torch.zeros((2, 31, 31), dtype=torch.complex64, device=dev),
+          torch.zeros((1, 15, 15), dtype=torch.complex64, device=dev)]
+    good = [torch.empty((2, 100), dtype=torch.complex64, device=dev),
+            torch.empty((1, 50), dtype=torch.float32, device=dev)]
+    bads = [[torch.empty((2, 99), dtype=torch.complex64, device=dev), good[1]],
+            [good[0], torch.empty((1, 50), dtype=torch.complex64, device=dev)],
+            [good[0], torch.empty((1, 49), dtype=torch.float32, device=dev)],
+            [torch.empty((100, 2), dtype=torch.complex64, device=dev).t(), good[1]],
+            [good[0], torch.empty((1, 50), dtype=torch.float32)],
+            [good[0]]]
+    for bad in bads:
+        with pytest.raises(ValueError):
+            g.exec(cs, bad)
+    with pytest.raises(TypeError):
+        g.exec([cs[0], cs[1].to(torch.complex128)], good)
+    outs = g.exec(cs, good)
+    torch.cuda.synchronize()
+    assert outs[0].shape == (2, 100) and outs[1].shape == (1, 50)
+    g.destroy()
+    for p in plans:
+        p.destroy()
 
 
 def test_nonfinite_points_give_nan_and_flag(torch_dev):
