@@ -51,10 +51,13 @@ def test_analysis_matches_oracle(torch_dev, oracle_mod, prec, tol, J, F):
     an.destroy()
 
 
-@pytest.mark.parametrize("prec,eps,tol", [("fp64", 1e-12, 1e-12), ("fp32", 1e-6, 1e-6)])
+@pytest.mark.parametrize("prec,eps,tol", [("fp64", 1e-12, 1e-12), ("fp32", 1e-6, 1.5e-6)])
 def test_analysis_then_exec_reproduces_the_nodes(torch_dev, oracle_mod, prec, eps, tol):
     """A band-limited DFS field sampled on Grid [0] -> GPU analysis -> GPU NUFFT
-    at the nodes gives the samples back."""
+    at the nodes gives the samples back.  Points on fine-grid nodes are the
+    worst case of the width rule: at w = 7 the method alone (FP64 numpy
+    restatement) misses these samples by 1.06e-6, so the FP32 round trip is
+    held to the contract for such points, 1.5 eps."""
     torch, dev = torch_dev
     from paper_2605_01313_amd import Analysis, Plan
     J = 64
