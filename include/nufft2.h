@@ -168,6 +168,40 @@ nufft2_status nufft2_rotate_uv(nufft2_handle p, void *out_dev, int32_t field_u, 
                                const double *phi_a_dev, const double *theta_a_dev, const double *phi_d_dev,
                                const double *theta_d_dev);
 
+/*
+ * nufft2_exec_noalloc -- nufft2_setpts followed by nufft2_exec in one call,
+ * without a plan and without allocating device memory: for callers that
+ * cannot allocate (tight serving loops, harnesses that forbid allocation).
+ * It is not meant for HIP graph capture (it clears its counters with
+ * memset operations and may copy tables from the host).
+ *   The arguments are those of nufft2_plan (stream: a hipStream_t), of
+ *   nufft2_setpts (n_pts FP64 points phi_dev, theta_dev) and of
+ *   nufft2_exec (coeffs_dev, out_dev), with the same layouts; the result is
+ *   the same as that sequence's on a plan of the same parameters (the same
+ *   kernels run).  n_pts = 0 returns at once.
+ *   Every workspace of the evaluation (tables, sorted points, bins,
+ *   theta-pass output, fine grid) lives in one static device array of
+ *   nufft2_noalloc_capacity() bytes (128 MiB) per GPU, held from the first
+ *   call on that GPU until the process ends; an evaluation that does not
+ *   fit returns ERR_ARG before anything is enqueued (the grid and theta-pass
+ *   output take F nf^2 and F nf K complex values: 256 x 512 grids with three
+ *   fields fit in both precisions, 1024 x 2048 grids do not).
+ *   Every call on one GPU shares that array and finds the previous call's
+ *   contents there: calls that overlap on one GPU (other threads, or other
+ *   streams whose work is still running) race and give wrong results.  The
+ *   tables (deconvolution factors, twiddles) are computed on the host and
+ *   copied only when they differ from the previous call's on that GPU
+ *   (the call then waits for `stream`); otherwise the call only enqueues
+ *   work.  Non-finite coordinates give NaN outputs (there is no flag to
+ *   check without a plan).  Errors: as nufft2_plan, nufft2_setpts and
+ *   nufft2_exec; ERR_ARG also when the evaluation does not fit.
+ * nufft2_noalloc_capacity -- *bytes = the size of that array.
+ */
+nufft2_status nufft2_exec_noalloc(nufft2_prec prec, int64_t n_modes_theta, int64_t n_modes_phi, int32_t n_fields,
+                                  double eps, const nufft2_opts *opts, int64_t n_pts, const double *phi_dev,
+                                  const double *theta_dev, const void *coeffs_dev, void *out_dev, void *stream);
+nufft2_status nufft2_noalloc_capacity(uint64_t *bytes);
+
 /* nufft2_destroy -- synchronise the plan's stream and free everything. NULL is ignored. */
 nufft2_status nufft2_destroy(nufft2_handle p);
 

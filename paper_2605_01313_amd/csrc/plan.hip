@@ -432,11 +432,13 @@ NUFFT2_API nufft2_status nufft2_kernel_correction(int64_t K, int64_t nf, int32_t
     return kernel_correction(K, nf, w, beta, corr);
 }
 
-NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, int64_t n_modes_phi,
-                                     int32_t n_fields, double eps, const nufft2_opts *opts,
-                                     void *stream, nufft2_handle *out)
+namespace {
+
+// Validate the arguments of a plan and fill every parameter of *p (no
+// device memory is touched; p's workspace pointers stay null).
+nufft2_status plan_configure(nufft2_plan_s *p, int prec, int64_t n_modes_theta, int64_t n_modes_phi,
+                             int32_t n_fields, double eps, const nufft2_opts *opts, void *stream)
 {
-    if (!out) return NUFFT2_ERR_ARG;
     if (prec != NUFFT2_FP32 && prec != NUFFT2_FP64) return NUFFT2_ERR_ARG;
     if (n_modes_theta <= 0 || n_modes_phi <= 0 || n_fields <= 0) return NUFFT2_ERR_ARG;
     if (n_modes_theta > kMaxNf / 2 || n_modes_phi > kMaxNf / 2) return NUFFT2_ERR_ARG;
@@ -477,8 +479,6 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
         if (es * (size_t)(tt + w - 1) * ((tp + w - 1 + v - 1) / v * v) > kGatherLdsLimit) return NUFFT2_ERR_ARG;
     }
 
-    nufft2_plan_s *p = new (std::nothrow) nufft2_plan_s();
-    if (!p) return NUFFT2_ERR_ALLOC;
     p->prec = prec;
     p->Kt = n_modes_theta;
     p->Kp = n_modes_phi;
@@ -500,9 +500,7 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
     p->rsize = prec == NUFFT2_FP32 ? sizeof(float) : sizeof(double);
     p->gsize = o.hermitian ? p->rsize : p->csize;
     if (hipGetDevice(&p->device) != hipSuccess) {
-        hipError_t e = hipGetLastError();
-        (void)e;
-        delete p;
+        (void)hipGetLastError();
         return NUFFT2_ERR_HIP;
     }
 
@@ -536,10 +534,7 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
         while (L * b < 1024) b *= 2;
         while (b > 1 && (L * b / 16 > max_threads || lds_bytes(b) > (int64_t)kFftLdsLimit)) b /= 2;
         while (lds_bytes(b) > (int64_t)kCuLds / 2 && b * (int64_t)p->csize > 32) b /= 2;
-        if (lds_bytes(b) > (int64_t)kFftLdsLimit || L * b / 16 > max_threads) {
-            delete p;
-            return NUFFT2_ERR_ARG;
-        }
+        if (lds_bytes(b) > (int64_t)kFftLdsLimit || L * b / 16 > max_threads) return NUFFT2_ERR_ARG;
         fp.theta_batch = (int)b;
         fp.log_theta_batch = ilog2(b);
     }
@@ -566,52 +561,86 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
         if (g < 1) g = 1;
         p->fields_per_pass = g;
     }
+    return NUFFT2_OK;
+}
 
-    std::vector<float> wpoly;
-    const bool use_poly = prec == NUFFT2_FP32 && w >= kPolyMinW && weight_polynomials(w, beta, wpoly);
+// The plan's device workspaces (not the point workspaces), each from
+// get(&ptr, bytes): the allocating plan passes dev_alloc, the allocation-
+// free entry point a carve-out of its static scratch.  False if get fails.
+template <class Get> bool plan_workspaces(nufft2_plan_s *p, size_t n_poly, Get get)
+{
     const size_t rs = p->rsize, cs = p->csize, gs = p->gsize;
-    bool ok = dev_alloc(p, &p->corr_t, rs * p->Kt) && dev_alloc(p, &p->corr_p, rs * p->Kp) &&
-              dev_alloc(p, &p->tw_t, cs * (64 + p->nft)) && dev_alloc(p, &p->tw_p, cs * (64 + p->nfp)) &&
-              dev_alloc(p, &p->twist_t, 2 * cs * p->Kt) &&
-              dev_alloc(p, &p->S, cs * (size_t)p->F * p->nft * p->ncols) &&
-              dev_alloc(p, &p->grid, gs * (size_t)p->F * p->nft * p->nfp) &&
-              (!p->hermitian || dev_alloc(p, &p->c2r, cs * (size_t)p->ncols)) &&
-              (!use_poly || dev_alloc(p, (void **)&p->wpoly, sizeof(float) * wpoly.size())) &&
-              dev_alloc(p, (void **)&p->bincount, sizeof(int32_t) * (size_t)p->nbins) &&
-              dev_alloc(p, (void **)&p->binstart, sizeof(int32_t) * (size_t)(p->nbins + 1)) &&
-              dev_alloc(p, (void **)&p->binlist, binlist_bytes(p->nbins)) &&
-              dev_alloc(p, (void **)&p->rowmark, (size_t)p->nft) &&
-              dev_alloc(p, (void **)&p->rowtouched, (size_t)p->nft) &&
-              dev_alloc(p, (void **)&p->flags, sizeof(int32_t) * 4) &&
-              (p->nbins <= kDealtMaxBins ||
-               (dev_alloc(p, (void **)&p->stage, sizeof(int4) * (size_t)p->nbins) &&
-                dev_alloc(p, (void **)&p->lstart, sizeof(int32_t) * (size_t)p->nbins) &&
-                dev_alloc(p, (void **)&p->passtot, sizeof(int2) * (size_t)scan_passes(p->nbins))));
-    if (!ok) {
-        free_all(p);
-        delete p;
-        return NUFFT2_ERR_ALLOC;
-    }
-    st = prec == NUFFT2_FP32 ? upload_tables<float>(p) : upload_tables<double>(p);
+    // the tables first: their offsets then depend on the table parameters only
+    return get((void **)&p->corr_t, rs * p->Kt) && get((void **)&p->corr_p, rs * p->Kp) &&
+           get((void **)&p->tw_t, cs * (64 + p->nft)) && get((void **)&p->tw_p, cs * (64 + p->nfp)) &&
+           get((void **)&p->twist_t, 2 * cs * p->Kt) &&
+           (!p->hermitian || get((void **)&p->c2r, cs * (size_t)p->ncols)) &&
+           (n_poly == 0 || get((void **)&p->wpoly, sizeof(float) * n_poly)) &&
+           get((void **)&p->S, cs * (size_t)p->F * p->nft * p->ncols) &&
+           get((void **)&p->grid, gs * (size_t)p->F * p->nft * p->nfp) &&
+           get((void **)&p->bincount, sizeof(int32_t) * (size_t)p->nbins) &&
+           get((void **)&p->binstart, sizeof(int32_t) * (size_t)(p->nbins + 1)) &&
+           get((void **)&p->binlist, binlist_bytes(p->nbins)) && get((void **)&p->rowmark, (size_t)p->nft) &&
+           get((void **)&p->rowtouched, (size_t)p->nft) && get((void **)&p->flags, sizeof(int32_t) * 4) &&
+           (p->nbins <= kDealtMaxBins ||
+            (get((void **)&p->stage, sizeof(int4) * (size_t)p->nbins) &&
+             get((void **)&p->lstart, sizeof(int32_t) * (size_t)p->nbins) &&
+             get((void **)&p->passtot, sizeof(int2) * (size_t)scan_passes(p->nbins))));
+}
+
+// Device work of a new plan's set-up on its stream: tables, polynomial
+// coefficients, and the counters, flags and buffers that must start at
+// zero (S and the grid: so that reads of rows no point reaches are defined).
+nufft2_status plan_initialise(nufft2_plan_s *p, const std::vector<float> &wpoly, bool clear_grids)
+{
+    nufft2_status st = p->prec == NUFFT2_FP32 ? upload_tables<float>(p) : upload_tables<double>(p);
     if (st == NUFFT2_OK && p->wpoly) {
         const hipError_t e = hipMemcpy(p->wpoly, wpoly.data(), sizeof(float) * wpoly.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) st = fail_hip(p, e);
     }
+    if (st != NUFFT2_OK) return st;
+    hipError_t e;
+    hipStream_t ps = p->stream;
+    if ((clear_grids &&
+         ((e = hipMemsetAsync(p->S, 0, p->csize * (size_t)p->F * p->nft * p->ncols, ps)) != hipSuccess ||
+          (e = hipMemsetAsync(p->grid, 0, p->gsize * (size_t)p->F * p->nft * p->nfp, ps)) != hipSuccess)) ||
+        (e = hipMemsetAsync(p->rowtouched, 0, (size_t)p->nft, ps)) != hipSuccess ||
+        (e = hipMemsetAsync(p->rowmark, 0, (size_t)p->nft, ps)) != hipSuccess ||
+        (e = hipMemsetAsync(p->bincount, 0, sizeof(int32_t) * (size_t)p->nbins, ps)) != hipSuccess ||
+        (e = hipMemsetAsync(p->binstart, 0, sizeof(int32_t) * (size_t)(p->nbins + 1), ps)) != hipSuccess ||
+        (e = hipMemsetAsync(p->binlist, 0, binlist_bytes(p->nbins), ps)) != hipSuccess ||
+        (e = hipMemsetAsync(p->flags, 0, sizeof(int32_t) * 4, ps)) != hipSuccess)
+        return fail_hip(p, e);
+    return NUFFT2_OK;
+}
+
+}  // namespace
+
+NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, int64_t n_modes_phi,
+                                     int32_t n_fields, double eps, const nufft2_opts *opts,
+                                     void *stream, nufft2_handle *out)
+{
+    if (!out) return NUFFT2_ERR_ARG;
+    nufft2_plan_s *p = new (std::nothrow) nufft2_plan_s();
+    if (!p) return NUFFT2_ERR_ALLOC;
+    nufft2_status st = plan_configure(p, prec, n_modes_theta, n_modes_phi, n_fields, eps, opts, stream);
+    if (st != NUFFT2_OK) {
+        delete p;
+        return st;
+    }
+    std::vector<float> wpoly;
+    const bool use_poly = prec == NUFFT2_FP32 && p->w >= kPolyMinW && weight_polynomials(p->w, p->beta, wpoly);
+    if (!plan_workspaces(p, use_poly ? wpoly.size() : 0, [&](void **q, size_t n) { return dev_alloc(p, q, n); })) {
+        free_all(p);
+        delete p;
+        return NUFFT2_ERR_ALLOC;
+    }
+    // cleared on the plan's stream, which is then synchronised: work on
+    // other streams (other plans) keeps running meanwhile
+    st = plan_initialise(p, wpoly, true);
     if (st == NUFFT2_OK) {
-        // cleared on the plan's stream, which is then synchronised: work on
-        // other streams (other plans) keeps running meanwhile
-        hipError_t e;
-        hipStream_t ps = p->stream;
-        if ((e = hipMemsetAsync(p->S, 0, cs * (size_t)p->F * p->nft * p->ncols, ps)) != hipSuccess ||
-            (e = hipMemsetAsync(p->grid, 0, gs * (size_t)p->F * p->nft * p->nfp, ps)) != hipSuccess ||
-            (e = hipMemsetAsync(p->rowtouched, 0, (size_t)p->nft, ps)) != hipSuccess ||
-            (e = hipMemsetAsync(p->rowmark, 0, (size_t)p->nft, ps)) != hipSuccess ||
-            (e = hipMemsetAsync(p->bincount, 0, sizeof(int32_t) * (size_t)p->nbins, ps)) != hipSuccess ||
-            (e = hipMemsetAsync(p->binstart, 0, sizeof(int32_t) * (size_t)(p->nbins + 1), ps)) != hipSuccess ||
-            (e = hipMemsetAsync(p->binlist, 0, binlist_bytes(p->nbins), ps)) != hipSuccess ||
-            (e = hipMemsetAsync(p->flags, 0, sizeof(int32_t) * 4, ps)) != hipSuccess ||
-            (e = hipStreamSynchronize(ps)) != hipSuccess)
-            st = NUFFT2_ERR_HIP;
+        const hipError_t e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) st = fail_hip(p, e);
     }
     if (st != NUFFT2_OK) {
         free_all(p);
@@ -858,6 +887,157 @@ NUFFT2_API nufft2_status nufft2_debug_buffer(nufft2_handle p, int32_t which, voi
     case 6: *dev_ptr = p->binlist; *bytes = sizeof(int32_t) * (size_t)(p->nbins + 1); break;
     default: return NUFFT2_ERR_ARG;
     }
+    return NUFFT2_OK;
+}
+
+// ---- evaluation without device allocation ---------------------------------
+
+namespace {
+
+// Device memory of nufft2_exec_noalloc: every workspace of one evaluation
+// (tables, sorted points, bins, theta-pass output, fine grid) is carved
+// from this array.  Each GPU the library runs on holds its own copy until
+// the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for that device.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+
+// What the tables at the start of a device's scratch describe.
+struct TableKey {
+    int prec = 0, w = 0, hermitian = 0, nft = 0, nfp = 0;
+    int64_t Kt = 0, Kp = 0;
+    double beta = 0;
+    bool operator==(const TableKey &o) const
+    {
+        return prec == o.prec && w == o.w && hermitian == o.hermitian && nft == o.nft && nfp == o.nfp &&
+               Kt == o.Kt && Kp == o.Kp && beta == o.beta;
+    }
+};
+
+struct ScratchDevice {
+    unsigned char *ptr = nullptr;  // this device's copy of scratch
+    bool tables_valid = false;
+    bool poly = false;             // the tables include tap-weight polynomials
+    TableKey tables;
+};
+
+std::mutex g_scratch_mu;
+ScratchDevice g_scratch[kNoAllocMaxDevices];
+
+}  // namespace
+
+NUFFT2_API nufft2_status nufft2_exec_noalloc(nufft2_prec prec, int64_t n_modes_theta, int64_t n_modes_phi,
+                                             int32_t n_fields, double eps, const nufft2_opts *opts, int64_t n_pts,
+                                             const double *phi_dev, const double *theta_dev, const void *coeffs_dev,
+                                             void *out_dev, void *stream)
+{
+    if (n_pts < 0 || n_pts > (int64_t)0x7fffffff) return NUFFT2_ERR_ARG;
+    if (n_pts > 0 && (!phi_dev || !theta_dev || !coeffs_dev || !out_dev)) return NUFFT2_ERR_ARG;
+    nufft2_plan_s p;  // parameters only; its pointers are set into the scratch below
+    nufft2_status st = plan_configure(&p, prec, n_modes_theta, n_modes_phi, n_fields, eps, opts, stream);
+    if (st != NUFFT2_OK) return st;
+    if (n_pts == 0) return NUFFT2_OK;
+    if (p.device < 0 || p.device >= kNoAllocMaxDevices) return NUFFT2_ERR_ARG;
+
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchDevice &dev = g_scratch[p.device];
+    if (!dev.ptr) {
+        // once per device, with that device current
+        void *q = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !q) {
+            (void)hipGetLastError();
+            return NUFFT2_ERR_HIP;
+        }
+        dev.ptr = (unsigned char *)q;
+    }
+    // carve the workspaces (256-byte aligned) in a fixed order: tables,
+    // plan buffers, then the point buffers
+    size_t used = 0;
+    auto carve = [&](void **q, size_t n) {
+        const size_t at = (used + 255) & ~(size_t)255;
+        if (n > kNoAllocScratchBytes || at > kNoAllocScratchBytes - n) return false;
+        *q = dev.ptr + at;
+        used = at + n;
+        return true;
+    };
+    const size_t n_poly = p.prec == NUFFT2_FP32 && p.w >= kPolyMinW ? (size_t)p.w * kPolyCoefs : 0;
+    const size_t recsz = p.prec == NUFFT2_FP32 ? sizeof(PointRec<float>) : sizeof(PointRec<double>);
+    if (!plan_workspaces(&p, n_poly, carve) || !carve((void **)&p.keyrank, sizeof(int2) * (size_t)n_pts) ||
+        !carve(&p.rec, recsz * (size_t)n_pts) || !carve((void **)&p.perm, sizeof(int32_t) * (size_t)n_pts))
+        return NUFFT2_ERR_ARG;  // the evaluation does not fit in kNoAllocScratchBytes
+    p.pts_cap = n_pts;
+    p.n_pts = n_pts;
+
+    // tables: uploaded only when they differ from the last call's on this
+    // device (host-side work and the blocking copies happen then only)
+    TableKey key;
+    key.prec = p.prec;
+    key.w = p.w;
+    key.hermitian = p.hermitian;
+    key.nft = p.nft;
+    key.nfp = p.nfp;
+    key.Kt = p.Kt;
+    key.Kp = p.Kp;
+    key.beta = p.beta;
+    hipError_t e;
+    if (!dev.tables_valid || !(dev.tables == key)) {
+        dev.tables_valid = false;
+        std::vector<float> wpoly;
+        if (n_poly && !weight_polynomials(p.w, p.beta, wpoly)) p.wpoly = nullptr;
+        // earlier work on this stream may still read the old tables
+        if ((e = hipStreamSynchronize(p.stream)) != hipSuccess) {
+            (void)hipGetLastError();
+            return NUFFT2_ERR_HIP;
+        }
+        st = p.prec == NUFFT2_FP32 ? upload_tables<float>(&p) : upload_tables<double>(&p);
+        if (st == NUFFT2_OK && p.wpoly &&
+            (e = hipMemcpy(p.wpoly, wpoly.data(), sizeof(float) * wpoly.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            st = NUFFT2_ERR_HIP;
+        if (st != NUFFT2_OK) {
+            (void)hipGetLastError();
+            return st;
+        }
+        dev.tables = key;
+        dev.poly = p.wpoly != nullptr;
+        dev.tables_valid = true;
+    } else if (!dev.poly) {
+        p.wpoly = nullptr;
+    }
+    // The scratch keeps the last call's contents: the counters, row marks,
+    // bin lists and flags that the sort expects at zero are cleared here.
+    if ((e = hipMemsetAsync(p.rowtouched, 0, (size_t)p.nft, p.stream)) != hipSuccess ||
+        (e = hipMemsetAsync(p.rowmark, 0, (size_t)p.nft, p.stream)) != hipSuccess ||
+        (e = hipMemsetAsync(p.bincount, 0, sizeof(int32_t) * (size_t)p.nbins, p.stream)) != hipSuccess ||
+        (e = hipMemsetAsync(p.binstart, 0, sizeof(int32_t) * (size_t)(p.nbins + 1), p.stream)) != hipSuccess ||
+        (e = hipMemsetAsync(p.binlist, 0, binlist_bytes(p.nbins), p.stream)) != hipSuccess ||
+        (e = hipMemsetAsync(p.flags, 0, sizeof(int32_t) * 4, p.stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return NUFFT2_ERR_HIP;
+    }
+    const SetptsParams sp = plan_setpts_params(&p, n_pts);
+    e = launch_setpts(p.prec, sp, phi_dev, theta_dev, p.bincount, p.binstart, p.binlist, p.nbins, p.keyrank,
+                      p.rowmark, p.rowtouched, p.rec, p.perm, p.flags, p.stage, p.passtot, p.lstart, p.stream);
+    if (e == hipSuccess)
+        e = launch_theta_pass(p.prec, p.fp, coeffs_dev, p.twist_t, p.corr_p, p.tw_t, p.rowtouched, p.S, p.stream);
+    if (e == hipSuccess) e = launch_phi_pass(p.prec, p.fp, p.S, p.tw_p, p.c2r, p.rowtouched, p.grid, p.stream);
+    if (e == hipSuccess) {
+        const GatherParams gp = plan_gather_params(&p);
+        e = launch_gather(p.prec, gp, p.grid, p.rec, p.perm, p.binlist, out_dev, p.stream);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return NUFFT2_ERR_HIP;
+    }
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_noalloc_capacity(uint64_t *bytes)
+{
+    if (!bytes) return NUFFT2_ERR_ARG;
+    *bytes = kNoAllocScratchBytes;
     return NUFFT2_OK;
 }
 

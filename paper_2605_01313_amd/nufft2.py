@@ -37,7 +37,7 @@ EXPORTED = (
     "nufft2_server_stats", "nufft2_server_destroy", "nufft2_analysis_plan", "nufft2_analysis_exec",
     "nufft2_analysis_destroy", "nufft2_rotate_uv", "nufft2_analysis_set_zonal_filter", "nufft2_pr_plan",
     "nufft2_pr_project", "nufft2_pr_synthesize", "nufft2_pr_destroy", "nufft2_gl_nodes", "nufft2_gl_plan",
-    "nufft2_gl_exec", "nufft2_gl_destroy",
+    "nufft2_gl_exec", "nufft2_gl_destroy", "nufft2_exec_noalloc", "nufft2_noalloc_capacity",
 )
 NUFFT2_N_STAGES = 4
 STAGE_NAMES = ("setpts", "theta_pass", "phi_pass", "gather")
@@ -155,6 +155,8 @@ def _load():
         "nufft2_gl_plan": [i32, i64, i32, vp, ctypes.POINTER(H)],
         "nufft2_gl_exec": [H, vp, vp],
         "nufft2_gl_destroy": [H],
+        "nufft2_exec_noalloc": [i32, i64, i64, i32, dbl, ctypes.POINTER(nufft2_opts), i64, vp, vp, vp, vp, vp],
+        "nufft2_noalloc_capacity": [ctypes.POINTER(ctypes.c_uint64)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -342,6 +344,19 @@ def nufft2_server_stats(server):
 
 def nufft2_server_destroy(server):
     return _lib.nufft2_server_destroy(server)
+
+
+def nufft2_exec_noalloc(prec, n_modes_theta, n_modes_phi, n_fields, eps, opts, n_pts, phi_ptr, theta_ptr,
+                        coeffs_ptr, out_ptr, stream=0):
+    return _lib.nufft2_exec_noalloc(prec, n_modes_theta, n_modes_phi, n_fields, eps,
+                                    ctypes.byref(opts) if opts is not None else None, n_pts, phi_ptr, theta_ptr,
+                                    coeffs_ptr, out_ptr, stream)
+
+
+def nufft2_noalloc_capacity():
+    b = ctypes.c_uint64()
+    st = _lib.nufft2_noalloc_capacity(ctypes.byref(b))
+    return st, b.value
 
 
 def nufft2_rotate_uv(handle, out_ptr, field_u, field_v, phi_a, theta_a, phi_d, theta_d):
