@@ -3,19 +3,23 @@
 // by gather tile ("bin").
 //
 // Pipeline (all on the plan's stream):
-//   k_setpts_bin       per point: wrap/split, bin id, rank within the bin
-//                      (one atomic per bin and wave), mark the first-tap
-//                      theta row
+//   k_setpts_bin       per point: wrap/split, bin id, count the point in
+//                      its bin (one atomic per bin and wave), mark the
+//                      first-tap theta row
 //   k_bin_scan         one workgroup: exclusive scan of the bin counts, the
 //                      list of non-empty bins, the set of theta rows any
-//                      point's taps reach; clears the counters and marks for
-//                      the next call
-//   k_setpts_scatter   per point: recompute the split, write the packed
-//                      record at binstart[bin] + rank, and the permutation
+//                      point's taps reach; clears the marks for the next call
+//   k_setpts_scatter   per point: recompute the split and the bin, take a
+//                      rank in the bin by decrementing its count (one atomic
+//                      per bin and wave), write the packed record at
+//                      binstart[bin] + rank and the permutation; the
+//                      decrements leave every count at zero for the next call
 // For small plans (bins in one scan pass, points in one wave of 1024-thread
 // workgroups) k_setpts_scatter_scan replaces the last two: each workgroup
-// scans the counts itself (see there).  Plans of several scan passes run the
-// passes side by side (k_bin_scan_passes, k_setpts_scatter_passes).
+// scans the counts itself (see there), so its points' ranks come from the
+// bin kernel instead (written per point, and cleared counts by a ticket).
+// Plans of several scan passes run the passes side by side
+// (k_bin_scan_passes, k_setpts_scatter_passes).
 //
 // The order of points inside a bin depends on atomic arbitration; the output
 // of an exec does not, because each point's sum is computed by one thread in a
@@ -72,8 +76,52 @@ __device__ inline int32_t wave_aggregated_rank(int32_t *__restrict__ bincount, i
     return __shfl(base, leader_of_mine, 64) + offset;
 }
 
-// Point j (a thread of a 256-thread block; j >= n: inactive).
+// The same grouping, taking ranks from the top: every group leader
+// subtracts its group's size from the bin's count; the ranks of the group
+// are the old count minus the size, plus the lane's place in the group.
+// Once every point of a bin has taken its rank the count is zero again.
+__device__ inline int32_t wave_aggregated_rank_down(int32_t *__restrict__ bincount, int32_t bin)
+{
+    const int lane = (int)__lane_id();
+    uint64_t pending = __ballot(1);
+    int leader_of_mine = lane;
+    int32_t offset = 0, count = 0;
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int32_t lbin = __shfl(bin, leader, 64);
+        const uint64_t grp = pending & __ballot(bin == lbin);
+        if ((grp >> lane) & 1ull) {
+            leader_of_mine = leader;
+            offset = (int32_t)__popcll(grp & ((1ull << lane) - 1ull));
+        }
+        if (lane == leader) count = (int32_t)__popcll(grp);
+        pending &= ~grp;
+    }
+    int32_t base = 0;
+    if (count > 0) base = atomicSub(&bincount[bin], count) - count;
+    return __shfl(base, leader_of_mine, 64) + offset;
+}
+
+// Wrap/split of one point and its bin (non-finite coordinates: bin 0 and a
+// NaN record).
 template <typename T>
+__device__ inline int32_t split_point(double ph, double th, const SetptsParams &sp, PointRec<T> &r)
+{
+    if (!isfinite(ph) || !isfinite(th)) {
+        r.it = 0;
+        r.ip = 0;
+        r.vt = (T)NAN;
+        r.vp = (T)NAN;
+        return 0;
+    }
+    split_axis<T>(th, sp.th, sp.w, r.it, r.vt);
+    split_axis<T>(ph, sp.ph, sp.w, r.ip, r.vp);
+    return (r.it / sp.th.tile) * sp.nbins_phi + r.ip / sp.ph.tile;
+}
+
+// Point j (a thread of a 256-thread block; j >= n: inactive).  KR: also
+// write the point's (bin, rank) for the fused scan + scatter.
+template <typename T, bool KR>
 __device__ inline void setpts_bin_point(int64_t j, const double *__restrict__ phi, const double *__restrict__ theta,
                                         const SetptsParams &sp, int32_t *__restrict__ bincount,
                                         int2 *__restrict__ keyrank, uint8_t *__restrict__ rowmark,
@@ -94,10 +142,10 @@ __device__ inline void setpts_bin_point(int64_t j, const double *__restrict__ ph
         rowmark[it] = 1;
     }
     const int32_t rank = wave_aggregated_rank(bincount, bin);
-    keyrank[j] = make_int2(bin, rank);
+    if (KR) keyrank[j] = make_int2(bin, rank);
 }
 
-template <typename T>
+template <typename T, bool KR>
 __global__ __launch_bounds__(256) void k_setpts_bin(const double *__restrict__ phi,
                                                     const double *__restrict__ theta, SetptsParams sp,
                                                     int32_t *__restrict__ bincount,
@@ -105,8 +153,8 @@ __global__ __launch_bounds__(256) void k_setpts_bin(const double *__restrict__ p
                                                     uint8_t *__restrict__ rowmark,
                                                     int32_t *__restrict__ flags)
 {
-    setpts_bin_point<T>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, phi, theta, sp, bincount, keyrank,
-                        rowmark, flags);
+    setpts_bin_point<T, KR>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, phi, theta, sp, bincount, keyrank,
+                            rowmark, flags);
 }
 
 // Group launches: job_of_block[b] is the member that owns point block b;
@@ -116,8 +164,8 @@ __global__ __launch_bounds__(256) void k_setpts_bin_group(const SetptsJob *__res
                                                           const int32_t *__restrict__ job_of_block)
 {
     const SetptsJob J = jobs[job_of_block[blockIdx.x]];
-    setpts_bin_point<T>((int64_t)((int)blockIdx.x - J.block_begin) * blockDim.x + threadIdx.x, J.phi, J.theta,
-                        J.sp, J.bincount, J.keyrank, J.rowmark, J.flags);
+    setpts_bin_point<T, false>((int64_t)((int)blockIdx.x - J.block_begin) * blockDim.x + threadIdx.x, J.phi,
+                               J.theta, J.sp, J.bincount, J.keyrank, J.rowmark, J.flags);
 }
 
 // Block-wide exclusive scans of two ints per thread at once (one set of
@@ -334,13 +382,6 @@ __device__ __attribute__((always_inline)) inline void bin_scan_body(int32_t *__r
                 h[p][k] = e < nbins ? bincount[e] : 0;
             }
 #pragma unroll
-        for (int p = 0; p < kScanHoist; ++p)
-#pragma unroll
-            for (int k = 0; k < kScanChunk; ++k) {
-                const int64_t e = (int64_t)p * PASS + k * kScanThreads + t;
-                if (e < nbins) bincount[e] = 0;
-            }
-#pragma unroll
         for (int p = 0; p < kScanHoist; ++p) {
             const int64_t base = (int64_t)p * PASS;
             if (base < nbins)
@@ -354,7 +395,6 @@ __device__ __attribute__((always_inline)) inline void bin_scan_body(int32_t *__r
             for (int k = 0; k < kScanChunk; ++k) {
                 const int64_t e = base + k * kScanThreads + t;
                 h[k] = e < nbins ? bincount[e] : 0;
-                if (e < nbins) bincount[e] = 0;
             }
             scan_pass(h, base, (int)((nbins - base) < PASS ? (nbins - base) : PASS), stage, cmp, lds, carry,
                       carry_ne, binstart, binlist, items);
@@ -391,23 +431,13 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_scan_group(const SetptsJob
 template <typename T>
 __device__ inline void setpts_scatter_point(int64_t j, const double *__restrict__ phi,
                                             const double *__restrict__ theta, const SetptsParams &sp,
-                                            const int2 *__restrict__ keyrank, const int32_t *__restrict__ binstart,
+                                            int32_t *__restrict__ bincount, const int32_t *__restrict__ binstart,
                                             PointRec<T> *__restrict__ rec, int32_t *__restrict__ perm)
 {
     if (j < sp.n) {
-        const double ph = phi[j], th = theta[j];
         PointRec<T> r;
-        if (!isfinite(ph) || !isfinite(th)) {
-            r.it = 0;
-            r.ip = 0;
-            r.vt = (T)NAN;
-            r.vp = (T)NAN;
-        } else {
-            split_axis<T>(th, sp.th, sp.w, r.it, r.vt);
-            split_axis<T>(ph, sp.ph, sp.w, r.ip, r.vp);
-        }
-        const int2 kr = keyrank[j];
-        const int32_t pos = binstart[kr.x] + kr.y;
+        const int32_t bin = split_point<T>(phi[j], theta[j], sp, r);
+        const int32_t pos = binstart[bin] + wave_aggregated_rank_down(bincount, bin);
         rec[pos] = r;
         perm[pos] = (int32_t)j;
     }
@@ -435,14 +465,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_setpts_scatter(const double *__restrict__ phi,
                                                         const double *__restrict__ theta,
                                                         SetptsParams sp,
-                                                        const int2 *__restrict__ keyrank,
+                                                        int32_t *__restrict__ bincount,
                                                         const int32_t *__restrict__ binstart,
                                                         PointRec<T> *__restrict__ rec,
                                                         int32_t *__restrict__ perm,
                                                         int32_t *__restrict__ binlist, int64_t nbins)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    setpts_scatter_point<T>(i, phi, theta, sp, keyrank, binstart, rec, perm);
+    setpts_scatter_point<T>(i, phi, theta, sp, bincount, binstart, rec, perm);
     scatter_dealt(i, (int64_t)gridDim.x * blockDim.x, binlist, nbins);
 }
 
@@ -452,7 +482,7 @@ __global__ __launch_bounds__(256) void k_setpts_scatter_group(const SetptsJob *_
 {
     const SetptsJob J = jobs[job_of_block[blockIdx.x]];
     const int64_t i = (int64_t)((int)blockIdx.x - J.block_begin) * blockDim.x + threadIdx.x;
-    setpts_scatter_point<T>(i, J.phi, J.theta, J.sp, J.keyrank, J.binstart, (PointRec<T> *)J.rec, J.perm);
+    setpts_scatter_point<T>(i, J.phi, J.theta, J.sp, J.bincount, J.binstart, (PointRec<T> *)J.rec, J.perm);
     const int64_t member_threads = (J.sp.n + blockDim.x - 1) / blockDim.x * blockDim.x;
     scatter_dealt(i, member_threads, J.binlist, J.nbins);
 }
@@ -552,7 +582,7 @@ __global__ __launch_bounds__(kScanThreads) void k_setpts_scatter_scan(
 // Plans with more bins than one scan pass: the passes run side by side, one
 // workgroup each (k_bin_scan_passes), instead of one after another in one
 // workgroup.  Pass workgroup b scans its bins into pass-local starts
-// (lstart; it clears its own counters once read), writes its non-empty
+// (lstart; the counts stay for the scatter's ranks), writes its non-empty
 // entries with pass-local first records to stage[b * PASS + i], and its
 // totals {points, non-empty bins} to passtot[b]; workgroup 0 also derives
 // the reached rows and publishes the non-finite flag.  The scatter
@@ -590,11 +620,6 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_scan_passes(int32_t *__res
         mk[i] = rows_wg && l < nft ? rowmark[l] : (uint8_t)0;
     }
     const int flag0 = rows_wg && t == 0 ? flags[0] : 0;
-#pragma unroll
-    for (int k = 0; k < kScanChunk; ++k) {
-        const int e = k * kScanThreads + t;
-        if (e < n) bincount[base + e] = 0;
-    }
     int carry = 0, carry_ne = 0;
     // pass-local starts; entries to this pass's stage region
     scan_pass(h, base, n, stg, cmp, lds, carry, carry_ne, lstart, nullptr, stage + base);
@@ -605,7 +630,7 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_scan_passes(int32_t *__res
 template <typename T>
 __global__ __launch_bounds__(256) void k_setpts_scatter_passes(
     const double *__restrict__ phi, const double *__restrict__ theta, SetptsParams sp,
-    const int2 *__restrict__ keyrank, const int32_t *__restrict__ lstart, const int4 *__restrict__ stage,
+    int32_t *__restrict__ bincount, const int32_t *__restrict__ lstart, const int4 *__restrict__ stage,
     const int2 *__restrict__ passtot, int npass, int32_t *__restrict__ binstart, int32_t *__restrict__ binlist,
     int64_t nbins, PointRec<T> *__restrict__ rec, int32_t *__restrict__ perm)
 {
@@ -614,12 +639,10 @@ __global__ __launch_bounds__(256) void k_setpts_scatter_passes(
     const int t = (int)threadIdx.x;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + t;
     double ph = 0.0, th = 0.0;
-    int2 kr = make_int2(0, 0);
     int2 inc = t < npass ? passtot[t] : make_int2(0, 0);
     if (j < sp.n) {
         ph = phi[j];
         th = theta[j];
-        kr = keyrank[j];
     }
     // pass b's totals on thread b: inclusive scan in each of the first two
     // waves, then the second adds the first's total
@@ -644,16 +667,8 @@ __global__ __launch_bounds__(256) void k_setpts_scatter_passes(
     __syncthreads();
     if (j < sp.n) {
         PointRec<T> r;
-        if (!isfinite(ph) || !isfinite(th)) {
-            r.it = 0;
-            r.ip = 0;
-            r.vt = (T)NAN;
-            r.vp = (T)NAN;
-        } else {
-            split_axis<T>(th, sp.th, sp.w, r.it, r.vt);
-            split_axis<T>(ph, sp.ph, sp.w, r.ip, r.vp);
-        }
-        const int32_t pos = lstart[kr.x] + pre[kr.x / kScanPass].x + kr.y;
+        const int32_t bin = split_point<T>(ph, th, sp, r);
+        const int32_t pos = lstart[bin] + pre[bin / kScanPass].x + wave_aggregated_rank_down(bincount, bin);
         rec[pos] = r;
         perm[pos] = (int32_t)j;
     }
@@ -708,12 +723,10 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
     const bool fused = sp.n > 0 && nbins <= (int64_t)kScanChunk * kScanThreads && fused_blocks <= kFusedMaxBlocks &&
                        sp.th.nf <= kMaxRowsPerScanThread * kScanThreads;
     if (sp.n > 0) {
-        if (prec == 1)
-            hipLaunchKernelGGL(k_setpts_bin<float>, dim3((unsigned)blocks), dim3(threads), 0, s, phi,
-                               theta, sp, bincount, keyrank, rowmark, flags);
-        else
-            hipLaunchKernelGGL(k_setpts_bin<double>, dim3((unsigned)blocks), dim3(threads), 0, s, phi,
-                               theta, sp, bincount, keyrank, rowmark, flags);
+        auto kern = prec == 1 ? (fused ? k_setpts_bin<float, true> : k_setpts_bin<float, false>)
+                              : (fused ? k_setpts_bin<double, true> : k_setpts_bin<double, false>);
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), 0, s, phi, theta, sp, bincount, keyrank,
+                           rowmark, flags);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (fused) {
@@ -735,11 +748,11 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (prec == 1)
             hipLaunchKernelGGL(k_setpts_scatter_passes<float>, dim3((unsigned)blocks), dim3(threads), 0, s, phi, theta,
-                               sp, keyrank, lstart, stage, passtot, (int)npass, binstart, binlist, nbins,
+                               sp, bincount, lstart, stage, passtot, (int)npass, binstart, binlist, nbins,
                                (PointRec<float> *)rec, perm);
         else
             hipLaunchKernelGGL(k_setpts_scatter_passes<double>, dim3((unsigned)blocks), dim3(threads), 0, s, phi,
-                               theta, sp, keyrank, lstart, stage, passtot, (int)npass, binstart, binlist, nbins,
+                               theta, sp, bincount, lstart, stage, passtot, (int)npass, binstart, binlist, nbins,
                                (PointRec<double> *)rec, perm);
         return hipGetLastError();
     }
@@ -749,10 +762,10 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
     if (sp.n > 0) {
         if (prec == 1)
             hipLaunchKernelGGL(k_setpts_scatter<float>, dim3((unsigned)blocks), dim3(threads), 0, s,
-                               phi, theta, sp, keyrank, binstart, (PointRec<float> *)rec, perm, binlist, nbins);
+                               phi, theta, sp, bincount, binstart, (PointRec<float> *)rec, perm, binlist, nbins);
         else
             hipLaunchKernelGGL(k_setpts_scatter<double>, dim3((unsigned)blocks), dim3(threads), 0, s,
-                               phi, theta, sp, keyrank, binstart, (PointRec<double> *)rec, perm, binlist, nbins);
+                               phi, theta, sp, bincount, binstart, (PointRec<double> *)rec, perm, binlist, nbins);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
