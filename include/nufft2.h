@@ -355,7 +355,10 @@ nufft2_status nufft2_autotune(nufft2_prec prec, int64_t n_modes_theta, int64_t n
  * nufft2_server_wait -- block until the request has completed; its status
  *   (a plan or HIP error of that request) and latency in seconds.
  * nufft2_server_stats -- counters and latency percentiles of the requests
- *   completed so far (and the high-water mark of reserved device memory).
+ *   completed so far, the breakdown of their time (queue wait, copies,
+ *   kernels) and the high-water mark of reserved device memory (cached
+ *   plans count with their own workspace size, including point workspaces
+ *   grown for larger requests, which are reserved before they are grown).
  * nufft2_server_drain -- block until every submitted request has completed.
  * nufft2_server_destroy -- drain, stop the thread, free everything.
  */
@@ -387,6 +390,11 @@ typedef struct {
     uint64_t hbm_high_water;     /* bytes reserved at most at once */
     int32_t max_inflight_seen;
     int32_t reserved;
+    /* where a completed request's time went (seconds, p50 and p99 over the
+     * completed requests): queue wait from arrival to admission, the
+     * host-to-device copies, setpts + exec, the device-to-host copy (the
+     * last three from HIP events on the request's stream) */
+    double queue_p50, queue_p99, h2d_p50, h2d_p99, kernel_p50, kernel_p99, d2h_p50, d2h_p99;
 } nufft2_server_stats_t;
 
 nufft2_status nufft2_server_create(const nufft2_server_opts *opts, nufft2_server *out);

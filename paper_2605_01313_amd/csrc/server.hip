@@ -51,7 +51,7 @@ struct CachedPlan {
     nufft2_handle h = nullptr;
     bool busy = false;
     uint64_t last_use = 0;
-    size_t bytes = 0;  // reserved for it (estimate until created, then the plan's own count)
+    size_t bytes = 0;  // reserved for it: the plan's own workspace count
 };
 
 struct Request {
@@ -62,12 +62,15 @@ struct Request {
     size_t buf_bytes = 0;   // its input and output buffers
     nufft2_status status = NUFFT2_OK;
     double latency = 0;
+    double t_admit = 0;     // server clock when its work was enqueued
     bool done = false;
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
+    // recorded before the host-to-device copies, after them, after the
+    // kernels, and after the device-to-host copy (completion)
+    hipEvent_t start = nullptr, h2d = nullptr, kern = nullptr, done = nullptr;
     void *d_buf = nullptr;  // coeffs | phi | theta | out
     size_t cap = 0;
     void *h_stage = nullptr;  // pinned; outputs of requests without out_host
@@ -110,6 +113,14 @@ size_t buffer_bytes(const nufft2_request &r)
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Device bytes per point of a plan's point workspaces (as nufft2_setpts
+// grows them): keyrank, record, permutation.
+size_t point_bytes(int prec)
+{
+    const size_t rs = csize(prec) / 2;
+    return sizeof(int2) + 2 * rs + 8 + sizeof(int32_t);
+}
+
 }  // namespace
 
 struct nufft2_server_s {
@@ -129,6 +140,9 @@ struct nufft2_server_s {
     bool stop = false;
     int64_t completed = 0, failed = 0, pf = 0, created = 0, evicted = 0;
     std::vector<double> latencies;
+    // per completed request: queue wait (arrival to admission), host-to-
+    // device copies, kernels, device-to-host copy (seconds)
+    std::vector<double> t_queue, t_h2d, t_kern, t_d2h;
     double first_arrival = 1e300, last_completion = 0;
     size_t high_water = 0;
 
@@ -182,7 +196,9 @@ void free_retired(nufft2_server_s *s)
 // idle plans (least recently used first), then free the buffers of idle
 // slots other than `keep`.  These frees synchronise the device, so they only
 // happen under memory pressure.  Returns whether it fits.  (A request that
-// passed the submit check always fits once nothing else is in flight.)
+// passed the submit check and needs a new plan always fits once nothing else
+// is in flight; start() falls back to that when a cached plan's growth does
+// not fit beside the plan.)
 bool make_room(nufft2_server_s *s, size_t need, const Slot *keep)
 {
     if (s->reserved + need > s->budget) free_retired(s);
@@ -223,12 +239,35 @@ Start start(nufft2_server_s *s, Slot &sl, Request *q, nufft2_status *st)
             break;
         }
     const size_t need_buf = round_up(q->buf_bytes, 1u << 20);
-    const size_t grow = need_buf > sl.cap ? need_buf : 0;  // a new buffer; the old one retires
-    const size_t need = grow + (cp ? 0 : q->plan_bytes);
+    const size_t grow = need_buf > sl.cap ? need_buf : 0;  // a new buffer
+    if (grow && sl.d_buf) {
+        // the slot's old buffer is idle (its request has completed): it
+        // retires now, reserved until make_room or an idle device frees it
+        s->retired.push_back({sl.d_buf, sl.cap});
+        sl.d_buf = nullptr;
+        sl.cap = 0;
+    }
+    // a cached plan grows its point workspaces in setpts when this request
+    // has more points than it held before
+    const size_t pts_grow =
+        cp && r.n_pts > cp->h->pts_cap ? (size_t)(r.n_pts - cp->h->pts_cap) * point_bytes(r.prec) : 0;
+    size_t need = grow + (cp ? pts_grow : q->plan_bytes);
     if (cp) cp->busy = true;  // not a candidate for eviction while making room
     if (!make_room(s, need, &sl)) {
         if (cp) cp->busy = false;
-        return Start::kWait;
+        if (s->busy > 0) return Start::kWait;  // room comes back as in-flight work completes
+        // nothing in flight, so nothing else will free memory: drop the
+        // cached plan and fall back to a new one, which the submit check
+        // guarantees fits an otherwise empty budget
+        if (cp) {
+            evict_plan(s, cp);
+            cp = nullptr;
+            need = grow + q->plan_bytes;
+        }
+        if (!make_room(s, need, &sl)) {
+            *st = NUFFT2_ERR_ALLOC;
+            return Start::kFailed;
+        }
     }
     auto fail = [&](nufft2_status e) {
         if (cp) cp->busy = false;
@@ -241,7 +280,6 @@ Start start(nufft2_server_s *s, Slot &sl, Request *q, nufft2_status *st)
             (void)hipGetLastError();
             return fail(NUFFT2_ERR_ALLOC);
         }
-        if (sl.d_buf) s->retired.push_back({sl.d_buf, sl.cap});  // still reserved until freed
         sl.d_buf = nb;
         sl.cap = need_buf;
         s->reserve(need_buf);
@@ -270,6 +308,8 @@ Start start(nufft2_server_s *s, Slot &sl, Request *q, nufft2_status *st)
             cp = nullptr;
             return fail(e);
         }
+        // reserved: the estimate, which also covers the point workspaces
+        // setpts will add; corrected to the plan's own count after setpts
         cp->bytes = q->plan_bytes;
         cp->busy = true;
         s->reserve(cp->bytes);
@@ -284,13 +324,24 @@ Start start(nufft2_server_s *s, Slot &sl, Request *q, nufft2_status *st)
     void *d_coeffs = base, *d_phi = base + c_bytes, *d_theta = base + c_bytes + p_bytes,
          *d_out = base + c_bytes + 2 * p_bytes;
     nufft2_status e = NUFFT2_OK;
-    if (hipMemcpyAsync(d_coeffs, r.coeffs_host, c_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
+    q->t_admit = s->now();
+    if (hipEventRecord(sl.start, sl.stream) != hipSuccess ||
+        hipMemcpyAsync(d_coeffs, r.coeffs_host, c_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
         hipMemcpyAsync(d_phi, r.phi_host, p_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
-        hipMemcpyAsync(d_theta, r.theta_host, p_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+        hipMemcpyAsync(d_theta, r.theta_host, p_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
+        hipEventRecord(sl.h2d, sl.stream) != hipSuccess)
         e = NUFFT2_ERR_HIP;
     if (e == NUFFT2_OK) e = nufft2_setpts(cp->h, r.n_pts, (const double *)d_phi, (const double *)d_theta);
+    if (e == NUFFT2_OK) {
+        // the plan's own count from now on (setpts may have grown it)
+        const size_t own = cp->h->ws_bytes;
+        if (own > cp->bytes) s->reserve(own - cp->bytes);
+        else s->reserved -= cp->bytes - own;
+        cp->bytes = own;
+    }
     if (e == NUFFT2_OK) e = nufft2_exec(cp->h, d_coeffs, d_out);
-    if (e == NUFFT2_OK && (hipMemcpyAsync(r.out_host ? r.out_host : sl.h_stage, d_out, out_bytes,
+    if (e == NUFFT2_OK && (hipEventRecord(sl.kern, sl.stream) != hipSuccess ||
+                           hipMemcpyAsync(r.out_host ? r.out_host : sl.h_stage, d_out, out_bytes,
                                           hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
                            hipEventRecord(sl.done, sl.stream) != hipSuccess))
         e = NUFFT2_ERR_HIP;
@@ -307,8 +358,24 @@ Start start(nufft2_server_s *s, Slot &sl, Request *q, nufft2_status *st)
     return Start::kStarted;
 }
 
+// Stage durations of a request whose completion event has fired (seconds;
+// -1 where an interval cannot be read).
+struct StageTimes {
+    double h2d = -1, kern = -1, d2h = -1;
+};
+StageTimes stage_times(const Slot &sl)
+{
+    StageTimes t;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, sl.start, sl.h2d) == hipSuccess) t.h2d = 1e-3 * ms;
+    if (hipEventElapsedTime(&ms, sl.h2d, sl.kern) == hipSuccess) t.kern = 1e-3 * ms;
+    if (hipEventElapsedTime(&ms, sl.kern, sl.done) == hipSuccess) t.d2h = 1e-3 * ms;
+    (void)hipGetLastError();
+    return t;
+}
+
 // Record a finished request (lock held).
-void record(nufft2_server_s *s, Request *q, nufft2_status st, double t_done)
+void record(nufft2_server_s *s, Request *q, nufft2_status st, double t_done, const StageTimes *tm = nullptr)
 {
     q->status = st;
     q->latency = t_done - q->r.t_arrival;
@@ -317,6 +384,12 @@ void record(nufft2_server_s *s, Request *q, nufft2_status st, double t_done)
         s->completed += 1;
         s->pf += (int64_t)q->r.n_fields * q->r.n_pts;
         s->latencies.push_back(q->latency);
+        s->t_queue.push_back(q->t_admit - q->r.t_arrival);
+        if (tm && tm->h2d >= 0 && tm->kern >= 0 && tm->d2h >= 0) {
+            s->t_h2d.push_back(tm->h2d);
+            s->t_kern.push_back(tm->kern);
+            s->t_d2h.push_back(tm->d2h);
+        }
         s->first_arrival = std::min(s->first_arrival, q->r.t_arrival);
         s->last_completion = std::max(s->last_completion, t_done);
     } else {
@@ -327,7 +400,12 @@ void record(nufft2_server_s *s, Request *q, nufft2_status st, double t_done)
 void worker_loop(nufft2_server_s *s)
 {
     (void)hipSetDevice(s->device);
-    std::vector<std::pair<Request *, nufft2_status>> done;
+    struct Done {
+        Request *q;
+        nufft2_status st;
+        StageTimes tm;
+    };
+    std::vector<Done> done;
     for (;;) {
         bool progress = false;
         // 1. retire completed requests
@@ -338,7 +416,7 @@ void worker_loop(nufft2_server_s *s)
             if (q == hipErrorNotReady) continue;
             const nufft2_status st = q == hipSuccess ? NUFFT2_OK : NUFFT2_ERR_HIP;
             if (q != hipSuccess) (void)hipGetLastError();
-            done.push_back({sl.req, st});
+            done.push_back({sl.req, st, st == NUFFT2_OK ? stage_times(sl) : StageTimes{}});
             CachedPlan *cp = sl.plan;
             cp->busy = false;
             cp->last_use = ++s->tick;
@@ -351,7 +429,7 @@ void worker_loop(nufft2_server_s *s)
             const double t = s->now();
             {
                 std::lock_guard<std::mutex> lk(s->mu);
-                for (auto &d : done) record(s, d.first, d.second, t);
+                for (auto &d : done) record(s, d.q, d.st, t, &d.tm);
                 s->inflight -= (int)done.size();
             }
             s->cv_done.notify_all();
@@ -423,14 +501,19 @@ NUFFT2_API nufft2_status nufft2_server_create(const nufft2_server_opts *opts, nu
         return NUFFT2_ERR_HIP;
     }
     s->slots.resize(s->max_inflight);
+    auto release = [&]() {
+        for (Slot &x : s->slots) {
+            for (hipEvent_t ev : {x.start, x.h2d, x.kern, x.done})
+                if (ev) (void)hipEventDestroy(ev);
+            if (x.stream) (void)hipStreamDestroy(x.stream);
+        }
+    };
     for (Slot &sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            hipEventCreate(&sl.start) != hipSuccess || hipEventCreate(&sl.h2d) != hipSuccess ||
+            hipEventCreate(&sl.kern) != hipSuccess || hipEventCreate(&sl.done) != hipSuccess) {
             (void)hipGetLastError();
-            for (Slot &x : s->slots) {
-                if (x.done) (void)hipEventDestroy(x.done);
-                if (x.stream) (void)hipStreamDestroy(x.stream);
-            }
+            release();
             delete s;
             return NUFFT2_ERR_HIP;
         }
@@ -438,10 +521,7 @@ NUFFT2_API nufft2_status nufft2_server_create(const nufft2_server_opts *opts, nu
     try {
         s->worker = std::thread(worker_loop, s);
     } catch (...) {
-        for (Slot &x : s->slots) {
-            (void)hipEventDestroy(x.done);
-            (void)hipStreamDestroy(x.stream);
-        }
+        release();
         delete s;
         return NUFFT2_ERR_ALLOC;
     }
@@ -524,6 +604,16 @@ NUFFT2_API nufft2_status nufft2_server_stats(nufft2_server s, nufft2_server_stat
         st->first_arrival = s->first_arrival;
         st->last_completion = s->last_completion;
     }
+    auto pcts = [](std::vector<double> v, double &p50, double &p99) {
+        std::sort(v.begin(), v.end());
+        if (v.empty()) return;
+        p50 = v[std::min(v.size() - 1, (size_t)(0.50 * (double)v.size()))];
+        p99 = v[std::min(v.size() - 1, (size_t)(0.99 * (double)v.size()))];
+    };
+    pcts(s->t_queue, st->queue_p50, st->queue_p99);
+    pcts(s->t_h2d, st->h2d_p50, st->h2d_p99);
+    pcts(s->t_kern, st->kernel_p50, st->kernel_p99);
+    pcts(s->t_d2h, st->d2h_p50, st->d2h_p99);
     st->plans_created = s->created;
     st->plans_evicted = s->evicted;
     st->hbm_high_water = s->high_water;
@@ -548,7 +638,7 @@ NUFFT2_API nufft2_status nufft2_server_destroy(nufft2_server s)
         (void)hipStreamSynchronize(sl.stream);
         if (sl.d_buf) (void)hipFree(sl.d_buf);
         if (sl.h_stage) (void)hipHostFree(sl.h_stage);
-        (void)hipEventDestroy(sl.done);
+        for (hipEvent_t ev : {sl.start, sl.h2d, sl.kern, sl.done}) (void)hipEventDestroy(ev);
         (void)hipStreamDestroy(sl.stream);
     }
     for (Request *q : s->all) delete q;

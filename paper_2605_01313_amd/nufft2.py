@@ -102,7 +102,11 @@ class nufft2_server_stats_t(ctypes.Structure):
                 ("first_arrival", ctypes.c_double), ("last_completion", ctypes.c_double),
                 ("plans_created", ctypes.c_int64), ("plans_evicted", ctypes.c_int64),
                 ("hbm_high_water", ctypes.c_uint64), ("max_inflight_seen", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32),
+                ("queue_p50", ctypes.c_double), ("queue_p99", ctypes.c_double),
+                ("h2d_p50", ctypes.c_double), ("h2d_p99", ctypes.c_double),
+                ("kernel_p50", ctypes.c_double), ("kernel_p99", ctypes.c_double),
+                ("d2h_p50", ctypes.c_double), ("d2h_p99", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

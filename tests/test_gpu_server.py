@@ -108,6 +108,96 @@ def test_server_small_budget_queues_and_evicts(torch_dev):
     srv.destroy()
 
 
+def c5_request(torch, rng, J, F, fp64):
+    """A request of the serving workload's kind: Grid [0] of J latitudes,
+    2J - 1 modes, decaying spectrum, departure points of a random 8-mode
+    wind with Courant number in [2, 8]."""
+    K = 2 * J - 1
+    c = synth.random_complex(rng, (F, K, K)) * synth.envelope_algebraic(K, K, 1.5)[None]
+    phi_a, theta_a = synth.grid0_points(J)
+    wind = synth.StreamFunctionWind(rng)
+    wind.normalize_courant(phi_a, theta_a, float(rng.uniform(2.0, 8.0)), J)
+    phi, theta = wind.departures(phi_a, theta_a)
+    prec = "fp64" if fp64 else "fp32"
+    cdt = torch.complex128 if fp64 else torch.complex64
+    return {"prec": prec, "eps": 1e-12 if fp64 else 1e-6, "c_np": c, "phi_np": phi, "theta_np": theta,
+            "coeffs": torch.from_numpy(c).to(cdt).pin_memory(),
+            "phi": torch.from_numpy(phi).pin_memory(), "theta": torch.from_numpy(theta).pin_memory(),
+            "out": torch.empty((F, phi.size), dtype=cdt).pin_memory()}
+
+
+def test_server_serving_grid_sizes(torch_dev, oracle_mod):
+    """The serving workload's grid sizes (64 x 128 .. 512 x 1024, 1-3 fields,
+    FP32 and FP64) submitted together: each result meets the oracle on 64
+    sampled points and is bit-identical when run again alone; the stats
+    break the time down into queue wait, copies and kernels."""
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Server
+    rng = np.random.default_rng(512)
+    spec = [(64, 1, False), (128, 3, True), (256, 2, False), (512, 3, False), (512, 1, True), (128, 2, False),
+            (256, 3, True), (64, 3, False)]
+    reqs = [c5_request(torch, rng, J, F, fp64) for J, F, fp64 in spec]
+    say("case server_serving_sizes " + ", ".join(f"{2 * J - 1}^2 x {F} {'fp64' if d else 'fp32'}"
+                                                   for J, F, d in spec))
+    srv = Server(hbm_budget=8 << 30, max_inflight=4)
+    tickets = [srv.submit(r["prec"], r["coeffs"], r["phi"], r["theta"], r["eps"], out=r["out"]) for r in reqs]
+    for t in tickets:
+        assert srv.wait(t)[0] == 0
+    st = srv.stats()
+    say(f"  stats {st}")
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert 0 <= st["queue_p50"] <= st["queue_p99"]
+    assert 0 < st["kernel_p50"] <= st["kernel_p99"] and 0 < st["h2d_p50"] and 0 < st["d2h_p50"]
+    mix = [r["out"].numpy().copy() for r in reqs]
+    srv.destroy()
+    alone = Server(hbm_budget=8 << 30, max_inflight=1)
+    for i, r in enumerate(reqs):
+        r["out"].zero_()
+        t = alone.submit(r["prec"], r["coeffs"], r["phi"], r["theta"], r["eps"], out=r["out"])
+        assert alone.wait(t)[0] == 0
+        assert np.array_equal(r["out"].numpy(), mix[i]), f"request {i} differs alone and in the mix"
+        sel = synth.sample_indices(r["phi_np"].size, 64, seed=i)
+        ref = oracle_mod.dfs_eval(r["c_np"], r["phi_np"][sel], r["theta_np"][sel])
+        err = max(float(np.linalg.norm(mix[i][f, sel] - ref[f]) / np.linalg.norm(ref[f]))
+                  for f in range(ref.shape[0]))
+        say(f"  request {i}: rel l2 on 64 points {err:.2e}")
+        assert err <= r["eps"]
+    alone.destroy()
+
+
+def test_server_reused_plan_with_growing_points_stays_in_budget(torch_dev):
+    """One plan key reused by requests of growing point counts under a tight
+    budget: the growth of the cached plan's point workspaces is reserved
+    before it happens, so the accounted high-water mark and the device
+    memory actually in use both stay within the budget."""
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Server
+    say("case server_growing_points")
+    rng = np.random.default_rng(77)
+    K = 63
+    c = torch.from_numpy(synth.random_complex(rng, (1, K, K))).to(torch.complex64).pin_memory()
+    budget = 48 << 20
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    srv = Server(hbm_budget=budget, max_inflight=2)
+    peak_used = 0
+    for n in (1000, 50000, 200000, 400000, 800000):
+        phi = torch.from_numpy(rng.uniform(0, 2 * np.pi, n)).pin_memory()
+        theta = torch.from_numpy(rng.uniform(0, np.pi, n)).pin_memory()
+        t = srv.submit("fp32", c, phi, theta, 1e-6)
+        assert srv.wait(t)[0] == 0
+        say(f"  n {n} done")
+        free, _ = torch.cuda.mem_get_info()
+        peak_used = max(peak_used, free0 - free)
+    st = srv.stats()
+    say(f"  stats {st}; device memory in use at most {peak_used / 2**20:.1f} MiB")
+    assert st["completed"] == 5 and st["hbm_high_water"] <= budget
+    # the server's streams, events and pinned staging take a little beyond
+    # the budgeted buffers
+    assert peak_used <= budget + (16 << 20)
+    srv.destroy()
+
+
 def test_server_argument_errors(torch_dev):
     torch, dev = torch_dev
     from paper_2605_01313_amd import Nufft2Error, Server, nufft2
