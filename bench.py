@@ -242,6 +242,31 @@ def cpu_baseline(wl, gpu_out, target_s, n_sample=None, one_core_s=5.0):
             "gpu_rel_l2_on_sample": errs}
 
 
+def oracle_checks(samples):
+    """Host-core leg: the oracle (FP64 direct sum) at the sampled points of
+    GPU results kept by a section; worst relative l2 error over fields, per
+    precision.  samples: (prec, FP64 coefficients [F][Kt][Kp], phi, theta,
+    GPU values [F][n])."""
+    import numpy as np
+
+    import oracle
+    worst = {}
+    for prec, c, phi, theta, got in samples:
+        ref = oracle.dfs_eval(c, phi, theta)
+        err = max(float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(ref.shape[0]))
+        worst[prec] = max(worst.get(prec, 0.0), err)
+    return worst
+
+
+def attach_oracle_checks(section, label, check):
+    """Replace a section's kept samples by the oracle's verdict on them (or
+    drop them when the host-core leg is off)."""
+    samples = section.pop("oracle_samples", [])
+    if check:
+        section[label] = {"samples": len(samples), "points_each": len(samples[0][2]) if samples else 0,
+                          "max_rel_l2": oracle_checks(samples)}
+
+
 def _member(spec):
     import synth
     return synth.ensemble_member(spec)
@@ -315,6 +340,16 @@ def serving_bench(args, torch):
         phi, theta = pool[J]["pts"][i % n_pts_pool]
         return ("fp64" if fp64 else "fp32", c, phi, theta, 1e-12 if fp64 else 1e-6)
 
+    # 1% of the stream (every 100th request) keeps its result, to be checked
+    # against the oracle on 64 sampled points and against a run of the same
+    # request alone; pinned outputs allocated before the stream starts
+    checked = list(range(0, n_req, 100))
+    check_out = {}
+    for i in checked:
+        J, F, fp64 = int(sizes[i]), int(fields[i]), bool(is64[i])
+        cdt = torch.complex128 if fp64 else torch.complex64
+        check_out[i] = torch.empty((F, 2 * J * J), dtype=cdt).pin_memory()
+
     # warm-up: a burst of the largest request grows every slot's buffers,
     # then a burst of every (size, fields, precision) creates plans for the
     # concurrency the stream will need
@@ -345,12 +380,31 @@ def serving_bench(args, torch):
                 time.sleep(t_arr - now - 0.001)
         lag = max(lag, srv.clock() - t_arr)
         prec, c, phi, theta, eps = request(i, int(sizes[i]), int(fields[i]), bool(is64[i]))
-        srv.submit(prec, c, phi, theta, eps, t_arrival=t_arr)
+        srv.submit(prec, c, phi, theta, eps, out=check_out.get(i), t_arrival=t_arr)
         if (i + 1) % 20000 == 0:
             log(f"bench: {i + 1} requests submitted")
     srv.drain()
     st = srv.stats()
     srv.destroy()
+    # the kept results: each request run again alone on a one-slot server
+    # must reproduce its in-stream result bit for bit; 64 sampled points of
+    # each go to the oracle check of the host-core leg (FP64 direct sum of
+    # the request's FP64 coefficients)
+    log(f"bench: re-running {len(checked)} kept requests alone")
+    alone = Server(hbm_budget=args.serve_budget_gib << 30, max_inflight=1)
+    identical = 0
+    samples = []
+    for i in checked:
+        J, F, fp64 = int(sizes[i]), int(fields[i]), bool(is64[i])
+        prec, c, phi, theta, eps = request(i, J, F, fp64)
+        got = check_out[i].numpy().copy()
+        sel = synth.sample_indices(phi.numel(), 64, seed=i)
+        samples.append((prec, pool[J]["c64"][i % n_coef_pool][:F].numpy(), phi.numpy()[sel],
+                        theta.numpy()[sel], got[:, sel]))
+        t = alone.submit(prec, c, phi, theta, eps, out=check_out[i])
+        alone.wait(t)
+        identical += int(np.array_equal(check_out[i].numpy(), got))
+    alone.destroy()
     done = st["completed"] - warm["completed"]
     pf = st["points_fields"] - warm["points_fields"]
     span = st["last_completion"] - t_start
@@ -363,6 +417,10 @@ def serving_bench(args, torch):
                    "grids": "64x128,128x256,256x512,512x1024", "fields": "1-3", "fp32_share": 0.8,
                    "hbm_budget_gib": args.serve_budget_gib, "max_inflight": args.serve_inflight,
                    "payload_pool_per_size": n_pts_pool},
+        "time_breakdown_ms": {k: st[k] * 1e3 for k in ("queue_p50", "queue_p99", "h2d_p50", "h2d_p99",
+                                                       "kernel_p50", "kernel_p99", "d2h_p50", "d2h_p99")},
+        "kept_requests": {"count": len(checked), "every": 100, "identical_when_run_alone": identical},
+        "oracle_samples": samples,
         "failed": st["failed"], "offered_points_fields_per_s": offered_pf,
         "submit_lag_max_ms": lag * 1e3, "plans_created": st["plans_created"],
         "plans_evicted": st["plans_evicted"], "hbm_high_water_gib": st["hbm_high_water"] / 2**30,
@@ -372,6 +430,7 @@ def serving_bench(args, torch):
 
 def serving_line(args, torch):
     r = serving_bench(args, torch)
+    attach_oracle_checks(r, "kept_requests_vs_oracle", not args.no_cpu_baseline)
     line = {
         "metric": METRIC, "value": r["value"], "unit": "points*fields/s", "n_gpus": 1,
         "steps": r["requests"], "warmup": 0, "ms_per_step": r["span_s"] * 1e3 / max(r["requests"], 1),
@@ -394,9 +453,6 @@ def ensemble_bench(args, torch, steps, warmup):
     eps 1e-12, one field per exec, synchronised after every exec."""
     import tempfile
 
-    import numpy as np
-
-    import oracle
     import synth
     from paper_2605_01313_amd import Group, Plan, autotune
     dev = torch.device("cuda:0")
@@ -478,16 +534,15 @@ def ensemble_bench(args, torch, steps, warmup):
     ms64 = (time.perf_counter() - t0) * 1e3 / reps
     log(f"bench: plain FP64 path {ms64:.3f} ms/step")
 
-    # accuracy on a few members against the oracle (256 sampled points each)
+    # results of a few members on 256 sampled points each, for the oracle
+    # check of the host-core leg
     step()
     torch.cuda.synchronize()
-    errs = []
+    samples = []
     for i in (0, 31, 63, 64, 79):
         m = members[i]
         sel = synth.sample_indices(m.n_pts, 256, seed=20 + i)
-        ref = oracle.dfs_eval(m.coeffs, m.phi[sel], m.theta[sel])
-        got = outs[i].cpu().numpy()[:, sel]
-        errs.append(max(float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(F)))
+        samples.append(("fp32", m.coeffs, m.phi[sel], m.theta[sel], outs[i].cpu().numpy()[:, sel]))
     info = g.info()
     g.destroy()
     return {
@@ -500,7 +555,7 @@ def ensemble_bench(args, torch, steps, warmup):
         "plain_fp64_single_field": {"value": n_pf / (ms64 * 1e-3), "unit": "points*fields/s",
                                     "ms_per_step": ms64, "eps": 1e-12,
                                     "speedup_of_batched_fp32": ms64 / ms},
-        "rel_l2_vs_oracle_sampled": {"members": [0, 31, 63, 64, 79], "max": max(errs)},
+        "oracle_samples": samples,
     }
 
 
@@ -601,6 +656,7 @@ def upstream_line(args, torch):
 
 def ensemble_line(args, torch):
     r = ensemble_bench(args, torch, args.steps, args.warmup)
+    attach_oracle_checks(r, "rel_l2_vs_oracle_sampled", not args.no_cpu_baseline)
     line = {
         "metric": METRIC, "value": r["value"], "unit": "points*fields/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
@@ -608,7 +664,7 @@ def ensemble_line(args, torch):
         "config": dict(workload="ensemble_64x128x256_16x256x512_3fields", **r["config"]),
         "latency_ms": r["latency_ms"],
         "plain_fp64_single_field": r["plain_fp64_single_field"],
-        "rel_l2_vs_oracle_sampled": r["rel_l2_vs_oracle_sampled"],
+        "rel_l2_vs_oracle_sampled": r.get("rel_l2_vs_oracle_sampled"),
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
@@ -694,6 +750,11 @@ def main():
         line["cpu_baseline"] = cpu_baseline(*cpu_args)
     else:
         line["cpu_baseline"] = None
+    # the sections' kept GPU results against the oracle (host-core leg)
+    if "ensemble" in line:
+        attach_oracle_checks(line["ensemble"], "rel_l2_vs_oracle_sampled", cpu_args is not None)
+    if "serving" in line:
+        attach_oracle_checks(line["serving"], "kept_requests_vs_oracle", cpu_args is not None)
     print(json.dumps(line), flush=True)
 
 
