@@ -21,7 +21,8 @@
 //
 // Kernel weights: FP32 plans of width >= 7 evaluate each tap's weight as a
 // degree-8 polynomial in the point's centred offset (coefficients from the
-// plan, interpolated in long double, within 1e-7 of the kernel); the direct
+// plan, interpolated in long double, within 1e-7 of the kernel; mirrored
+// taps share the even and odd parts of one polynomial); the direct
 // form is used otherwise, written as exp(-beta z^2 / (1 + sqrt(1 - z^2)))
 // in FP32, which has no cancellation near the kernel's peak.
 #pragma once
@@ -55,28 +56,58 @@ template <> __device__ inline double es_kernel<double>(double z, double k)
     return exp(k * (sqrt(t) - 1.0));
 }
 
-// Weights of the W taps along one axis for a point with offset v (natural
-// column order).
+// Weights of the W taps along both axes for a point with offsets v0 and v1
+// (natural column order), into w0 and w1.
 template <typename T, int W>
-__device__ __forceinline__ void tap_weights(T v, const GatherParams &gp, T (&pw)[W])
+__device__ __forceinline__ void tap_weights2(T v0, T v1, const GatherParams &gp, T (&w0)[W], T (&w1)[W])
 {
     constexpr int H = W / 2;
     if constexpr (sizeof(T) == 4 && W >= kPolyMinW) {
         if (gp.wpoly) {
             // u: the offset relative to the centre of its range (0 for odd
             // w, -1/2 for even w)
-            const float u = (W & 1) ? v : v + 0.5f;
+            const float u0 = (W & 1) ? v0 : v0 + 0.5f;
+            const float u1 = (W & 1) ? v1 : v1 + 0.5f;
             // read through the constant address space: the same for every
             // lane, so the coefficients come in by scalar loads into SGPRs
-            // (a plain global pointer gets per-lane vector loads)
+            // (a plain global pointer gets per-lane vector loads); both axes
+            // use each coefficient as it arrives
             using cfloat = const __attribute__((address_space(4))) float;
             cfloat *c = (cfloat *)gp.wpoly;
+            // The kernel is even, so tap w-1-b at offset u weighs what tap b
+            // weighs at -u: with p_b(u) = E(u^2) + u O(u^2), one even and
+            // one odd part give both taps of a mirrored pair (the fits at
+            // symmetric nodes agree with this up to rounding), and the
+            // middle tap of an odd width is its even part alone.
+            static_assert(kPolyCoefs % 2 == 1, "even part of degree kPolyCoefs - 1");
+            const float t0 = u0 * u0, t1 = u1 * u1;
 #pragma unroll
-            for (int b = 0; b < W; ++b) {
-                float acc = c[b * kPolyCoefs + kPolyCoefs - 1];
+            for (int b = 0; b < (W + 1) / 2; ++b) {
+                const float ce = c[b * kPolyCoefs + kPolyCoefs - 1];
+                float e0 = ce, e1 = ce;
 #pragma unroll
-                for (int j = kPolyCoefs - 2; j >= 0; --j) acc = fmaf(acc, u, c[b * kPolyCoefs + j]);
-                pw[b] = acc;
+                for (int j = kPolyCoefs - 3; j >= 0; j -= 2) {
+                    const float cj = c[b * kPolyCoefs + j];
+                    e0 = fmaf(e0, t0, cj);
+                    e1 = fmaf(e1, t1, cj);
+                }
+                if ((W & 1) && b == W / 2) {
+                    w0[b] = e0;
+                    w1[b] = e1;
+                    break;
+                }
+                const float co = c[b * kPolyCoefs + kPolyCoefs - 2];
+                float o0 = co, o1 = co;
+#pragma unroll
+                for (int j = kPolyCoefs - 4; j >= 1; j -= 2) {
+                    const float cj = c[b * kPolyCoefs + j];
+                    o0 = fmaf(o0, t0, cj);
+                    o1 = fmaf(o1, t1, cj);
+                }
+                w0[b] = fmaf(u0, o0, e0);
+                w0[W - 1 - b] = fmaf(-u0, o0, e0);
+                w1[b] = fmaf(u1, o1, e1);
+                w1[W - 1 - b] = fmaf(-u1, o1, e1);
             }
             return;
         }
@@ -84,7 +115,10 @@ __device__ __forceinline__ void tap_weights(T v, const GatherParams &gp, T (&pw)
     const T inv_hw = (T)2 / (T)W;
     const T kc = es_constant<T>(gp.beta);
 #pragma unroll
-    for (int b = 0; b < W; ++b) pw[b] = es_kernel<T>(((T)(b - H) - v) * inv_hw, kc);
+    for (int b = 0; b < W; ++b) {
+        w0[b] = es_kernel<T>(((T)(b - H) - v0) * inv_hw, kc);
+        w1[b] = es_kernel<T>(((T)(b - H) - v1) * inv_hw, kc);
+    }
 }
 
 // Accumulation a += w v for real and complex grid values.
@@ -119,7 +153,11 @@ template <> struct VecOf<float> { using type = float4; };
 template <typename T, bool RG> struct GridElem { using type = cplx<T>; };
 template <typename T> struct GridElem<T, true> { using type = T; };
 
-constexpr int kGatherThreads = 256;
+// Workgroup size: FP32 bins (about 128 points at the default tile) run on
+// kGatherThreadsF32 threads, FP64 on 256 (whose bins of at most 128 points
+// split their rows over two lanes).
+constexpr int kGatherThreadsF32 = 256;
+template <typename T> constexpr int gather_threads() { return sizeof(T) == 4 ? kGatherThreadsF32 : 256; }
 constexpr int kLoadBatch = 4;
 // FP64 splits the rows of a point over two lanes when a chunk holds at most
 // half a workgroup's points (see gather_body).
@@ -208,11 +246,13 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
     const int plane = TR * TCP;
     constexpr int H = W / 2;
     constexpr int NK = lds_lane_group<E>();
+    constexpr int NT = gather_threads<T>();
+    static_assert(NT % NK == 0 && NK <= 64, "lane groups tile the workgroup; the key scan runs in wave 0");
     __shared__ int bucket[NK];  // per bank key: count, then start
-    __shared__ short slot[kGatherThreads];  // lane -> point of the chunk (-1: none)
-    __shared__ int dsts[kGatherThreads];    // destination of each point of the chunk
-    __shared__ PointRec<T> recs[kGatherThreads];  // record of each point of the chunk
-    __shared__ E xsum[kSplitRows<T> ? kGatherThreads / 2 * FG : 1];  // partial sums of split points
+    __shared__ short slot[NT];  // lane -> point of the chunk (-1: none)
+    __shared__ int dsts[NT];    // destination of each point of the chunk
+    __shared__ PointRec<T> recs[NT];  // record of each point of the chunk
+    __shared__ E xsum[kSplitRows<T> ? NT / 2 * FG : 1];  // partial sums of split points
     const int64_t field_stride = (int64_t)gp.nft * gp.nfp;
 
     // FG fields per pass; the last pass may hold fewer (fg)
@@ -227,7 +267,7 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
         const E *gridf[FG];
 #pragma unroll
         for (int f = 0; f < FG; ++f) gridf[f] = grid + (int64_t)(f0 + (f < fg ? f : 0)) * field_stride;
-        for (int j0 = 0; j0 < nchunk; j0 += kLoadBatch * kGatherThreads) {
+        for (int j0 = 0; j0 < nchunk; j0 += kLoadBatch * NT) {
             Vec buf[kLoadBatch][FG];
             int lo[kLoadBatch];
             // Loads past the patch are clamped to its first chunk and not
@@ -237,8 +277,8 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
 #pragma unroll
             for (int u = 0; u < kLoadBatch; ++u) {
                 lo[u] = -1;
-                if (!FIXED || j0 + u * kGatherThreads < nchunk) {
-                    const int j = j0 + u * kGatherThreads + (int)threadIdx.x;
+                if (!FIXED || j0 + u * NT < nchunk) {
+                    const int j = j0 + u * NT + (int)threadIdx.x;
                     const int jj = j < nchunk ? j : 0;
                     const int r = jj / NC, k = jj - r * NC;
                     const int off = ((r0 + r) & (gp.nft - 1)) * gp.nfp + ((c0 + k * V) & (gp.nfp - 1));
@@ -256,7 +296,7 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
             }
         }
         __syncthreads();
-        for (int base = 0; base < cnt; base += kGatherThreads) {
+        for (int base = 0; base < cnt; base += NT) {
             // Deal this chunk's points to lanes: counting-sort them by bank
             // key (patch offset of the first tap plus the column rotation,
             // modulo NK), then give sorted position k to lane
@@ -264,7 +304,7 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
             // lane group, so a group holds distinct keys unless one key has
             // more than R points.  The order inside a key (atomic ranks) does
             // not matter: a point's sum does not depend on its lane.
-            const int n = min(kGatherThreads, cnt - base);
+            const int n = min(NT, cnt - base);
             const int R = (n + NK - 1) / NK;
             const int t = (int)threadIdx.x;
             if (t < NK) bucket[t] = 0;
@@ -309,7 +349,7 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
             // waves work on the taps instead of two.  The choice depends on
             // the bin's count only, never on which chunk a point fell in, so
             // a point's sum stays independent of the order inside its bin.
-            constexpr int HALF = kGatherThreads / 2;
+            constexpr int HALF = NT / 2;
             const bool split = kSplitRows<T> && cnt <= HALF;
             const bool upper = split && t >= HALF;
             const int mine = upper ? slot[t - HALF] : slot[t];
@@ -328,8 +368,10 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
                 // step b reads column (b + rot) mod w; wp[b] is that column's weight
                 const int rot = bad ? 0 : column_rotation(pr.it, pr.ip);
                 const int last = rot ? 0 : W - 1;  // column of the final step
-                T pw[W], wp[W];
-                tap_weights<T, W>(bad ? (T)0 : pr.vp, gp, pw);
+                // FP32 takes the row weights with the column weights; FP64
+                // computes them row by row below
+                T pw[W], wp[W], pt[W];
+                tap_weights2<T, W>(bad ? (T)0 : pr.vp, bad ? (T)0 : pr.vt, gp, pw, pt);
 #pragma unroll
                 for (int b = 0; b < W; ++b) wp[b] = rot ? pw[(b + 1) % W] : pw[b];
                 const E *row0 = tiles + lr * TCP + lc;
@@ -338,8 +380,6 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
                     // when the tile is fixed; the scheduling barrier after
                     // each row keeps the compiler from hoisting every row's
                     // LDS reads (and running out of registers)
-                    T pt[W];
-                    tap_weights<T, W>(bad ? (T)0 : pr.vt, gp, pt);
                     const E *rrow = row0 + rot;
                     const E *lrow = row0 + last;
 #pragma unroll
@@ -413,7 +453,7 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
 }
 
 template <typename T, bool RG, int W, int FG, int TT, int TP>
-__global__ __launch_bounds__(kGatherThreads) void k_gather(const typename GridElem<T, RG>::type *__restrict__ grid,
+__global__ __launch_bounds__(gather_threads<T>()) void k_gather(const typename GridElem<T, RG>::type *__restrict__ grid,
                                                            const PointRec<T> *__restrict__ rec,
                                                            const int32_t *__restrict__ perm,
                                                            const int32_t *__restrict__ binlist,
@@ -425,7 +465,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const typename GridEl
 // Member j of a group class owns workgroups [j * per, (j + 1) * per); per is
 // a multiple of 8, so a workgroup's XCD is the same as in a launch of its own.
 template <typename T, bool RG, int W, int FG, int TT, int TP>
-__global__ __launch_bounds__(kGatherThreads) void k_gather_group(const GatherJob *__restrict__ jobs, int per)
+__global__ __launch_bounds__(gather_threads<T>()) void k_gather_group(const GatherJob *__restrict__ jobs, int per)
 {
     const int j = (int)blockIdx.x / per;
     const GatherJob J = jobs[j];
@@ -451,27 +491,31 @@ static hipError_t launch_tile(const GatherParams &gp, const void *grid, const vo
         auto kern = k_gather_group<T, RG, W, FG, TT, TP>;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(kern, dim3((unsigned)(per * n_members)), dim3(kGatherThreads), lds, s, jobs, per);
+        hipLaunchKernelGGL(kern, dim3((unsigned)(per * n_members)), dim3(gather_threads<T>()), lds, s, jobs, per);
     } else {
         auto kern = k_gather<T, RG, W, FG, TT, TP>;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(kern, dim3((unsigned)per), dim3(kGatherThreads), lds, s, (const E *)grid,
+        hipLaunchKernelGGL(kern, dim3((unsigned)per), dim3(gather_threads<T>()), lds, s, (const E *)grid,
                            (const PointRec<T> *)rec, perm, binlist, out, gp);
     }
     return hipGetLastError();
 }
 
-// The default tile (16 x 32) of FP32 plans has compile-time patch
-// geometry; other tiles and FP64 take it at run time.
+// The default tiles of FP32 plans (16 x 32 complex, 16 x 64 real-field)
+// have compile-time patch geometry; other tiles and FP64 take it at run time.
 template <typename T, bool RG, int W, int FG>
 static hipError_t launch_wf(const GatherParams &gp, const void *grid, const void *rec,
                             const int32_t *perm, const int32_t *binlist, void *out, const GatherJob *jobs,
                             int n_members, hipStream_t s)
 {
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4 && !RG) {
         if (gp.tile_t == 16 && gp.tile_p == 32)
             return launch_tile<T, RG, W, FG, 16, 32>(gp, grid, rec, perm, binlist, out, jobs, n_members, s);
+    }
+    if constexpr (sizeof(T) == 4 && RG) {
+        if (gp.tile_t == 16 && gp.tile_p == 64)
+            return launch_tile<T, RG, W, FG, 16, 64>(gp, grid, rec, perm, binlist, out, jobs, n_members, s);
     }
     return launch_tile<T, RG, W, FG, 0, 0>(gp, grid, rec, perm, binlist, out, jobs, n_members, s);
 }
