@@ -26,6 +26,11 @@ constexpr int kMaxW = 16;
 constexpr double kDefaultBetaOverW = 2.30;
 constexpr int kDefaultTileTheta = 16;
 constexpr int kDefaultTilePhi = 32;
+// FP32 real-field plans: a real patch takes half the LDS of a complex one,
+// and the wider tile gives the gather's workgroup about twice the points
+// (16 x 64 measured 7% faster than 16 x 32 at 2048^2 with the tile taken
+// at run time, and faster than 32 x 32, 8 x 64 and 32 x 64).
+constexpr int kDefaultTilePhiReal32 = 64;
 constexpr size_t kGatherLdsLimit = 65536;  // per staged field group
 constexpr size_t kFftLdsLimit = 155648;    // 152 KiB of the 160 KiB per workgroup
 constexpr size_t kCuLds = 163840;          // LDS per CU
@@ -469,7 +474,8 @@ nufft2_status plan_configure(nufft2_plan_s *p, int prec, int64_t n_modes_theta, 
 
     bool bad_tile = false;
     const int tt = choose_tile(o.tile_theta, kDefaultTileTheta, (int)nft, &bad_tile);
-    const int tp = choose_tile(o.tile_phi, kDefaultTilePhi, (int)nfp, &bad_tile);
+    const int tp = choose_tile(o.tile_phi, prec == NUFFT2_FP32 && o.hermitian ? kDefaultTilePhiReal32 : kDefaultTilePhi,
+                               (int)nfp, &bad_tile);
     if (bad_tile) return NUFFT2_ERR_ARG;
     {
         // the gather stages a (tile + w - 1)^2 patch of one field in LDS
