@@ -49,31 +49,49 @@ __device__ inline void split_axis(double x, const AxisParams &ax, int w, int32_t
     v = (T)(u - (double)(w >> 1));
 }
 
-// Rank of this lane's point among the points of its bin.  Lanes of a wave
-// that share a bin are grouped with ballots first (no memory traffic); then
-// every group leader adds its group's size with one atomic, all leaders in
-// the same instruction, so the wave pays one atomic round trip.  Departure
-// points arrive in grid order, so a wave touches only a few bins.
-__device__ inline int32_t wave_aggregated_rank(int32_t *__restrict__ bincount, int32_t bin)
+// Lanes of a wave that share a bin are grouped with ballots (no memory
+// traffic): the group's leader lane, this lane's place in its group, and on
+// the leader the group's size (0 elsewhere).  Departure points arrive in
+// grid order, so a wave touches only a few bins.
+struct WaveGroup {
+    int leader;
+    int32_t offset, count;
+};
+__device__ inline WaveGroup wave_group(int32_t bin)
 {
     const int lane = (int)__lane_id();
     uint64_t pending = __ballot(1);
-    int leader_of_mine = lane;
-    int32_t offset = 0, count = 0;
+    WaveGroup g{lane, 0, 0};
     while (pending) {
         const int leader = __ffsll((unsigned long long)pending) - 1;
         const int32_t lbin = __shfl(bin, leader, 64);
         const uint64_t grp = pending & __ballot(bin == lbin);
         if ((grp >> lane) & 1ull) {
-            leader_of_mine = leader;
-            offset = (int32_t)__popcll(grp & ((1ull << lane) - 1ull));
+            g.leader = leader;
+            g.offset = (int32_t)__popcll(grp & ((1ull << lane) - 1ull));
         }
-        if (lane == leader) count = (int32_t)__popcll(grp);
+        if (lane == leader) g.count = (int32_t)__popcll(grp);
         pending &= ~grp;
     }
+    return g;
+}
+
+// Rank of this lane's point among the points of its bin: every group leader
+// adds its group's size with one atomic, all leaders in the same
+// instruction, so the wave pays one atomic round trip.
+__device__ inline int32_t wave_aggregated_rank(int32_t *__restrict__ bincount, int32_t bin)
+{
+    const WaveGroup g = wave_group(bin);
     int32_t base = 0;
-    if (count > 0) base = atomicAdd(&bincount[bin], count);
-    return __shfl(base, leader_of_mine, 64) + offset;
+    if (g.count > 0) base = atomicAdd(&bincount[bin], g.count);
+    return __shfl(base, g.leader, 64) + g.offset;
+}
+
+// Counting only (the rank is not needed).
+__device__ inline void wave_aggregated_count(int32_t *__restrict__ bincount, int32_t bin)
+{
+    const WaveGroup g = wave_group(bin);
+    if (g.count > 0) atomicAdd(&bincount[bin], g.count);
 }
 
 // The same grouping, taking ranks from the top: every group leader
@@ -82,24 +100,10 @@ __device__ inline int32_t wave_aggregated_rank(int32_t *__restrict__ bincount, i
 // Once every point of a bin has taken its rank the count is zero again.
 __device__ inline int32_t wave_aggregated_rank_down(int32_t *__restrict__ bincount, int32_t bin)
 {
-    const int lane = (int)__lane_id();
-    uint64_t pending = __ballot(1);
-    int leader_of_mine = lane;
-    int32_t offset = 0, count = 0;
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int32_t lbin = __shfl(bin, leader, 64);
-        const uint64_t grp = pending & __ballot(bin == lbin);
-        if ((grp >> lane) & 1ull) {
-            leader_of_mine = leader;
-            offset = (int32_t)__popcll(grp & ((1ull << lane) - 1ull));
-        }
-        if (lane == leader) count = (int32_t)__popcll(grp);
-        pending &= ~grp;
-    }
+    const WaveGroup g = wave_group(bin);
     int32_t base = 0;
-    if (count > 0) base = atomicSub(&bincount[bin], count) - count;
-    return __shfl(base, leader_of_mine, 64) + offset;
+    if (g.count > 0) base = atomicSub(&bincount[bin], g.count) - g.count;
+    return __shfl(base, g.leader, 64) + g.offset;
 }
 
 // Wrap/split of one point and its bin (non-finite coordinates: bin 0 and a
@@ -119,16 +123,14 @@ __device__ inline int32_t split_point(double ph, double th, const SetptsParams &
     return (r.it / sp.th.tile) * sp.nbins_phi + r.ip / sp.ph.tile;
 }
 
-// Point j (a thread of a 256-thread block; j >= n: inactive).  KR: also
-// write the point's (bin, rank) for the fused scan + scatter.
+// Point j with coordinates (ph, th) (a thread of a 256-thread block; the
+// caller skips j >= n).  KR: also write the point's (bin, rank) for the
+// fused scan + scatter.
 template <typename T, bool KR>
-__device__ inline void setpts_bin_point(int64_t j, const double *__restrict__ phi, const double *__restrict__ theta,
-                                        const SetptsParams &sp, int32_t *__restrict__ bincount,
-                                        int2 *__restrict__ keyrank, uint8_t *__restrict__ rowmark,
-                                        int32_t *__restrict__ flags)
+__device__ inline void setpts_bin_point(int64_t j, double ph, double th, const SetptsParams &sp,
+                                        int32_t *__restrict__ bincount, int2 *__restrict__ keyrank,
+                                        uint8_t *__restrict__ rowmark, int32_t *__restrict__ flags)
 {
-    if (j >= sp.n) return;
-    const double ph = phi[j], th = theta[j];
     int32_t bin;
     if (!isfinite(ph) || !isfinite(th)) {
         atomicOr(&flags[0], 1);
@@ -141,20 +143,39 @@ __device__ inline void setpts_bin_point(int64_t j, const double *__restrict__ ph
         bin = (it / sp.th.tile) * sp.nbins_phi + ip / sp.ph.tile;
         rowmark[it] = 1;
     }
-    const int32_t rank = wave_aggregated_rank(bincount, bin);
-    if (KR) keyrank[j] = make_int2(bin, rank);
+    if (KR) keyrank[j] = make_int2(bin, wave_aggregated_rank(bincount, bin));
+    else wave_aggregated_count(bincount, bin);
 }
 
+// Points per thread of the bin and scatter kernels of a single plan: a
+// thread's points (256 apart, so that each wave still takes consecutive
+// points) are loaded together, which keeps several loads in flight per
+// thread.
+constexpr int kPointsPerThread = 4;
+constexpr int kSetptsThreads = 256;
+constexpr int64_t kPointsPerBlock = (int64_t)kPointsPerThread * kSetptsThreads;
+
 template <typename T, bool KR>
-__global__ __launch_bounds__(256) void k_setpts_bin(const double *__restrict__ phi,
-                                                    const double *__restrict__ theta, SetptsParams sp,
-                                                    int32_t *__restrict__ bincount,
-                                                    int2 *__restrict__ keyrank,
-                                                    uint8_t *__restrict__ rowmark,
-                                                    int32_t *__restrict__ flags)
+__global__ __launch_bounds__(kSetptsThreads) void k_setpts_bin(const double *__restrict__ phi,
+                                                               const double *__restrict__ theta, SetptsParams sp,
+                                                               int32_t *__restrict__ bincount,
+                                                               int2 *__restrict__ keyrank,
+                                                               uint8_t *__restrict__ rowmark,
+                                                               int32_t *__restrict__ flags)
 {
-    setpts_bin_point<T, KR>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, phi, theta, sp, bincount, keyrank,
-                            rowmark, flags);
+    const int64_t j0 = (int64_t)blockIdx.x * kPointsPerBlock + threadIdx.x;
+    double ph[kPointsPerThread], th[kPointsPerThread];
+#pragma unroll
+    for (int q = 0; q < kPointsPerThread; ++q) {
+        const int64_t j = j0 + q * kSetptsThreads;
+        ph[q] = j < sp.n ? phi[j] : 0.0;
+        th[q] = j < sp.n ? theta[j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kPointsPerThread; ++q) {
+        const int64_t j = j0 + q * kSetptsThreads;
+        if (j < sp.n) setpts_bin_point<T, KR>(j, ph[q], th[q], sp, bincount, keyrank, rowmark, flags);
+    }
 }
 
 // Group launches: job_of_block[b] is the member that owns point block b;
@@ -164,8 +185,8 @@ __global__ __launch_bounds__(256) void k_setpts_bin_group(const SetptsJob *__res
                                                           const int32_t *__restrict__ job_of_block)
 {
     const SetptsJob J = jobs[job_of_block[blockIdx.x]];
-    setpts_bin_point<T, false>((int64_t)((int)blockIdx.x - J.block_begin) * blockDim.x + threadIdx.x, J.phi,
-                               J.theta, J.sp, J.bincount, J.keyrank, J.rowmark, J.flags);
+    const int64_t j = (int64_t)((int)blockIdx.x - J.block_begin) * blockDim.x + threadIdx.x;
+    if (j < J.sp.n) setpts_bin_point<T, false>(j, J.phi[j], J.theta[j], J.sp, J.bincount, J.keyrank, J.rowmark, J.flags);
 }
 
 // Block-wide exclusive scans of two ints per thread at once (one set of
@@ -443,6 +464,44 @@ __device__ inline void setpts_scatter_point(int64_t j, const double *__restrict_
     }
 }
 
+// kPointsPerThread points of one thread (j0, j0 + 256, ...; coordinates
+// already loaded): every point's split and lane grouping first, then all
+// their count decrements, so that the atomics' round trips overlap; each
+// point then goes to start(bin) + its rank.
+template <typename T, class Start>
+__device__ inline void setpts_scatter_points(int64_t j0, const double (&ph)[kPointsPerThread],
+                                             const double (&th)[kPointsPerThread], const SetptsParams &sp,
+                                             int32_t *__restrict__ bincount, const Start &start,
+                                             PointRec<T> *__restrict__ rec, int32_t *__restrict__ perm)
+{
+    PointRec<T> r[kPointsPerThread];
+    int32_t bin[kPointsPerThread], base[kPointsPerThread];
+    WaveGroup g[kPointsPerThread];
+#pragma unroll
+    for (int q = 0; q < kPointsPerThread; ++q) {
+        bin[q] = 0;
+        base[q] = 0;
+        g[q] = WaveGroup{0, 0, 0};
+        if (j0 + q * kSetptsThreads < sp.n) {
+            bin[q] = split_point<T>(ph[q], th[q], sp, r[q]);
+            g[q] = wave_group(bin[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kPointsPerThread; ++q)
+        if (j0 + q * kSetptsThreads < sp.n && g[q].count > 0)
+            base[q] = atomicSub(&bincount[bin[q]], g[q].count) - g[q].count;
+#pragma unroll
+    for (int q = 0; q < kPointsPerThread; ++q) {
+        const int64_t j = j0 + q * kSetptsThreads;
+        if (j < sp.n) {
+            const int32_t pos = start(bin[q]) + __shfl(base[q], g[q].leader, 64) + g[q].offset;
+            rec[pos] = r[q];
+            perm[pos] = (int32_t)j;
+        }
+    }
+}
+
 // Above kDealtMaxBins bins the gather's per-slot table (see bin_dealt) is
 // written here, by the scatter's threads (thread i of n: slots i, i + n,
 // ...), from the entries the scan published: one workgroup could not write
@@ -462,18 +521,25 @@ __device__ inline void scatter_dealt(int64_t i, int64_t n, int32_t *__restrict__
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_setpts_scatter(const double *__restrict__ phi,
-                                                        const double *__restrict__ theta,
-                                                        SetptsParams sp,
-                                                        int32_t *__restrict__ bincount,
-                                                        const int32_t *__restrict__ binstart,
-                                                        PointRec<T> *__restrict__ rec,
-                                                        int32_t *__restrict__ perm,
-                                                        int32_t *__restrict__ binlist, int64_t nbins)
+__global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter(const double *__restrict__ phi,
+                                                                   const double *__restrict__ theta,
+                                                                   SetptsParams sp,
+                                                                   int32_t *__restrict__ bincount,
+                                                                   const int32_t *__restrict__ binstart,
+                                                                   PointRec<T> *__restrict__ rec,
+                                                                   int32_t *__restrict__ perm,
+                                                                   int32_t *__restrict__ binlist, int64_t nbins)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    setpts_scatter_point<T>(i, phi, theta, sp, bincount, binstart, rec, perm);
-    scatter_dealt(i, (int64_t)gridDim.x * blockDim.x, binlist, nbins);
+    const int64_t j0 = (int64_t)blockIdx.x * kPointsPerBlock + threadIdx.x;
+    double ph[kPointsPerThread], th[kPointsPerThread];
+#pragma unroll
+    for (int q = 0; q < kPointsPerThread; ++q) {
+        const int64_t j = j0 + q * kSetptsThreads;
+        ph[q] = j < sp.n ? phi[j] : 0.0;
+        th[q] = j < sp.n ? theta[j] : 0.0;
+    }
+    setpts_scatter_points<T>(j0, ph, th, sp, bincount, [&](int32_t b) { return binstart[b]; }, rec, perm);
+    scatter_dealt((int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x, binlist, nbins);
 }
 
 template <typename T>
@@ -628,7 +694,7 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_scan_passes(int32_t *__res
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_setpts_scatter_passes(
+__global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter_passes(
     const double *__restrict__ phi, const double *__restrict__ theta, SetptsParams sp,
     int32_t *__restrict__ bincount, const int32_t *__restrict__ lstart, const int4 *__restrict__ stage,
     const int2 *__restrict__ passtot, int npass, int32_t *__restrict__ binstart, int32_t *__restrict__ binlist,
@@ -637,12 +703,14 @@ __global__ __launch_bounds__(256) void k_setpts_scatter_passes(
     __shared__ int2 pre[kMaxScanPasses + 1];  // exclusive prefix of the pass totals
     __shared__ int2 half0;                    // totals of passes 0..63
     const int t = (int)threadIdx.x;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + t;
-    double ph = 0.0, th = 0.0;
+    const int64_t j0 = (int64_t)blockIdx.x * kPointsPerBlock + t;
+    double ph[kPointsPerThread], th[kPointsPerThread];
     int2 inc = t < npass ? passtot[t] : make_int2(0, 0);
-    if (j < sp.n) {
-        ph = phi[j];
-        th = theta[j];
+#pragma unroll
+    for (int q = 0; q < kPointsPerThread; ++q) {
+        const int64_t j = j0 + q * kSetptsThreads;
+        ph[q] = j < sp.n ? phi[j] : 0.0;
+        th[q] = j < sp.n ? theta[j] : 0.0;
     }
     // pass b's totals on thread b: inclusive scan in each of the first two
     // waves, then the second adds the first's total
@@ -665,13 +733,8 @@ __global__ __launch_bounds__(256) void k_setpts_scatter_passes(
         if (t == 0) pre[0] = make_int2(0, 0);
     }
     __syncthreads();
-    if (j < sp.n) {
-        PointRec<T> r;
-        const int32_t bin = split_point<T>(ph, th, sp, r);
-        const int32_t pos = lstart[bin] + pre[bin / kScanPass].x + wave_aggregated_rank_down(bincount, bin);
-        rec[pos] = r;
-        perm[pos] = (int32_t)j;
-    }
+    setpts_scatter_points<T>(j0, ph, th, sp, bincount,
+                             [&](int32_t b) { return lstart[b] + pre[b / kScanPass].x; }, rec, perm);
     // the tables, grid-stride over bins, entries and gather slots
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + t, gstride = (int64_t)gridDim.x * blockDim.x;
     const int n_ne = pre[npass].y;
@@ -717,8 +780,8 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
     // bincount, rowmark, flags[0] and the ticket flags[2] are zero on entry:
     // the plan clears them once and every path below leaves them cleared.
     hipError_t e;
-    const int threads = 256;
-    const int64_t blocks = (sp.n + threads - 1) / threads;
+    const int threads = kSetptsThreads;
+    const int64_t blocks = (sp.n + kPointsPerBlock - 1) / kPointsPerBlock;
     const int64_t fused_blocks = (sp.n + kScanThreads - 1) / kScanThreads;
     const bool fused = sp.n > 0 && nbins <= (int64_t)kScanChunk * kScanThreads && fused_blocks <= kFusedMaxBlocks &&
                        sp.th.nf <= kMaxRowsPerScanThread * kScanThreads;
