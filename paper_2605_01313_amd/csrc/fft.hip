@@ -329,7 +329,7 @@ template <typename T> struct ThetaLoad {
         const bool live = a >= 0 && m < ncols;
         const int ac = live ? a : 0, mc = live ? m : 0;
         const cplx<T> f = fac[ac];
-        const cplx<T> x = cmul(coef[(int64_t)ac * Kp + mc], cplx<T>{f.x * cpm, f.y * cpm});
+        const cplx<T> x = cmul(coef[ac * Kp + mc], cplx<T>{f.x * cpm, f.y * cpm});
         return live ? x : cplx<T>{(T)0, (T)0};
     }
 };
@@ -342,7 +342,7 @@ template <typename T> struct ThetaStore {
     {
         const int m = m0 + b;
         const int l = 2 * q + parity;
-        if (m < ncols && reached[q]) S[(int64_t)l * ncols + m] = v;
+        if (m < ncols && reached[q]) S[l * ncols + m] = v;
     }
 };
 
@@ -408,7 +408,10 @@ constexpr int theta_flag_bytes(int L) { return (L + 15) & ~15; }
 // parities of a batch next to each other, so that the XCD-aware mapping runs
 // them on the same XCD and the second read of the coefficient batch hits its
 // L2.
-template <typename T, int LOGL, int E>
+//
+// FB: the column batch at compile time (0: fp.theta_batch at run time); a
+// fixed batch turns the per-element LDS address arithmetic into constants.
+template <typename T, int LOGL, int E, int FB>
 __device__ inline void theta_body(int item, const cplx<T> *__restrict__ coeffs, const cplx<T> *__restrict__ fac_t,
                                   const T *__restrict__ corr_p, const cplx<T> *__restrict__ tws,
                                   const uint8_t *__restrict__ touched, cplx<T> *__restrict__ S,
@@ -420,40 +423,42 @@ __device__ inline void theta_body(int item, const cplx<T> *__restrict__ coeffs, 
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
     uint8_t *flags = reinterpret_cast<uint8_t *>(tw + tw_lds_len(L));
     cplx<T> *s = reinterpret_cast<cplx<T> *>(flags + theta_flag_bytes(L));
-    const int ntiles = (fp.ncols + fp.theta_batch - 1) / fp.theta_batch;
+    const int B = FB > 0 ? FB : fp.theta_batch;
+    const int logB = FB > 0 ? __builtin_ctz(FB > 0 ? FB : 1) : fp.log_theta_batch;
+    const int ntiles = (fp.ncols + B - 1) / B;
     const int parity = item & 1;
     const int tile = item >> 1;
     const int f = tile / ntiles;
-    const int m0 = (tile - f * ntiles) * fp.theta_batch;
-    const int mt = m0 + ((int)threadIdx.x & (fp.theta_batch - 1));
+    const int m0 = (tile - f * ntiles) * B;
+    const int mt = m0 + ((int)threadIdx.x & (B - 1));
     const T cpm = corr_p[fp.col0 + (mt < fp.ncols ? mt : 0)];
     ThetaLoad<T> ld{coeffs + (int64_t)f * fp.Kt * fp.Kp + fp.col0, fac_t + parity * fp.Kt, cpm, fp.Kt, fp.Kp,
                     fp.ncols, L, m0};
     ThetaStore<T> st{S + (int64_t)f * fp.nft * fp.ncols, flags, fp.ncols, m0, parity};
     ThetaPro<cplx<T>, E> pro{tw, tws, tw_lds_len(L), flags, touched, L, parity};
-    fft_stages<T, LOGL, 0, E, true>(s, fp.log_theta_batch, fp.theta_batch, 1, tw, ld, st, pro);
+    fft_stages<T, LOGL, 0, E, true>(s, logB, B, 1, tw, ld, st, pro);
 }
 
-template <typename T, int LOGL, int E>
+template <typename T, int LOGL, int E, int FB>
 __global__ __launch_bounds__(theta_max_threads<T>()) void k_theta_pass(
     const cplx<T> *__restrict__ coeffs, const cplx<T> *__restrict__ fac_t,
     const T *__restrict__ corr_p, const cplx<T> *__restrict__ tws,
     const uint8_t *__restrict__ touched, cplx<T> *__restrict__ S, FFTParams fp)
 {
-    theta_body<T, LOGL, E>(xcd_remap(blockIdx.x, gridDim.x), coeffs, fac_t, corr_p, tws, touched, S, fp);
+    theta_body<T, LOGL, E, FB>(xcd_remap(blockIdx.x, gridDim.x), coeffs, fac_t, corr_p, tws, touched, S, fp);
 }
 
 // Members of a group class share every shape parameter, so member j owns
 // work items [j * per, (j + 1) * per) of the class grid (per even: the two
 // parities of a batch stay with one member and one XCD).
-template <typename T, int LOGL, int E>
+template <typename T, int LOGL, int E, int FB>
 __global__ __launch_bounds__(theta_max_threads<T>()) void k_theta_group(const ThetaJob *__restrict__ jobs,
                                                                         int per)
 {
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int j = item / per;
     const ThetaJob J = jobs[j];
-    theta_body<T, LOGL, E>(item - j * per, (const cplx<T> *)J.coeffs, (const cplx<T> *)J.fac_t,
+    theta_body<T, LOGL, E, FB>(item - j * per, (const cplx<T> *)J.coeffs, (const cplx<T> *)J.fac_t,
                            (const T *)J.corr_p, (const cplx<T> *)J.tws, J.touched, (cplx<T> *)J.S, J.fp);
 }
 
@@ -562,29 +567,39 @@ __global__ __launch_bounds__(256) void k_phi_group(const PhiJob *__restrict__ jo
 
 constexpr int kElemsPerThread = 16;
 
+// Column batch given a compile-time instance for transforms of length
+// 2^LOGL: the batch the plan takes for the large lengths (0: none).
+template <typename T, int LOGL> constexpr int theta_fixed_batch()
+{
+    if (LOGL == 11) return sizeof(T) == 4 ? 4 : 2;
+    if (LOGL == 10) return sizeof(T) == 4 ? 8 : 4;
+    return 0;
+}
+
 // jobs == nullptr: one plan (the pointer arguments); otherwise n_members
 // members of one group class described by jobs (device memory).
-template <typename T, int LOGL>
-static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const void *fac_t,
+template <typename T, int LOGL, int FB>
+static hipError_t launch_theta_b(const FFTParams &fp, const void *coeffs, const void *fac_t,
                                  const void *corr_p, const void *tws_t, const uint8_t *touched,
                                  void *S, const ThetaJob *jobs, int n_members, hipStream_t s)
 {
     const int L = 1 << LOGL;
     const int ept = fp.theta_ept == 8 ? 8 : kElemsPerThread;
     const int threads = L * fp.theta_batch / ept;
-    if (threads < 1 || threads > theta_max_threads<T>() || threads % fp.theta_batch != 0)
+    if (threads < 1 || threads > theta_max_threads<T>() || threads % fp.theta_batch != 0 ||
+        (FB > 0 && fp.theta_batch != FB))
         return hipErrorInvalidConfiguration;
     const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(L) * fp.theta_batch + tw_lds_len(L)) +
                        theta_flag_bytes(L);
     const int ntiles = (fp.ncols + fp.theta_batch - 1) / fp.theta_batch;
     const int per = 2 * ntiles * fp.n_fields;
     if (jobs) {
-        auto kern = ept == 8 ? k_theta_group<T, LOGL, 8> : k_theta_group<T, LOGL, kElemsPerThread>;
+        auto kern = ept == 8 ? k_theta_group<T, LOGL, 8, FB> : k_theta_group<T, LOGL, kElemsPerThread, FB>;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, dim3(per * n_members), dim3(threads), lds, s, jobs, per);
     } else {
-        auto kern = ept == 8 ? k_theta_pass<T, LOGL, 8> : k_theta_pass<T, LOGL, kElemsPerThread>;
+        auto kern = ept == 8 ? k_theta_pass<T, LOGL, 8, FB> : k_theta_pass<T, LOGL, kElemsPerThread, FB>;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, dim3(per), dim3(threads), lds, s, (const cplx<T> *)coeffs,
@@ -592,6 +607,19 @@ static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const 
                            (cplx<T> *)S, fp);
     }
     return hipGetLastError();
+}
+
+template <typename T, int LOGL>
+static hipError_t launch_theta_t(const FFTParams &fp, const void *coeffs, const void *fac_t,
+                                 const void *corr_p, const void *tws_t, const uint8_t *touched,
+                                 void *S, const ThetaJob *jobs, int n_members, hipStream_t s)
+{
+    constexpr int FB = theta_fixed_batch<T, LOGL>();
+    if constexpr (FB > 0) {
+        if (fp.theta_batch == FB)
+            return launch_theta_b<T, LOGL, FB>(fp, coeffs, fac_t, corr_p, tws_t, touched, S, jobs, n_members, s);
+    }
+    return launch_theta_b<T, LOGL, 0>(fp, coeffs, fac_t, corr_p, tws_t, touched, S, jobs, n_members, s);
 }
 
 template <typename T, int LOGN, bool C2R>
