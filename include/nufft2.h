@@ -30,7 +30,9 @@
  *   nufft2_autotune    kernel width and gather tiles measured for a problem;
  *   nufft2_server_*    a request loop with continuous batching under an HBM
  *                      budget (host buffers in and out);
- *   nufft2_rotate_uv   the rotation Q of section 3 for interpolated (u, v);
+ *   nufft2_setpts_vector  setpts with the rotation Q of section 3 applied
+ *                      to (u, v) inside every exec;
+ *   nufft2_rotate_uv   the same rotation as a separate pass over an output;
  *   nufft2_analysis_*  Grid [0] samples -> exp-form coefficients (section 4),
  *                      with the zonal filter of section 4;
  *   nufft2_pr_*        the partial-regularity expansion of section 4;
@@ -92,7 +94,8 @@ typedef struct {
     int32_t last_hip_error;  /* hipError_t of the last failure, 0 if none */
     int32_t device;
     int32_t hermitian;       /* 1: real-field plan */
-    int32_t reserved;
+    int32_t fields_per_pass; /* fields the gather stages together: fields f
+                                and g share a pass iff f / this == g / this */
 } nufft2_info;
 
 /*
@@ -138,6 +141,31 @@ nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, int64_t n_mod
  */
 nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const double *phi_dev,
                             const double *theta_dev);
+
+/*
+ * nufft2_setpts_vector -- nufft2_setpts for a plan whose fields include the
+ * east and north components (u, v) of a vector field: fields field_u and
+ * field_v.  Every following nufft2_exec returns them in the frame of each
+ * point's arrival point, p u + q v and -q u + p v (section 3: the matrix
+ * Q = [[p, q], [-q, p]], p and q as printed after eq. sslforceb), applied
+ * inside the gather before the values are stored; the other fields are as
+ * with nufft2_setpts.
+ *   phi_a_dev, theta_a_dev  FP64 arrival longitude / colatitude of each
+ *               point (device, n_pts each, the caller's point order), read
+ *               during this call only.
+ *   p and q are computed here, once per point: in FP64 for FP64 plans; for
+ *   FP32 plans the angles are reduced in FP64 and the sines and cosines
+ *   taken in FP32 (about 1e-7 relative).  Undefined for antipodal pairs.
+ *   Applies to both parts of complex outputs.  The plan keeps one (p, q)
+ *   pair per point (2 x 4 or 2 x 8 bytes).  A later nufft2_setpts (or a
+ *   group setpts) drops the rotation.
+ *   Errors: ERR_ARG (null pointers with n_pts > 0, fields equal or out of
+ *   range, or in different gather passes: field / fields_per_pass of
+ *   nufft2_info must agree), ERR_ALLOC, ERR_HIP.
+ */
+nufft2_status nufft2_setpts_vector(nufft2_handle p, int64_t n_pts, const double *phi_dev,
+                                   const double *theta_dev, const double *phi_a_dev,
+                                   const double *theta_a_dev, int32_t field_u, int32_t field_v);
 
 /*
  * nufft2_exec -- evaluate all fields at the current points.

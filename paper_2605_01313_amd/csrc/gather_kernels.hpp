@@ -439,6 +439,28 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
                 }
             }
             if (mine < 0 || upper) continue;
+            if (gp.pq && gp.rot_u >= f0 && gp.rot_u < f0 + fg) {
+                // vector rotation: (u, v) -> (p u + q v, -q u + p v) with the
+                // point's pair from setpts (both fields are in this pass)
+                const T *pq = reinterpret_cast<const T *>(gp.pq) + 2 * ((int64_t)start + base + mine);
+                const T p = pq[0], q = pq[1];
+                E u{}, v{};
+#pragma unroll
+                for (int f = 0; f < FG; ++f) {
+                    if (f0 + f == gp.rot_u) u = acc[f];
+                    if (f0 + f == gp.rot_v) v = acc[f];
+                }
+                E ru{}, rv{};
+                acc_fma(ru, p, u);
+                acc_fma(ru, q, v);
+                acc_fma(rv, -q, u);
+                acc_fma(rv, p, v);
+#pragma unroll
+                for (int f = 0; f < FG; ++f) {
+                    if (f0 + f == gp.rot_u) acc[f] = ru;
+                    if (f0 + f == gp.rot_v) acc[f] = rv;
+                }
+            }
 #pragma unroll
             for (int f = 0; f < FG; ++f) {
                 if (f < fg) {

@@ -338,7 +338,10 @@ NUFFT2_API nufft2_status nufft2_group_setpts(nufft2_group g, const int64_t *n_pt
     if ((e = enter(g)) != hipSuccess || (e = hipGraphLaunch(g->g_setpts, g->stream)) != hipSuccess ||
         (e = leave(g)) != hipSuccess)
         return group_fail(g, e);
-    for (int i = 0; i < n; ++i) g->m[i]->n_pts = n_pts[i];
+    for (int i = 0; i < n; ++i) {
+        g->m[i]->n_pts = n_pts[i];
+        g->m[i]->rot_u = g->m[i]->rot_v = -1;  // group setpts does not rotate
+    }
     return NUFFT2_OK;
 }
 

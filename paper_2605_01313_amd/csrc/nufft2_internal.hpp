@@ -30,6 +30,10 @@ struct SetptsParams {
     int32_t w;
     int32_t nbins_phi;
     int64_t n;
+    // vector rotation: the arrival points (caller's order) and the output
+    // (p, q) pairs in sorted order (plan precision); all null otherwise
+    const double *phi_a, *theta_a;
+    void *pq;
 };
 
 // The bin list of a plan: nbins + 1 int32 (the non-empty bins in order, then
@@ -153,6 +157,11 @@ struct GatherParams {
     // point's centred offset (device table [w][kPolyCoefs], lowest degree
     // first); nullptr otherwise.
     const float *wpoly;
+    // vector rotation: the (p, q) pair of each sorted point (plan
+    // precision) and the fields (u, v) it rotates, in one gather pass;
+    // pq == nullptr: none
+    const void *pq;
+    int32_t rot_u, rot_v;
 };
 constexpr int kPolyCoefs = 9;
 constexpr int kPolyMinW = 7;

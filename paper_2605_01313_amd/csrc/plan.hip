@@ -223,7 +223,7 @@ void free_all(nufft2_plan_s *p)
 {
     void *ptrs[] = {p->corr_t, p->corr_p, p->tw_t,  p->tw_p,  p->twist_t,   p->S,     p->grid,
                     p->bincount, p->binstart, p->binlist, p->rowmark, p->rowtouched, p->flags, p->keyrank,
-                    p->rec,    p->perm,   p->stage, p->passtot, p->lstart, p->c2r, p->wpoly};
+                    p->rec,    p->perm,   p->stage, p->passtot, p->lstart, p->c2r, p->wpoly, p->pq};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     p->c2r = nullptr;
@@ -236,6 +236,9 @@ void free_all(nufft2_plan_s *p)
     p->stage = nullptr;
     p->passtot = nullptr;
     p->lstart = nullptr;
+    p->pq = nullptr;
+    p->pq_cap = 0;
+    p->rot_u = p->rot_v = -1;
 }
 
 bool dev_alloc(nufft2_plan_s *p, void **ptr, size_t bytes)
@@ -725,17 +728,27 @@ GatherParams nufft2::plan_gather_params(const nufft2_plan_s *p)
     gp.real_output = p->real_output;
     gp.real_grid = p->hermitian;
     gp.wpoly = p->wpoly;
+    gp.pq = p->rot_u >= 0 ? p->pq : nullptr;
+    gp.rot_u = p->rot_u;
+    gp.rot_v = p->rot_v;
     return gp;
 }
 
-NUFFT2_API nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const double *phi_dev,
-                                       const double *theta_dev)
+namespace {
+
+// Set-up of the points, with the vector rotation's (p, q) pairs when
+// phi_a != nullptr (pq then has room for n_pts pairs).
+nufft2_status setpts_impl(nufft2_plan_s *p, int64_t n_pts, const double *phi_dev, const double *theta_dev,
+                          const double *phi_a, const double *theta_a)
 {
-    if (!p || n_pts < 0 || n_pts > (int64_t)0x7fffffff) return NUFFT2_ERR_ARG;
-    if (n_pts > 0 && (!phi_dev || !theta_dev)) return NUFFT2_ERR_ARG;
     nufft2_status st = plan_reserve_points(p, n_pts);
     if (st != NUFFT2_OK) return st;
-    const SetptsParams sp = plan_setpts_params(p, n_pts);
+    SetptsParams sp = plan_setpts_params(p, n_pts);
+    if (phi_a) {
+        sp.phi_a = phi_a;
+        sp.theta_a = theta_a;
+        sp.pq = p->pq;
+    }
     const int slot = prof_begin(p, 0);
     hipError_t e = launch_setpts(p->prec, sp, phi_dev, theta_dev, p->bincount, p->binstart, p->binlist, p->nbins,
                                  p->keyrank, p->rowmark, p->rowtouched, p->rec, p->perm, p->flags, p->stage,
@@ -743,6 +756,44 @@ NUFFT2_API nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const dou
     prof_end(p, slot);
     if (e != hipSuccess) return fail_hip(p, e);
     p->n_pts = n_pts;
+    return NUFFT2_OK;
+}
+
+}  // namespace
+
+NUFFT2_API nufft2_status nufft2_setpts(nufft2_handle p, int64_t n_pts, const double *phi_dev,
+                                       const double *theta_dev)
+{
+    if (!p || n_pts < 0 || n_pts > (int64_t)0x7fffffff) return NUFFT2_ERR_ARG;
+    if (n_pts > 0 && (!phi_dev || !theta_dev)) return NUFFT2_ERR_ARG;
+    p->rot_u = p->rot_v = -1;
+    return setpts_impl(p, n_pts, phi_dev, theta_dev, nullptr, nullptr);
+}
+
+NUFFT2_API nufft2_status nufft2_setpts_vector(nufft2_handle p, int64_t n_pts, const double *phi_dev,
+                                              const double *theta_dev, const double *phi_a_dev,
+                                              const double *theta_a_dev, int32_t field_u, int32_t field_v)
+{
+    if (!p || n_pts < 0 || n_pts > (int64_t)0x7fffffff) return NUFFT2_ERR_ARG;
+    if (n_pts > 0 && (!phi_dev || !theta_dev || !phi_a_dev || !theta_a_dev)) return NUFFT2_ERR_ARG;
+    if (field_u < 0 || field_u >= p->F || field_v < 0 || field_v >= p->F || field_u == field_v) return NUFFT2_ERR_ARG;
+    // the gather rotates the pair in its epilogue: both fields in one pass
+    if (field_u / p->fields_per_pass != field_v / p->fields_per_pass) return NUFFT2_ERR_ARG;
+    p->rot_u = p->rot_v = -1;
+    if (n_pts > p->pq_cap) {
+        hipError_t e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return fail_hip(p, e);
+        if (p->pq) (void)hipFree(p->pq);
+        p->ws_bytes -= 2 * p->rsize * (size_t)p->pq_cap;
+        p->pq = nullptr;
+        p->pq_cap = 0;
+        if (!dev_alloc(p, &p->pq, 2 * p->rsize * (size_t)n_pts)) return NUFFT2_ERR_ALLOC;
+        p->pq_cap = n_pts;
+    }
+    nufft2_status st = setpts_impl(p, n_pts, phi_dev, theta_dev, n_pts > 0 ? phi_a_dev : nullptr, theta_a_dev);
+    if (st != NUFFT2_OK) return st;
+    p->rot_u = field_u;
+    p->rot_v = field_v;
     return NUFFT2_OK;
 }
 
@@ -873,6 +924,7 @@ NUFFT2_API nufft2_status nufft2_get_info(nufft2_handle p, nufft2_info *info)
     info->last_hip_error = (int32_t)p->last_err;
     info->device = p->device;
     info->hermitian = p->hermitian;
+    info->fields_per_pass = p->fields_per_pass;
     return NUFFT2_OK;
 }
 

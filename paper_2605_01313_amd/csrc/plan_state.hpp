@@ -50,6 +50,12 @@ struct nufft2_plan_s {
     int2 *keyrank = nullptr;
     void *rec = nullptr;
     int32_t *perm = nullptr;
+    // vector rotation (nufft2_setpts_vector): the (p, q) pair of each sorted
+    // point (plan precision, pq_cap points) and the rotated fields (u, v);
+    // rot_u < 0: no rotation (plain nufft2_setpts, group setpts)
+    void *pq = nullptr;
+    int64_t pq_cap = 0;
+    int32_t rot_u = -1, rot_v = -1;
 
     int64_t n_pts = -1;
     size_t ws_bytes = 0;

@@ -123,6 +123,39 @@ __device__ inline int32_t split_point(double ph, double th, const SetptsParams &
     return (r.it / sp.th.tile) * sp.nbins_phi + r.ip / sp.ph.tile;
 }
 
+// The pair (p, q) of the matrix Q that takes a vector at departure point D
+// to the local frame of arrival point A (section 3, after the semi-implicit
+// forcing equations):
+//   p = (sin tA sin tD + (1 + cos tA cos tD) cos(pA - pD)) / (1 + cos eta),
+//   q = (cos tA + cos tD) sin(pA - pD) / (1 + cos eta),
+//   cos eta = sin tA sin tD cos(pA - pD) + cos tA cos tD.
+// FP64 plans evaluate it in FP64.  FP32 plans reduce the angles in FP64 and
+// evaluate the trigonometric functions in FP32 (about 1e-7 relative in p
+// and q, an order below the plan's tolerance).  Undefined for antipodal
+// pairs (cos eta = -1).
+__device__ inline void rotation_pair(double pa, double ta, double pd, double td, double *out)
+{
+    double sa, ca, sd, cd, sp, cp;
+    sincos(ta, &sa, &ca);
+    sincos(td, &sd, &cd);
+    sincos(pa - pd, &sp, &cp);
+    const double den = 1.0 + (sa * sd * cp + ca * cd);
+    out[0] = (sa * sd + (1.0 + ca * cd) * cp) / den;
+    out[1] = (ca + cd) * sp / den;
+}
+__device__ inline void rotation_pair(double pa, double ta, double pd, double td, float *out)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    auto reduce = [&](double x) { return (float)(x - two_pi * rint(x * (1.0 / two_pi))); };
+    float sa, ca, sd, cd, sp, cp;
+    sincosf(reduce(ta), &sa, &ca);
+    sincosf(reduce(td), &sd, &cd);
+    sincosf(reduce(pa - pd), &sp, &cp);
+    const float den = 1.0f + (sa * sd * cp + ca * cd);
+    out[0] = (sa * sd + (1.0f + ca * cd) * cp) / den;
+    out[1] = (ca + cd) * sp / den;
+}
+
 // Point j with coordinates (ph, th) (a thread of a 256-thread block; the
 // caller skips j >= n).  KR: also write the point's (bin, rank) for the
 // fused scan + scatter.
@@ -468,12 +501,22 @@ __device__ inline void setpts_scatter_point(int64_t j, const double *__restrict_
 // already loaded): every point's split and lane grouping first, then all
 // their count decrements, so that the atomics' round trips overlap; each
 // point then goes to start(bin) + its rank.
-template <typename T, class Start>
+// ROT (the vector rotation, sp.pq): each point's (p, q) pair goes to
+// pq[pos] as well, from its arrival point.
+template <typename T, bool ROT, class Start>
 __device__ inline void setpts_scatter_points(int64_t j0, const double (&ph)[kPointsPerThread],
                                              const double (&th)[kPointsPerThread], const SetptsParams &sp,
                                              int32_t *__restrict__ bincount, const Start &start,
                                              PointRec<T> *__restrict__ rec, int32_t *__restrict__ perm)
 {
+    double pa[kPointsPerThread], ta[kPointsPerThread];
+#pragma unroll
+    for (int q = 0; q < kPointsPerThread; ++q) {
+        const int64_t j = j0 + q * kSetptsThreads;
+        const bool load = ROT && j < sp.n;
+        pa[q] = load ? sp.phi_a[j] : 0.0;
+        ta[q] = load ? sp.theta_a[j] : 0.0;
+    }
     PointRec<T> r[kPointsPerThread];
     int32_t bin[kPointsPerThread], base[kPointsPerThread];
     WaveGroup g[kPointsPerThread];
@@ -498,6 +541,7 @@ __device__ inline void setpts_scatter_points(int64_t j0, const double (&ph)[kPoi
             const int32_t pos = start(bin[q]) + __shfl(base[q], g[q].leader, 64) + g[q].offset;
             rec[pos] = r[q];
             perm[pos] = (int32_t)j;
+            if (ROT) rotation_pair(pa[q], ta[q], ph[q], th[q], reinterpret_cast<T *>(sp.pq) + 2 * (int64_t)pos);
         }
     }
 }
@@ -520,7 +564,7 @@ __device__ inline void scatter_dealt(int64_t i, int64_t n, int32_t *__restrict__
     }
 }
 
-template <typename T>
+template <typename T, bool ROT>
 __global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter(const double *__restrict__ phi,
                                                                    const double *__restrict__ theta,
                                                                    SetptsParams sp,
@@ -538,7 +582,7 @@ __global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter(const double 
         ph[q] = j < sp.n ? phi[j] : 0.0;
         th[q] = j < sp.n ? theta[j] : 0.0;
     }
-    setpts_scatter_points<T>(j0, ph, th, sp, bincount, [&](int32_t b) { return binstart[b]; }, rec, perm);
+    setpts_scatter_points<T, ROT>(j0, ph, th, sp, bincount, [&](int32_t b) { return binstart[b]; }, rec, perm);
     scatter_dealt((int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x, binlist, nbins);
 }
 
@@ -565,7 +609,7 @@ __global__ __launch_bounds__(256) void k_setpts_scatter_group(const SetptsJob *_
 // single-workgroup kernel fewer than bin count -> scan -> scatter.
 constexpr int kFusedMaxBlocks = 256;
 
-template <typename T>
+template <typename T, bool ROT>
 __global__ __launch_bounds__(kScanThreads) void k_setpts_scatter_scan(
     const double *__restrict__ phi, const double *__restrict__ theta, SetptsParams sp,
     int32_t *__restrict__ bincount, int32_t *__restrict__ binstart, int32_t *__restrict__ binlist, int nbins,
@@ -631,6 +675,7 @@ __global__ __launch_bounds__(kScanThreads) void k_setpts_scatter_scan(
         const int32_t pos = stage[scan_slot(kr.x)] + kr.y;
         rec[pos] = r;
         perm[pos] = (int32_t)j;
+        if (ROT) rotation_pair(sp.phi_a[j], sp.theta_a[j], ph, th, reinterpret_cast<T *>(sp.pq) + 2 * (int64_t)pos);
     }
     if (rows_wg) {
         // with one workgroup it also wrote the per-slot table from cmp above
@@ -693,7 +738,7 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_scan_passes(int32_t *__res
     if (rows_wg) reached_rows(mk, flag0, reinterpret_cast<uint8_t *>(stg), rowmark, rowtouched, nft, w, flags);
 }
 
-template <typename T>
+template <typename T, bool ROT>
 __global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter_passes(
     const double *__restrict__ phi, const double *__restrict__ theta, SetptsParams sp,
     int32_t *__restrict__ bincount, const int32_t *__restrict__ lstart, const int4 *__restrict__ stage,
@@ -733,7 +778,7 @@ __global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter_passes(
         if (t == 0) pre[0] = make_int2(0, 0);
     }
     __syncthreads();
-    setpts_scatter_points<T>(j0, ph, th, sp, bincount,
+    setpts_scatter_points<T, ROT>(j0, ph, th, sp, bincount,
                              [&](int32_t b) { return lstart[b] + pre[b / kScanPass].x; }, rec, perm);
     // the tables, grid-stride over bins, entries and gather slots
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + t, gstride = (int64_t)gridDim.x * blockDim.x;
@@ -771,11 +816,12 @@ __global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter_passes(
     }
 }
 
-hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, const double *theta,
-                         int32_t *bincount, int32_t *binstart, int32_t *binlist, int64_t nbins,
-                         int2 *keyrank,
-                         uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
-                         int32_t *flags, int4 *stage, int2 *passtot, int32_t *lstart, hipStream_t s)
+// The launches of one precision; ROT: with the vector rotation's pairs.
+template <typename T, bool ROT>
+static hipError_t launch_setpts_t(const SetptsParams &sp, const double *phi, const double *theta,
+                                  int32_t *bincount, int32_t *binstart, int32_t *binlist, int64_t nbins,
+                                  int2 *keyrank, uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
+                                  int32_t *flags, int4 *stage, int2 *passtot, int32_t *lstart, hipStream_t s)
 {
     // bincount, rowmark, flags[0] and the ticket flags[2] are zero on entry:
     // the plan clears them once and every path below leaves them cleared.
@@ -785,22 +831,17 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
     const int64_t fused_blocks = (sp.n + kScanThreads - 1) / kScanThreads;
     const bool fused = sp.n > 0 && nbins <= (int64_t)kScanChunk * kScanThreads && fused_blocks <= kFusedMaxBlocks &&
                        sp.th.nf <= kMaxRowsPerScanThread * kScanThreads;
+    PointRec<T> *r = (PointRec<T> *)rec;
     if (sp.n > 0) {
-        auto kern = prec == 1 ? (fused ? k_setpts_bin<float, true> : k_setpts_bin<float, false>)
-                              : (fused ? k_setpts_bin<double, true> : k_setpts_bin<double, false>);
+        auto kern = fused ? k_setpts_bin<T, true> : k_setpts_bin<T, false>;
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), 0, s, phi, theta, sp, bincount, keyrank,
                            rowmark, flags);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (fused) {
-        if (prec == 1)
-            hipLaunchKernelGGL(k_setpts_scatter_scan<float>, dim3((unsigned)fused_blocks), dim3(kScanThreads), 0, s,
-                               phi, theta, sp, bincount, binstart, binlist, (int)nbins, keyrank, rowmark,
-                               rowtouched, sp.th.nf, flags, (PointRec<float> *)rec, perm);
-        else
-            hipLaunchKernelGGL(k_setpts_scatter_scan<double>, dim3((unsigned)fused_blocks), dim3(kScanThreads), 0, s,
-                               phi, theta, sp, bincount, binstart, binlist, (int)nbins, keyrank, rowmark,
-                               rowtouched, sp.th.nf, flags, (PointRec<double> *)rec, perm);
+        hipLaunchKernelGGL((k_setpts_scatter_scan<T, ROT>), dim3((unsigned)fused_blocks), dim3(kScanThreads), 0, s,
+                           phi, theta, sp, bincount, binstart, binlist, (int)nbins, keyrank, rowmark, rowtouched,
+                           sp.th.nf, flags, r, perm);
         return hipGetLastError();
     }
     const int64_t npass = (nbins + kScanPass - 1) / kScanPass;
@@ -809,29 +850,37 @@ hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, co
         hipLaunchKernelGGL(k_bin_scan_passes, dim3((unsigned)npass), dim3(kScanThreads), 0, s, bincount, nbins,
                            lstart, stage, passtot, rowmark, rowtouched, sp.th.nf, sp.w, flags);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (prec == 1)
-            hipLaunchKernelGGL(k_setpts_scatter_passes<float>, dim3((unsigned)blocks), dim3(threads), 0, s, phi, theta,
-                               sp, bincount, lstart, stage, passtot, (int)npass, binstart, binlist, nbins,
-                               (PointRec<float> *)rec, perm);
-        else
-            hipLaunchKernelGGL(k_setpts_scatter_passes<double>, dim3((unsigned)blocks), dim3(threads), 0, s, phi,
-                               theta, sp, bincount, lstart, stage, passtot, (int)npass, binstart, binlist, nbins,
-                               (PointRec<double> *)rec, perm);
+        hipLaunchKernelGGL((k_setpts_scatter_passes<T, ROT>), dim3((unsigned)blocks), dim3(threads), 0, s, phi, theta,
+                           sp, bincount, lstart, stage, passtot, (int)npass, binstart, binlist, nbins, r, perm);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kScanThreads), 0, s, bincount, binstart, binlist, nbins,
                        rowmark, rowtouched, sp.th.nf, sp.w, flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (sp.n > 0) {
-        if (prec == 1)
-            hipLaunchKernelGGL(k_setpts_scatter<float>, dim3((unsigned)blocks), dim3(threads), 0, s,
-                               phi, theta, sp, bincount, binstart, (PointRec<float> *)rec, perm, binlist, nbins);
-        else
-            hipLaunchKernelGGL(k_setpts_scatter<double>, dim3((unsigned)blocks), dim3(threads), 0, s,
-                               phi, theta, sp, bincount, binstart, (PointRec<double> *)rec, perm, binlist, nbins);
+        hipLaunchKernelGGL((k_setpts_scatter<T, ROT>), dim3((unsigned)blocks), dim3(threads), 0, s, phi, theta, sp,
+                           bincount, binstart, r, perm, binlist, nbins);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, const double *theta,
+                         int32_t *bincount, int32_t *binstart, int32_t *binlist, int64_t nbins,
+                         int2 *keyrank,
+                         uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
+                         int32_t *flags, int4 *stage, int2 *passtot, int32_t *lstart, hipStream_t s)
+{
+    const bool rot = sp.pq != nullptr;
+    if (prec == 1)
+        return rot ? launch_setpts_t<float, true>(sp, phi, theta, bincount, binstart, binlist, nbins, keyrank, rowmark,
+                                                  rowtouched, rec, perm, flags, stage, passtot, lstart, s)
+                   : launch_setpts_t<float, false>(sp, phi, theta, bincount, binstart, binlist, nbins, keyrank, rowmark,
+                                                   rowtouched, rec, perm, flags, stage, passtot, lstart, s);
+    return rot ? launch_setpts_t<double, true>(sp, phi, theta, bincount, binstart, binlist, nbins, keyrank, rowmark,
+                                               rowtouched, rec, perm, flags, stage, passtot, lstart, s)
+               : launch_setpts_t<double, false>(sp, phi, theta, bincount, binstart, binlist, nbins, keyrank, rowmark,
+                                                rowtouched, rec, perm, flags, stage, passtot, lstart, s);
 }
 
 hipError_t launch_setpts_group(int prec, const SetptsJob *jobs, int n_members, const int32_t *job_of_block,

@@ -28,7 +28,7 @@ NUFFT2_FP32 = 1
 NUFFT2_FP64 = 2
 
 EXPORTED = (
-    "nufft2_plan", "nufft2_setpts", "nufft2_exec", "nufft2_destroy", "nufft2_strerror",
+    "nufft2_plan", "nufft2_setpts", "nufft2_setpts_vector", "nufft2_exec", "nufft2_destroy", "nufft2_strerror",
     "nufft2_get_info", "nufft2_check", "nufft2_set_stream", "nufft2_kernel_params",
     "nufft2_kernel_correction", "nufft2_debug_buffer", "nufft2_profile_enable",
     "nufft2_profile_read", "nufft2_group_create", "nufft2_group_setpts", "nufft2_group_exec",
@@ -57,10 +57,10 @@ class nufft2_info(ctypes.Structure):
                 ("tile_theta", ctypes.c_int32), ("tile_phi", ctypes.c_int32),
                 ("n_bins", ctypes.c_int64), ("n_pts", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_uint64), ("last_hip_error", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("hermitian", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("hermitian", ctypes.c_int32), ("fields_per_pass", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class nufft2_group_info(ctypes.Structure):
@@ -150,6 +150,7 @@ def _load():
         "nufft2_analysis_exec": [H, vp, vp],
         "nufft2_analysis_destroy": [H],
         "nufft2_rotate_uv": [H, vp, i32, i32, vp, vp, vp, vp],
+        "nufft2_setpts_vector": [H, i64, vp, vp, vp, vp, i32, i32],
         "nufft2_analysis_set_zonal_filter": [H, i32],
         "nufft2_pr_plan": [i32, i64, i64, i32, vp, ctypes.POINTER(H)],
         "nufft2_pr_project": [H, vp, vp],
@@ -204,6 +205,12 @@ def nufft2_plan(prec, n_modes_theta, n_modes_phi, n_fields, eps, opts=None, stre
 def nufft2_setpts(handle, n_pts, phi_ptr, theta_ptr):
     return _lib.nufft2_setpts(handle, int(n_pts), ctypes.c_void_p(phi_ptr or None),
                               ctypes.c_void_p(theta_ptr or None))
+
+
+def nufft2_setpts_vector(handle, n_pts, phi_ptr, theta_ptr, phi_a_ptr, theta_a_ptr, field_u, field_v):
+    P = lambda x: ctypes.c_void_p(x or None)
+    return _lib.nufft2_setpts_vector(handle, int(n_pts), P(phi_ptr), P(theta_ptr), P(phi_a_ptr), P(theta_a_ptr),
+                                     int(field_u), int(field_v))
 
 
 def nufft2_exec(handle, coeffs_ptr, out_ptr):
@@ -508,6 +515,20 @@ class Plan:
         _check(nufft2_setpts(self.handle, n, phi.data_ptr() if n else 0,
                              theta.data_ptr() if n else 0), "nufft2_setpts")
         self._pts = (phi, theta)   # keep alive until the stream has consumed them
+        self.n_pts = n
+
+    def setpts_vector(self, phi, theta, phi_a, theta_a, field_u, field_v):
+        """setpts whose following execs return fields (u, v) rotated into each
+        point's arrival frame (section 3's matrix Q, inside the gather)."""
+        n = self._check_points(phi, theta)
+        for x in (phi_a, theta_a):
+            if x.dtype != self._torch.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != n:
+                raise TypeError("arrival points must be contiguous float64 device tensors of n_pts entries")
+        P = (lambda x: x.data_ptr() if n else 0)
+        _check(nufft2_setpts_vector(self.handle, n, P(phi), P(theta), P(phi_a), P(theta_a), field_u, field_v),
+               "nufft2_setpts_vector")
+        self._pts = (phi, theta)
+        self._arrival = (phi_a, theta_a)   # read by this call's kernels
         self.n_pts = n
 
     def exec(self, coeffs, out=None):
