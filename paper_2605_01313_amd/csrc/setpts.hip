@@ -180,15 +180,15 @@ __device__ inline void setpts_bin_point(int64_t j, double ph, double th, const S
     else wave_aggregated_count(bincount, bin);
 }
 
-// Points per thread of the bin and scatter kernels of a single plan: a
-// thread's points (256 apart, so that each wave still takes consecutive
+// Points per thread (PPT) of the bin and scatter kernels of a single plan:
+// a thread's points (256 apart, so that each wave still takes consecutive
 // points) are loaded together, which keeps several loads in flight per
-// thread.
-constexpr int kPointsPerThread = 4;
+// thread.  Four per thread from kManyPoints points on (2048+ workgroups);
+// below that one, so that smaller plans still spread over every CU.
 constexpr int kSetptsThreads = 256;
-constexpr int64_t kPointsPerBlock = (int64_t)kPointsPerThread * kSetptsThreads;
+constexpr int64_t kManyPoints = int64_t(1) << 21;
 
-template <typename T, bool KR>
+template <typename T, bool KR, int PPT>
 __global__ __launch_bounds__(kSetptsThreads) void k_setpts_bin(const double *__restrict__ phi,
                                                                const double *__restrict__ theta, SetptsParams sp,
                                                                int32_t *__restrict__ bincount,
@@ -196,16 +196,16 @@ __global__ __launch_bounds__(kSetptsThreads) void k_setpts_bin(const double *__r
                                                                uint8_t *__restrict__ rowmark,
                                                                int32_t *__restrict__ flags)
 {
-    const int64_t j0 = (int64_t)blockIdx.x * kPointsPerBlock + threadIdx.x;
-    double ph[kPointsPerThread], th[kPointsPerThread];
+    const int64_t j0 = (int64_t)blockIdx.x * (PPT * kSetptsThreads) + threadIdx.x;
+    double ph[PPT], th[PPT];
 #pragma unroll
-    for (int q = 0; q < kPointsPerThread; ++q) {
+    for (int q = 0; q < PPT; ++q) {
         const int64_t j = j0 + q * kSetptsThreads;
         ph[q] = j < sp.n ? phi[j] : 0.0;
         th[q] = j < sp.n ? theta[j] : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < kPointsPerThread; ++q) {
+    for (int q = 0; q < PPT; ++q) {
         const int64_t j = j0 + q * kSetptsThreads;
         if (j < sp.n) setpts_bin_point<T, KR>(j, ph[q], th[q], sp, bincount, keyrank, rowmark, flags);
     }
@@ -497,31 +497,31 @@ __device__ inline void setpts_scatter_point(int64_t j, const double *__restrict_
     }
 }
 
-// kPointsPerThread points of one thread (j0, j0 + 256, ...; coordinates
+// PPT points of one thread (j0, j0 + 256, ...; coordinates
 // already loaded): every point's split and lane grouping first, then all
 // their count decrements, so that the atomics' round trips overlap; each
 // point then goes to start(bin) + its rank.
 // ROT (the vector rotation, sp.pq): each point's (p, q) pair goes to
 // pq[pos] as well, from its arrival point.
-template <typename T, bool ROT, class Start>
-__device__ inline void setpts_scatter_points(int64_t j0, const double (&ph)[kPointsPerThread],
-                                             const double (&th)[kPointsPerThread], const SetptsParams &sp,
+template <typename T, bool ROT, int PPT, class Start>
+__device__ inline void setpts_scatter_points(int64_t j0, const double (&ph)[PPT],
+                                             const double (&th)[PPT], const SetptsParams &sp,
                                              int32_t *__restrict__ bincount, const Start &start,
                                              PointRec<T> *__restrict__ rec, int32_t *__restrict__ perm)
 {
-    double pa[kPointsPerThread], ta[kPointsPerThread];
+    double pa[PPT], ta[PPT];
 #pragma unroll
-    for (int q = 0; q < kPointsPerThread; ++q) {
+    for (int q = 0; q < PPT; ++q) {
         const int64_t j = j0 + q * kSetptsThreads;
         const bool load = ROT && j < sp.n;
         pa[q] = load ? sp.phi_a[j] : 0.0;
         ta[q] = load ? sp.theta_a[j] : 0.0;
     }
-    PointRec<T> r[kPointsPerThread];
-    int32_t bin[kPointsPerThread], base[kPointsPerThread];
-    WaveGroup g[kPointsPerThread];
+    PointRec<T> r[PPT];
+    int32_t bin[PPT], base[PPT];
+    WaveGroup g[PPT];
 #pragma unroll
-    for (int q = 0; q < kPointsPerThread; ++q) {
+    for (int q = 0; q < PPT; ++q) {
         bin[q] = 0;
         base[q] = 0;
         g[q] = WaveGroup{0, 0, 0};
@@ -531,11 +531,11 @@ __device__ inline void setpts_scatter_points(int64_t j0, const double (&ph)[kPoi
         }
     }
 #pragma unroll
-    for (int q = 0; q < kPointsPerThread; ++q)
+    for (int q = 0; q < PPT; ++q)
         if (j0 + q * kSetptsThreads < sp.n && g[q].count > 0)
             base[q] = atomicSub(&bincount[bin[q]], g[q].count) - g[q].count;
 #pragma unroll
-    for (int q = 0; q < kPointsPerThread; ++q) {
+    for (int q = 0; q < PPT; ++q) {
         const int64_t j = j0 + q * kSetptsThreads;
         if (j < sp.n) {
             const int32_t pos = start(bin[q]) + __shfl(base[q], g[q].leader, 64) + g[q].offset;
@@ -564,7 +564,7 @@ __device__ inline void scatter_dealt(int64_t i, int64_t n, int32_t *__restrict__
     }
 }
 
-template <typename T, bool ROT>
+template <typename T, bool ROT, int PPT>
 __global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter(const double *__restrict__ phi,
                                                                    const double *__restrict__ theta,
                                                                    SetptsParams sp,
@@ -574,15 +574,15 @@ __global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter(const double 
                                                                    int32_t *__restrict__ perm,
                                                                    int32_t *__restrict__ binlist, int64_t nbins)
 {
-    const int64_t j0 = (int64_t)blockIdx.x * kPointsPerBlock + threadIdx.x;
-    double ph[kPointsPerThread], th[kPointsPerThread];
+    const int64_t j0 = (int64_t)blockIdx.x * (PPT * kSetptsThreads) + threadIdx.x;
+    double ph[PPT], th[PPT];
 #pragma unroll
-    for (int q = 0; q < kPointsPerThread; ++q) {
+    for (int q = 0; q < PPT; ++q) {
         const int64_t j = j0 + q * kSetptsThreads;
         ph[q] = j < sp.n ? phi[j] : 0.0;
         th[q] = j < sp.n ? theta[j] : 0.0;
     }
-    setpts_scatter_points<T, ROT>(j0, ph, th, sp, bincount, [&](int32_t b) { return binstart[b]; }, rec, perm);
+    setpts_scatter_points<T, ROT, PPT>(j0, ph, th, sp, bincount, [&](int32_t b) { return binstart[b]; }, rec, perm);
     scatter_dealt((int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x, binlist, nbins);
 }
 
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_scan_passes(int32_t *__res
     if (rows_wg) reached_rows(mk, flag0, reinterpret_cast<uint8_t *>(stg), rowmark, rowtouched, nft, w, flags);
 }
 
-template <typename T, bool ROT>
+template <typename T, bool ROT, int PPT>
 __global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter_passes(
     const double *__restrict__ phi, const double *__restrict__ theta, SetptsParams sp,
     int32_t *__restrict__ bincount, const int32_t *__restrict__ lstart, const int4 *__restrict__ stage,
@@ -748,11 +748,11 @@ __global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter_passes(
     __shared__ int2 pre[kMaxScanPasses + 1];  // exclusive prefix of the pass totals
     __shared__ int2 half0;                    // totals of passes 0..63
     const int t = (int)threadIdx.x;
-    const int64_t j0 = (int64_t)blockIdx.x * kPointsPerBlock + t;
-    double ph[kPointsPerThread], th[kPointsPerThread];
+    const int64_t j0 = (int64_t)blockIdx.x * (PPT * kSetptsThreads) + t;
+    double ph[PPT], th[PPT];
     int2 inc = t < npass ? passtot[t] : make_int2(0, 0);
 #pragma unroll
-    for (int q = 0; q < kPointsPerThread; ++q) {
+    for (int q = 0; q < PPT; ++q) {
         const int64_t j = j0 + q * kSetptsThreads;
         ph[q] = j < sp.n ? phi[j] : 0.0;
         th[q] = j < sp.n ? theta[j] : 0.0;
@@ -778,7 +778,7 @@ __global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter_passes(
         if (t == 0) pre[0] = make_int2(0, 0);
     }
     __syncthreads();
-    setpts_scatter_points<T, ROT>(j0, ph, th, sp, bincount,
+    setpts_scatter_points<T, ROT, PPT>(j0, ph, th, sp, bincount,
                              [&](int32_t b) { return lstart[b] + pre[b / kScanPass].x; }, rec, perm);
     // the tables, grid-stride over bins, entries and gather slots
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + t, gstride = (int64_t)gridDim.x * blockDim.x;
@@ -816,9 +816,10 @@ __global__ __launch_bounds__(kSetptsThreads) void k_setpts_scatter_passes(
     }
 }
 
-// The launches of one precision; ROT: with the vector rotation's pairs.
-template <typename T, bool ROT>
-static hipError_t launch_setpts_t(const SetptsParams &sp, const double *phi, const double *theta,
+// The launches of one precision; ROT: with the vector rotation's pairs;
+// PPT: points per thread of the bin and scatter kernels.
+template <typename T, bool ROT, int PPT>
+static hipError_t launch_setpts_b(const SetptsParams &sp, const double *phi, const double *theta,
                                   int32_t *bincount, int32_t *binstart, int32_t *binlist, int64_t nbins,
                                   int2 *keyrank, uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
                                   int32_t *flags, int4 *stage, int2 *passtot, int32_t *lstart, hipStream_t s)
@@ -827,13 +828,13 @@ static hipError_t launch_setpts_t(const SetptsParams &sp, const double *phi, con
     // the plan clears them once and every path below leaves them cleared.
     hipError_t e;
     const int threads = kSetptsThreads;
-    const int64_t blocks = (sp.n + kPointsPerBlock - 1) / kPointsPerBlock;
+    const int64_t blocks = (sp.n + PPT * kSetptsThreads - 1) / (PPT * kSetptsThreads);
     const int64_t fused_blocks = (sp.n + kScanThreads - 1) / kScanThreads;
     const bool fused = sp.n > 0 && nbins <= (int64_t)kScanChunk * kScanThreads && fused_blocks <= kFusedMaxBlocks &&
                        sp.th.nf <= kMaxRowsPerScanThread * kScanThreads;
     PointRec<T> *r = (PointRec<T> *)rec;
     if (sp.n > 0) {
-        auto kern = fused ? k_setpts_bin<T, true> : k_setpts_bin<T, false>;
+        auto kern = fused ? k_setpts_bin<T, true, PPT> : k_setpts_bin<T, false, PPT>;
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), 0, s, phi, theta, sp, bincount, keyrank,
                            rowmark, flags);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -850,7 +851,7 @@ static hipError_t launch_setpts_t(const SetptsParams &sp, const double *phi, con
         hipLaunchKernelGGL(k_bin_scan_passes, dim3((unsigned)npass), dim3(kScanThreads), 0, s, bincount, nbins,
                            lstart, stage, passtot, rowmark, rowtouched, sp.th.nf, sp.w, flags);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_setpts_scatter_passes<T, ROT>), dim3((unsigned)blocks), dim3(threads), 0, s, phi, theta,
+        hipLaunchKernelGGL((k_setpts_scatter_passes<T, ROT, PPT>), dim3((unsigned)blocks), dim3(threads), 0, s, phi, theta,
                            sp, bincount, lstart, stage, passtot, (int)npass, binstart, binlist, nbins, r, perm);
         return hipGetLastError();
     }
@@ -858,11 +859,24 @@ static hipError_t launch_setpts_t(const SetptsParams &sp, const double *phi, con
                        rowmark, rowtouched, sp.th.nf, sp.w, flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (sp.n > 0) {
-        hipLaunchKernelGGL((k_setpts_scatter<T, ROT>), dim3((unsigned)blocks), dim3(threads), 0, s, phi, theta, sp,
+        hipLaunchKernelGGL((k_setpts_scatter<T, ROT, PPT>), dim3((unsigned)blocks), dim3(threads), 0, s, phi, theta, sp,
                            bincount, binstart, r, perm, binlist, nbins);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <typename T, bool ROT>
+static hipError_t launch_setpts_t(const SetptsParams &sp, const double *phi, const double *theta,
+                                  int32_t *bincount, int32_t *binstart, int32_t *binlist, int64_t nbins,
+                                  int2 *keyrank, uint8_t *rowmark, uint8_t *rowtouched, void *rec, int32_t *perm,
+                                  int32_t *flags, int4 *stage, int2 *passtot, int32_t *lstart, hipStream_t s)
+{
+    if (sp.n >= kManyPoints)
+        return launch_setpts_b<T, ROT, 4>(sp, phi, theta, bincount, binstart, binlist, nbins, keyrank, rowmark,
+                                          rowtouched, rec, perm, flags, stage, passtot, lstart, s);
+    return launch_setpts_b<T, ROT, 1>(sp, phi, theta, bincount, binstart, binlist, nbins, keyrank, rowmark,
+                                      rowtouched, rec, perm, flags, stage, passtot, lstart, s);
 }
 
 hipError_t launch_setpts(int prec, const SetptsParams &sp, const double *phi, const double *theta,
