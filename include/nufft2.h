@@ -318,12 +318,14 @@ nufft2_status nufft2_group_get_info(nufft2_group g, nufft2_group_info *info);
  * nufft2_autotune -- choose the kernel width and gather tiles for a problem
  * (the same shape, tolerance and point distribution as the caller's).
  *   Width: the rule w0 = ceil(log10(1/eps)) + 1 is a guide, not the answer:
- *   for w in w0 - 1, w0, w0 + 1 the tuner measures the relative l2 error of
- *   a plan of width w against an FP64 plan of width min(16, w0 + 3) on the
- *   first min(n_pts, 16384) of the caller's points and one field of
- *   pseudo-random coefficients with a flat spectrum (the hardest case for a
- *   given tolerance), and keeps the smallest w whose error is <= eps (w0 + 1
- *   if none is).
+ *   for w = w0 - 1, w0, ... below the reference width min(16, w0 + 3) the
+ *   tuner measures the relative l2 error of a plan of width w against an
+ *   FP64 plan of the reference width on the first min(n_pts, 16384) of the
+ *   caller's points and one field of pseudo-random coefficients with a flat
+ *   spectrum (the hardest case for a given tolerance), and keeps the
+ *   smallest w whose error is <= eps.  If none is (eps at the precision's
+ *   floor), it returns ERR_EPS_RANGE with result->w and result->err of the
+ *   widest candidate, and writes nothing to the cache.
  *   Tiles: for that width it times setpts + exec of n_fields fields on all
  *   n_pts points (HIP events on `stream`, median of 3 after a warm-up) for
  *   each gather tile shape in a fixed candidate list that fits the LDS, and
@@ -336,8 +338,8 @@ nufft2_status nufft2_group_get_info(nufft2_group g, nufft2_group_info *info);
  *   result (may be NULL) the measured error, time and whether the cache
  *   answered.  The tuner creates and destroys its own plans and buffers on
  *   the current device and synchronises `stream`.
- *   Errors: as nufft2_plan for the arguments (n_pts must be >= 1), ERR_ALLOC,
- *   ERR_HIP.
+ *   Errors: as nufft2_plan for the arguments (n_pts must be >= 1),
+ *   ERR_EPS_RANGE (no width reaches eps, see above), ERR_ALLOC, ERR_HIP.
  */
 typedef struct {
     int32_t w, tile_theta, tile_phi;

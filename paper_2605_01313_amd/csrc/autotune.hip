@@ -216,10 +216,13 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
             (e = hipMemcpy(ref.data(), d_ref, ref.size() * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)
             return NUFFT2_ERR_HIP;
     }
-    // width: smallest candidate within eps on the probe
+    // width: smallest candidate within eps on the probe, widening up to the
+    // reference's width (beyond it the reference cannot judge)
     int w_best = -1;
     double err_best = 0;
-    for (int w = std::max(2, w0 - 1); w <= std::min(kMaxW, w0 + 1); ++w) {
+    const int w_ref = std::min(kMaxW, w0 + 3);
+    // (at the widest width the reference is the only judge there is)
+    for (int w = std::max(2, w0 - 1); w < w_ref || (w == w_ref && w == kMaxW); ++w) {
         nufft2_handle h;
         if ((st = make_plan(prec, 1, w, 0, 0, &h)) != NUFFT2_OK) return st;
         if ((st = nufft2_setpts(h, np, phi_dev, theta_dev)) != NUFFT2_OK || (st = nufft2_exec(h, d_cin, d_out)) != NUFFT2_OK)
@@ -238,6 +241,16 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
         w_best = w;
         err_best = err;
         if (err <= eps) break;
+    }
+    if (!(err_best <= eps)) {
+        // no width reaches eps on the probe (the precision's floor): report
+        // the closest, write nothing to the cache
+        if (result) {
+            memset(result, 0, sizeof(*result));
+            result->w = w_best;
+            result->err = err_best;
+        }
+        return NUFFT2_ERR_EPS_RANGE;
     }
     // tiles: fastest candidate for that width
     hipEvent_t ev0 = nullptr, ev1 = nullptr;

@@ -76,3 +76,29 @@ def test_autotune_argument_errors(torch_dev):
     assert st == nufft2.NUFFT2_ERR_EPS_RANGE
     st, _, _ = nufft2.nufft2_autotune(1, 63, 63, 1, 1e-6, 8, 0, x.data_ptr())
     assert st == nufft2.NUFFT2_ERR_ARG
+
+
+def test_autotune_at_the_fp32_floor_meets_eps_or_says_it_cannot(torch_dev, tmp_path):
+    """eps 1e-7 in FP32 (the floor) on a flat-spectrum probe: the tuner either
+    returns a width whose measured error is within eps, or ERR_EPS_RANGE with
+    the closest width and error, and then writes no cache entry."""
+    torch, dev = torch_dev
+    import os
+
+    from paper_2605_01313_amd import nufft2
+    say("case autotune fp32 eps 1e-7")
+    rng = np.random.default_rng(3)
+    n = 20000
+    phi = torch.from_numpy(rng.uniform(0, 2 * np.pi, n)).to(dev)
+    theta = torch.from_numpy(rng.uniform(0, np.pi, n)).to(dev)
+    cache = str(tmp_path / "tune.json")
+    st, opts, res = nufft2.nufft2_autotune(nufft2.NUFFT2_FP32, 127, 127, 1, 1e-7, n, phi.data_ptr(),
+                                           theta.data_ptr(), torch.cuda.current_stream().cuda_stream, cache)
+    say(f"  status {st}, w {res.w}, err {res.err:.3e}")
+    if st == nufft2.NUFFT2_OK:
+        assert res.err <= 1e-7 and opts.w == res.w
+        assert os.path.exists(cache)
+    else:
+        assert st == nufft2.NUFFT2_ERR_EPS_RANGE
+        assert res.err > 1e-7 and res.w >= 8
+        assert not os.path.exists(cache) or "eps1.000e-07" not in open(cache).read()
