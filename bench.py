@@ -34,8 +34,14 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # dense matrix-core peaks of 
 PROFILE_EVERY = 10   # timed steps per step with the dominant kernel bracketed by events
 STAGES = ("setpts", "theta_pass", "phi_pass", "gather")
 SINGLE_KERNEL_STAGES = ("theta_pass", "phi_pass", "gather")
-KERNEL_SOURCES = {"setpts": "setpts.hip", "theta_pass": "fft.hip", "phi_pass": "fft.hip",
-                  "gather": "gather.hip"}
+# the sources each stage's kernels are built from (their hash keys the
+# committed counter summaries)
+KERNEL_SOURCES = {"setpts": ("setpts.hip", "nufft2_internal.hpp"),
+                  "theta_pass": ("fft.hip", "nufft2_internal.hpp"),
+                  "phi_pass": ("fft.hip", "nufft2_internal.hpp"),
+                  "gather": ("gather_kernels.hpp", "gather.hip", "gather_f64.hip", "nufft2_internal.hpp")}
+PLAN_KINDS = (("fp32", "fp32", 1e-6, True), ("fp64", "fp64", 1e-12, True),
+              ("fp32_complex", "fp32", 1e-6, False), ("fp64_complex", "fp64", 1e-12, False))
 
 
 def log(msg):
@@ -43,8 +49,10 @@ def log(msg):
 
 
 def source_hash(stage):
-    path = os.path.join(ROOT, "paper_2605_01313_amd", "csrc", KERNEL_SOURCES[stage])
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[stage]:
+        h.update(open(os.path.join(ROOT, "paper_2605_01313_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def stage_bytes(stage, info, n_touched, real_output=False):
@@ -696,6 +704,8 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (ensemble)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter scale for rocprofv3 --pmc)")
+    ap.add_argument("--profile-plan", choices=[k[0] for k in PLAN_KINDS], default=None,
+                    help="run only this plan kind of the workload and print its times (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
@@ -717,6 +727,9 @@ def main():
         return
     headline = single_workload(args, torch, args.workload, args.steps, args.warmup)
     line, runners, wl = headline["line"], headline["runners"], headline["wl"]
+    if args.profile_plan:
+        print(json.dumps(line), flush=True)
+        return
     cpu_args = None
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
@@ -772,8 +785,9 @@ def single_workload(args, torch, which, steps, warmup):
         workload = "grid1024x2048_wind"
     log(f"bench: {wl.n_pts} points x {wl.n_fields} fields")
     runs = {}
-    for key, prec, eps, herm in (("fp32", "fp32", 1e-6, True), ("fp64", "fp64", 1e-12, True),
-                                 ("fp32_complex", "fp32", 1e-6, False), ("fp64_complex", "fp64", 1e-12, False)):
+    for key, prec, eps, herm in PLAN_KINDS:
+        if args.profile_plan and key != args.profile_plan:
+            continue
         r = Runner(torch, wl, prec, eps, hermitian=herm)
         res = r.timed(steps, warmup)
         log(f"bench: {key} {res['ms_per_step']:.4f} ms/step; stages {res['stage_avg_ms']}")
@@ -787,6 +801,12 @@ def single_workload(args, torch, which, steps, warmup):
             dst.copy_(src)
         torch.cuda.synchronize()
         log("bench: copy probe 256 MiB x 5 done")
+    if args.profile_plan:
+        # profiling run of one plan kind: no headline line
+        r, res, roof = runs[args.profile_plan]
+        return {"line": {"profile_plan": args.profile_plan, "workload": workload,
+                         "ms_per_step": res["ms_per_step"], "stages_ms": res["stage_avg_ms"]},
+                "runners": [r], "wl": wl}
 
     def summary(key):
         r, res, roof = runs[key]
