@@ -334,7 +334,10 @@ nufft2_status nufft2_group_get_info(nufft2_group g, nufft2_group_info *info);
  *   precision, mode counts, fields, eps, point count rounded up to a power of
  *   two and the device's architecture name; a hit skips the measurements,
  *   a miss adds an entry (the file is rewritten through a temporary file).
- *   opts_out receives w, tile_theta and tile_phi (other fields zero);
+ *   opts_out: on input, hermitian = 1 times the tiles on real-field plans
+ *   (odd mode counts; the width search is the same), 0 on complex ones (its
+ *   other input fields are ignored); on output it receives w, tile_theta,
+ *   tile_phi and hermitian (other fields zero), ready for nufft2_plan;
  *   result (may be NULL) the measured error, time and whether the cache
  *   answered.  The tuner creates and destroys its own plans and buffers on
  *   the current device and synchronises `stream`.

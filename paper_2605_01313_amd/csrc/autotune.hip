@@ -128,6 +128,10 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
 {
     if (!opts_out || n_pts < 1 || n_pts > (int64_t)0x7fffffff || !phi_dev || !theta_dev || n_fields < 1)
         return NUFFT2_ERR_ARG;
+    // opts_out->hermitian on input: time the tiles on real-field plans
+    const int herm = opts_out->hermitian;
+    if (herm != 0 && herm != 1) return NUFFT2_ERR_ARG;
+    if (herm && (Kt % 2 == 0 || Kp % 2 == 0)) return NUFFT2_ERR_ARG;
     int32_t w0;
     double beta0;
     nufft2_status st = nufft2_kernel_params(prec, eps, &w0, &beta0);
@@ -149,8 +153,8 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
             if (*c == '"' || *c == '\\' || *c == ':') *c = '_';
         int64_t nb = 1;
         while (nb < n_pts) nb <<= 1;
-        snprintf(key, sizeof key, "prec%d_K%lldx%lld_F%d_eps%.3e_n%lld_%s", (int)prec, (long long)Kt, (long long)Kp,
-                 n_fields, eps, (long long)nb, arch);
+        snprintf(key, sizeof key, "prec%d_K%lldx%lld_F%d_eps%.3e_n%lld_h%d_%s", (int)prec, (long long)Kt,
+                 (long long)Kp, n_fields, eps, (long long)nb, herm, arch);
     }
     std::vector<CacheEntry> cache = read_cache(cache_path);
     for (const CacheEntry &c : cache)
@@ -159,6 +163,7 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
             opts_out->w = c.w;
             opts_out->tile_theta = c.tt;
             opts_out->tile_phi = c.tp;
+            opts_out->hermitian = herm;
             if (result) {
                 memset(result, 0, sizeof(*result));
                 result->w = c.w;
@@ -193,11 +198,12 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
                            hipMemcpyDeviceToDevice)) != hipSuccess)
             return NUFFT2_ERR_HIP;
 
-    auto make_plan = [&](nufft2_prec pr, int32_t F, int32_t w, int tt, int tp, nufft2_handle *h) {
+    auto make_plan = [&](nufft2_prec pr, int32_t F, int32_t w, int tt, int tp, nufft2_handle *h, int hm = 0) {
         nufft2_opts o{};
         o.w = w;
         o.tile_theta = tt;
         o.tile_phi = tp;
+        o.hermitian = hm;
         const double pe = pr == NUFFT2_FP64 ? std::max(eps, 1e-15) : eps;
         nufft2_status r = nufft2_plan(pr, Kt, Kp, F, pe, &o, stream, h);
         if (r == NUFFT2_OK) sc.plans.push_back(*h);
@@ -263,7 +269,7 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
     double ms_best = 1e300;
     for (const auto &tc : kTileCandidates) {
         nufft2_handle h;
-        if (make_plan(prec, n_fields, w_best, tc[0], tc[1], &h) != NUFFT2_OK) continue;  // e.g. LDS limit
+        if (make_plan(prec, n_fields, w_best, tc[0], tc[1], &h, herm) != NUFFT2_OK) continue;  // e.g. LDS limit
         std::vector<float> ms;
         for (int rep = 0; rep <= kTimedReps; ++rep) {
             if (hipEventRecord(ev0, s) != hipSuccess) break;
@@ -296,6 +302,7 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
     opts_out->w = w_best;
     opts_out->tile_theta = tt_best;
     opts_out->tile_phi = tp_best;
+    opts_out->hermitian = herm;
     if (result) {
         memset(result, 0, sizeof(*result));
         result->w = w_best;

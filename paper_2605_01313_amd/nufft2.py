@@ -305,9 +305,10 @@ def nufft2_group_get_info(group):
 
 
 def nufft2_autotune(prec, n_modes_theta, n_modes_phi, n_fields, eps, n_pts, phi_ptr, theta_ptr,
-                    stream=0, cache_path=None):
+                    stream=0, cache_path=None, hermitian=False):
     """Returns (status, nufft2_opts, nufft2_tune_result)."""
     opts = nufft2_opts()
+    opts.hermitian = int(bool(hermitian))
     res = nufft2_tune_result()
     st = _lib.nufft2_autotune(int(prec), int(n_modes_theta), int(n_modes_phi), int(n_fields), float(eps),
                               int(n_pts), ctypes.c_void_p(phi_ptr or None), ctypes.c_void_p(theta_ptr or None),
@@ -672,7 +673,8 @@ class Group:
             pass
 
 
-def autotune(prec, n_modes_theta, n_modes_phi, n_fields, eps, phi, theta, cache_path=None, stream=None):
+def autotune(prec, n_modes_theta, n_modes_phi, n_fields, eps, phi, theta, cache_path=None, stream=None,
+             hermitian=False):
     """Tune width and tiles on the given points (float64 device tensors).
 
     Returns a dict: w, tile_theta, tile_phi (keyword arguments for Plan) and
@@ -686,7 +688,7 @@ def autotune(prec, n_modes_theta, n_modes_phi, n_fields, eps, phi, theta, cache_
             raise TypeError("points must be contiguous float64 device tensors")
     s = stream if stream is not None else torch.cuda.current_stream()
     st, opts, res = nufft2_autotune(prec_code, n_modes_theta, n_modes_phi, n_fields, eps, phi.numel(),
-                                    phi.data_ptr(), theta.data_ptr(), s.cuda_stream, cache_path)
+                                    phi.data_ptr(), theta.data_ptr(), s.cuda_stream, cache_path, hermitian)
     _check(st, "nufft2_autotune")
     out = res.as_dict()
     out.update(w=opts.w, tile_theta=opts.tile_theta, tile_phi=opts.tile_phi)

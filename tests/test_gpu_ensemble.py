@@ -34,22 +34,24 @@ def members():
     return out
 
 
-def test_full_ensemble_group_meets_oracle_per_member(members, oracle_mod):
+@pytest.mark.parametrize("herm", [False, True])
+def test_full_ensemble_group_meets_oracle_per_member(members, oracle_mod, herm):
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     from paper_2605_01313_amd import Group, Plan
     dev = torch.device("cuda:0")
     assert len(members) == 80
     assert [m.coeffs.shape[-1] for m in members] == [255] * 64 + [511] * 16
-    say("case ensemble_full 64 x 255^2 + 16 x 511^2 modes, 3 fields, fp32 eps 1e-6")
+    say(f"case ensemble_full 64 x 255^2 + 16 x 511^2 modes, 3 fields, fp32 eps 1e-6, "
+        f"{'real-field' if herm else 'complex'} plans")
     plans, coeffs, phis, thetas, outs = [], [], [], [], []
     for m in members:
         F, Kt, Kp = m.coeffs.shape
-        plans.append(Plan("fp32", Kt, Kp, n_fields=F, eps=1e-6))
+        plans.append(Plan("fp32", Kt, Kp, n_fields=F, eps=1e-6, hermitian=herm))
         coeffs.append(torch.from_numpy(m.coeffs).to(dev).to(torch.complex64).contiguous())
         phis.append(torch.from_numpy(m.phi).to(dev))
         thetas.append(torch.from_numpy(m.theta).to(dev))
-        outs.append(torch.empty((F, m.n_pts), dtype=torch.complex64, device=dev))
+        outs.append(torch.empty((F, m.n_pts), dtype=torch.float32 if herm else torch.complex64, device=dev))
     g = Group(plans)
     info = g.info()
     say(f"  group: {info['n_members']} members, {info['n_classes']} classes")
@@ -63,6 +65,8 @@ def test_full_ensemble_group_meets_oracle_per_member(members, oracle_mod):
     for i, m in enumerate(members):
         sel = synth.sample_indices(m.n_pts, 128, seed=300 + i)
         ref = oracle_mod.dfs_eval(m.coeffs, m.phi[sel], m.theta[sel])
+        if herm:
+            ref = ref.real
         got = outs[i][:, torch.from_numpy(sel).to(dev)].cpu().numpy()
         err = max(float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(ref.shape[0]))
         worst = max(worst, err)
