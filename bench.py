@@ -175,8 +175,23 @@ class Runner:
             lat.append(a.elapsed_time(b))
         lat.sort()
         pct = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]
+        # cold caches: a 1 GiB fill (past the 256 MB Infinity Cache and the
+        # L2s) before each timed step; median of 10
+        flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        cold = []
+        for i in range(10):
+            flush.fill_(float(i))
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            self.step()
+            b.record(s)
+            b.synchronize()
+            cold.append(a.elapsed_time(b))
+        del flush
+        cold.sort()
         return {"ms_per_step": ms_step, "stage_avg_ms": avg, "dominant": dominant,
-                "live_ms": live, "p50_ms": pct(0.50), "p99_ms": pct(0.99)}
+                "live_ms": live, "p50_ms": pct(0.50), "p99_ms": pct(0.99), "cold_ms": cold[len(cold) // 2]}
 
     def roofline(self, res, workload, tag):
         """HBM roofline of one kernel of this plan from the live events."""
@@ -687,10 +702,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("wind1024", "sbr256", "ensemble", "serving", "upstream"),
+    ap.add_argument("--workload", choices=("wind1024", "sbr256", "sbr256c5", "ensemble", "serving", "upstream"),
                     default="wind1024",
                     help="wind1024: 1024x2048 grid, 8-mode wind, Courant 8 (default); "
-                         "sbr256: 256x512 grid, solid-body rotation; "
+                         "sbr256: 256x512 grid, solid-body rotation (dt 1200 s); "
+                         "sbr256c5: the same at dt 10125 s (Courant ~5); "
                          "ensemble: 64 + 16 members of uneven size as one group; "
                          "serving: Poisson request stream through the serving loop; "
                          "upstream: analysis, partial-regularity and rotation kernels at 1024x2048")
@@ -750,8 +766,16 @@ def main():
         for r in small["runners"]:
             r.plan.destroy()
         line["grid256x512_sbr"] = {k: small["line"][k] for k in
-                                   ("value", "unit", "ms_per_step", "config", "latency_ms", "stages_ms",
-                                    "roofline", "gather_roofline", "fp64", "fp32_complex", "fp64_complex")}
+                                   ("value", "unit", "ms_per_step", "config", "latency_ms", "cold_cache_ms_per_step",
+                                    "stages_ms", "roofline", "gather_roofline", "fp64", "fp32_complex",
+                                    "fp64_complex")}
+        log("bench: 256x512 Courant-5 section")
+        c5 = single_workload(args, torch, "sbr256c5", 100, 10)
+        for r in c5["runners"]:
+            r.plan.destroy()
+        line["grid256x512_sbr_courant5"] = {k: c5["line"][k] for k in
+                                            ("value", "unit", "ms_per_step", "config", "latency_ms",
+                                             "cold_cache_ms_per_step", "stages_ms", "fp64")}
         log("bench: ensemble section")
         line["ensemble"] = ensemble_bench(args, torch, 20, 3)
         log("bench: serving section")
@@ -781,6 +805,11 @@ def single_workload(args, torch, which, steps, warmup):
         log("bench: building the 256x512 solid-body-rotation workload")
         wl = synth.workload_sbr()
         workload = "grid256x512_sbr"
+    elif which == "sbr256c5":
+        # the same rotation with a time step of 10,125 s: Courant number ~5
+        log("bench: building the 256x512 solid-body-rotation workload at Courant ~5")
+        wl = synth.workload_sbr(dt=10125.0)
+        workload = "grid256x512_sbr_courant5"
     else:
         log("bench: building the 1024x2048 8-mode-wind workload")
         wl = synth.workload_large()
@@ -816,6 +845,7 @@ def single_workload(args, torch, which, steps, warmup):
                 "ms_per_step": res["ms_per_step"], "eps": 1e-6 if r.prec == "fp32" else 1e-12,
                 "w": r.info["w"], "plan": "real-field" if r.hermitian else "complex",
                 "latency_ms": {"p50": res["p50_ms"], "p99": res["p99_ms"]},
+                "cold_cache_ms_per_step": res["cold_ms"],
                 "stages_ms": res["stage_avg_ms"],
                 "roofline": roof[res["dominant"]], "gather_roofline": roof["gather"]}
 
@@ -832,6 +862,7 @@ def single_workload(args, torch, which, steps, warmup):
                    "fields": "real (Hermitian coefficients): real-field plan, real output",
                    "step": "setpts + exec (all fields)"},
         "latency_ms": {"p50": res32["p50_ms"], "p99": res32["p99_ms"]},
+        "cold_cache_ms_per_step": res32["cold_ms"],
         "stages_ms": res32["stage_avg_ms"],
         "roofline": roof32[res32["dominant"]],
         "gather_roofline": roof32["gather"],
