@@ -77,6 +77,8 @@ typedef struct {
                              64 for FP32 plans with hermitian = 1 */
     int32_t real_output;  /* 1: write only the real part (fields known to be real) */
     int32_t hermitian;    /* 1: real fields, see below (implies real output) */
+    int32_t m_major;      /* 1: coefficients stored mode-m outer, see nufft2_exec */
+    int32_t reserved;     /* 0 */
 } nufft2_opts;
 
 typedef struct {
@@ -96,6 +98,8 @@ typedef struct {
     int32_t hermitian;       /* 1: real-field plan */
     int32_t fields_per_pass; /* fields the gather stages together: fields f
                                 and g share a pass iff f / this == g / this */
+    int32_t m_major;         /* 1: coefficients [n_fields][n_modes_phi][n_modes_theta] */
+    int32_t reserved;
 } nufft2_info;
 
 /*
@@ -170,7 +174,12 @@ nufft2_status nufft2_setpts_vector(nufft2_handle p, int64_t n_pts, const double 
 /*
  * nufft2_exec -- evaluate all fields at the current points.
  *   coeffs_dev  [n_fields][n_modes_theta][n_modes_phi] complex (re, im
- *               interleaved) in the plan's precision, row-major, centred.
+ *               interleaved) in the plan's precision, row-major, centred;
+ *               with opts.m_major = 1, [n_fields][n_modes_phi][n_modes_theta]
+ *               (entry [f][b][a] is mode n = a - n_modes_theta/2, m =
+ *               b - n_modes_phi/2), the layout nufft2_analysis writes when
+ *               asked (nufft2_analysis_set_layout): the theta pass then reads
+ *               each mode column as one contiguous run.
  *   out_dev     [n_fields][n_pts] complex in the plan's precision, in the
  *               caller's point order; with real_output or hermitian,
  *               [n_fields][n_pts] real.
@@ -480,6 +489,16 @@ nufft2_status nufft2_analysis_destroy(nufft2_analysis a);
  * plan's stream.  Errors: ERR_ARG (null handle), ERR_HIP.
  */
 nufft2_status nufft2_analysis_set_zonal_filter(nufft2_analysis a, int32_t M0);
+
+/*
+ * nufft2_analysis_set_layout -- the output layout of the following
+ * nufft2_analysis_exec calls: m_major = 0 (the default) writes
+ * [n_fields][2J-1 (n)][2J-1 (m)], m_major = 1 writes
+ * [n_fields][2J-1 (m)][2J-1 (n)], the layout of a plan created with
+ * opts.m_major = 1 (its theta pass then reads whole mode columns).  The
+ * same values either way.  Errors: ERR_ARG.
+ */
+nufft2_status nufft2_analysis_set_layout(nufft2_analysis a, int32_t m_major);
 
 /*
  * Partial-regularity DFS expansion (section 4, eq. pr_dfs).  Column m of

@@ -320,6 +320,7 @@ template <typename T> struct ThetaLoad {
     const cplx<T> *fac;   // this parity's factors
     T cpm;
     int Kt, Kp, ncols, L, m0;
+    int m_major;          // 1: column m's modes are contiguous ([Kp][Kt])
     // Loads are unconditional (clamped indices) so that the compiler issues
     // every element's loads before the first wait; padding slots select 0.
     __device__ cplx<T> operator()(int i, int b) const
@@ -329,7 +330,7 @@ template <typename T> struct ThetaLoad {
         const bool live = a >= 0 && m < ncols;
         const int ac = live ? a : 0, mc = live ? m : 0;
         const cplx<T> f = fac[ac];
-        const cplx<T> x = cmul(coef[ac * Kp + mc], cplx<T>{f.x * cpm, f.y * cpm});
+        const cplx<T> x = cmul(coef[m_major ? mc * Kt + ac : ac * Kp + mc], cplx<T>{f.x * cpm, f.y * cpm});
         return live ? x : cplx<T>{(T)0, (T)0};
     }
 };
@@ -432,8 +433,8 @@ __device__ inline void theta_body(int item, const cplx<T> *__restrict__ coeffs, 
     const int m0 = (tile - f * ntiles) * B;
     const int mt = m0 + ((int)threadIdx.x & (B - 1));
     const T cpm = corr_p[fp.col0 + (mt < fp.ncols ? mt : 0)];
-    ThetaLoad<T> ld{coeffs + (int64_t)f * fp.Kt * fp.Kp + fp.col0, fac_t + parity * fp.Kt, cpm, fp.Kt, fp.Kp,
-                    fp.ncols, L, m0};
+    ThetaLoad<T> ld{coeffs + (int64_t)f * fp.Kt * fp.Kp + (fp.m_major ? (int64_t)fp.col0 * fp.Kt : fp.col0),
+                    fac_t + parity * fp.Kt, cpm, fp.Kt, fp.Kp, fp.ncols, L, m0, fp.m_major};
     ThetaStore<T> st{S + (int64_t)f * fp.nft * fp.ncols, flags, fp.ncols, m0, parity};
     ThetaPro<cplx<T>, E> pro{tw, tws, tw_lds_len(L), flags, touched, L, parity};
     fft_stages<T, LOGL, 0, E, true>(s, logB, B, 1, tw, ld, st, pro);
@@ -786,16 +787,17 @@ template <typename T> struct AnaColLoad {
     }
 };
 template <typename T> struct AnaColStore {
-    cplx<T> *out;          // this field, [K][K]
+    cplx<T> *out;          // this field, [K][K] (rows n, or rows m when m_major)
     const cplx<T> *phase;  // [K]: e^{-i n pi/(2J)} / (2J)^2, n = -(J-1) .. J-1
-    int J, K, m0;
+    int J, K, m0, m_major;
     __device__ void operator()(int o, int b, cplx<T> v) const
     {
         const int mi = m0 + b;
         if (mi >= K || o == J) return;
         const int n = o < J ? o : o - 2 * J;
         const cplx<T> z{v.x, -v.y};  // conj back: forward transform
-        out[(int64_t)(n + J - 1) * K + mi] = cmul(z, phase[n + J - 1]);
+        const int64_t o2 = m_major ? (int64_t)mi * K + (n + J - 1) : (int64_t)(n + J - 1) * K + mi;
+        out[o2] = cmul(z, phase[n + J - 1]);
     }
 };
 
@@ -804,7 +806,7 @@ __global__ __launch_bounds__(512) void k_analysis_theta(const cplx<T> *__restric
                                                         const cplx<T> *__restrict__ tws,
                                                         const cplx<T> *__restrict__ phase,
                                                         cplx<T> *__restrict__ out, int J, int cols_per_wg,
-                                                        int log_cols_per_wg)
+                                                        int log_cols_per_wg, int m_major)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int N = 1 << LOGN;  // = 2J
@@ -815,7 +817,7 @@ __global__ __launch_bounds__(512) void k_analysis_theta(const cplx<T> *__restric
     const int f = (int)blockIdx.x / ntiles;
     const int m0 = ((int)blockIdx.x - f * ntiles) * cols_per_wg;
     AnaColLoad<T> ld{A + (int64_t)f * J * K, J, K, m0};
-    AnaColStore<T> st{out + (int64_t)f * K * K, phase, J, K, m0};
+    AnaColStore<T> st{out + (int64_t)f * K * K, phase, J, K, m0, m_major};
     TwiddleCopy<cplx<T>> pro{tw, tws, tw_lds_len(N)};
     fft_stages<T, LOGN, 0, E, true>(s, log_cols_per_wg, cols_per_wg, 1, tw, ld, st, pro);
 }
@@ -874,7 +876,7 @@ static hipError_t launch_analysis_t(const AnalysisParams &ap, const void *vals, 
         const int K = 2 * J - 1;
         const int ntiles = (K + cb - 1) / cb;
         hipLaunchKernelGGL(kern, dim3(ntiles * ap.n_fields), dim3(threads), lds, s, (const cplx<T> *)A,
-                           (const cplx<T> *)tws, (const cplx<T> *)phase, (cplx<T> *)out, J, cb, lcb);
+                           (const cplx<T> *)tws, (const cplx<T> *)phase, (cplx<T> *)out, J, cb, lcb, ap.m_major);
     }
     return hipGetLastError();
 }

@@ -57,7 +57,7 @@ bool same_class(const nufft2_plan_s *a, const nufft2_plan_s *b)
            a->fields_per_pass == b->fields_per_pass &&
            a->tile_pitch == b->tile_pitch &&
            a->fp.theta_batch == b->fp.theta_batch && a->fp.phi_batch == b->fp.phi_batch &&
-           a->fp.theta_ept == b->fp.theta_ept && a->fp.phi_ept == b->fp.phi_ept;
+           a->fp.theta_ept == b->fp.theta_ept && a->fp.phi_ept == b->fp.phi_ept && a->fp.m_major == b->fp.m_major;
 }
 
 

@@ -109,6 +109,9 @@ struct FFTParams {
     int32_t col0, ncols;
     int32_t c2r;
     int32_t log_phi_len;                    // log2 of the phi-pass transform length
+    // 1: the coefficients are stored m-major ([F][Kp][Kt]: each column's
+    // Kt modes contiguous), so the theta pass reads whole columns
+    int32_t m_major;
 };
 
 // fac_t: complex [2][Kt]: corr_t[a], then corr_t[a] e^{2 pi i n / nft}
@@ -204,6 +207,7 @@ struct AnalysisParams {
     int32_t J, log_len;  // log_len = log2(2J)
     int32_t n_fields;
     const int32_t *zonal_cut;  // [J] kept |m| per row (device), or nullptr: no zonal filter
+    int32_t m_major;           // 1: output [F][K][K] with mode m outer (nufft2_exec's m-major layout)
 };
 hipError_t launch_analysis(int prec, const AnalysisParams &ap, const void *vals, const void *tws, const void *phase,
                            void *A, void *out, hipStream_t s);

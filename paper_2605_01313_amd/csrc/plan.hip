@@ -452,7 +452,8 @@ nufft2_status plan_configure(nufft2_plan_s *p, int prec, int64_t n_modes_theta, 
     if (n_modes_theta > kMaxNf / 2 || n_modes_phi > kMaxNf / 2) return NUFFT2_ERR_ARG;
     nufft2_opts o{};
     if (opts) o = *opts;
-    if ((o.hermitian != 0 && o.hermitian != 1) || o.w < 0 || o.w > kMaxW || o.w == 1 || o.beta_over_w < 0 ||
+    if ((o.hermitian != 0 && o.hermitian != 1) || (o.m_major != 0 && o.m_major != 1) || o.reserved != 0 ||
+        o.w < 0 || o.w > kMaxW || o.w == 1 || o.beta_over_w < 0 ||
         !isfinite(o.beta_over_w) || (o.real_output != 0 && o.real_output != 1))
         return NUFFT2_ERR_ARG;
     // a real field's modes are symmetric about zero: odd counts
@@ -523,6 +524,7 @@ nufft2_status plan_configure(nufft2_plan_s *p, int prec, int64_t n_modes_theta, 
     fp.n_fields = p->F;
     fp.col0 = o.hermitian ? (int)(p->Kp / 2) : 0;
     fp.ncols = (int)p->ncols;
+    fp.m_major = o.m_major;
     fp.c2r = o.hermitian;
     fp.log_phi_len = fp.log_nfp - (o.hermitian ? 1 : 0);
     {
@@ -925,6 +927,7 @@ NUFFT2_API nufft2_status nufft2_get_info(nufft2_handle p, nufft2_info *info)
     info->device = p->device;
     info->hermitian = p->hermitian;
     info->fields_per_pass = p->fields_per_pass;
+    info->m_major = p->fp.m_major;
     return NUFFT2_OK;
 }
 
@@ -1108,6 +1111,7 @@ struct nufft2_analysis_s {
     void *tws = nullptr, *phase = nullptr, *A = nullptr;
     int32_t *cut = nullptr;  // zonal filter: kept |m| per row
     bool zonal = false;
+    int m_major = 0;         // output layout
 };
 
 namespace {
@@ -1178,6 +1182,7 @@ NUFFT2_API nufft2_status nufft2_analysis_exec(nufft2_analysis a, const void *val
     ap.log_len = ilog2(2 * (int64_t)a->J);
     ap.n_fields = a->F;
     ap.zonal_cut = a->zonal ? a->cut : nullptr;
+    ap.m_major = a->m_major;
     const hipError_t e = launch_analysis(a->prec, ap, values_dev, a->tws, a->phase, a->A, coeffs_dev, a->stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -1211,6 +1216,13 @@ NUFFT2_API nufft2_status nufft2_analysis_set_zonal_filter(nufft2_analysis a, int
         return NUFFT2_ERR_HIP;
     }
     a->zonal = true;
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_analysis_set_layout(nufft2_analysis a, int32_t m_major)
+{
+    if (!a || (m_major != 0 && m_major != 1)) return NUFFT2_ERR_ARG;
+    a->m_major = m_major;
     return NUFFT2_OK;
 }
 

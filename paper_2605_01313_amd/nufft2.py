@@ -35,7 +35,7 @@ EXPORTED = (
     "nufft2_group_destroy", "nufft2_group_get_info", "nufft2_autotune", "nufft2_server_create",
     "nufft2_server_clock", "nufft2_server_submit", "nufft2_server_wait", "nufft2_server_drain",
     "nufft2_server_stats", "nufft2_server_destroy", "nufft2_analysis_plan", "nufft2_analysis_exec",
-    "nufft2_analysis_destroy", "nufft2_rotate_uv", "nufft2_analysis_set_zonal_filter", "nufft2_pr_plan",
+    "nufft2_analysis_destroy", "nufft2_rotate_uv", "nufft2_analysis_set_zonal_filter", "nufft2_analysis_set_layout", "nufft2_pr_plan",
     "nufft2_pr_project", "nufft2_pr_synthesize", "nufft2_pr_destroy", "nufft2_gl_nodes", "nufft2_gl_plan",
     "nufft2_gl_exec", "nufft2_gl_destroy", "nufft2_exec_noalloc", "nufft2_noalloc_capacity",
 )
@@ -46,7 +46,8 @@ STAGE_NAMES = ("setpts", "theta_pass", "phi_pass", "gather")
 class nufft2_opts(ctypes.Structure):
     _fields_ = [("w", ctypes.c_int32), ("beta_over_w", ctypes.c_double),
                 ("tile_theta", ctypes.c_int32), ("tile_phi", ctypes.c_int32),
-                ("real_output", ctypes.c_int32), ("hermitian", ctypes.c_int32)]
+                ("real_output", ctypes.c_int32), ("hermitian", ctypes.c_int32),
+                ("m_major", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class nufft2_info(ctypes.Structure):
@@ -57,10 +58,11 @@ class nufft2_info(ctypes.Structure):
                 ("tile_theta", ctypes.c_int32), ("tile_phi", ctypes.c_int32),
                 ("n_bins", ctypes.c_int64), ("n_pts", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_uint64), ("last_hip_error", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("hermitian", ctypes.c_int32), ("fields_per_pass", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("hermitian", ctypes.c_int32), ("fields_per_pass", ctypes.c_int32),
+                ("m_major", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class nufft2_group_info(ctypes.Structure):
@@ -152,6 +154,7 @@ def _load():
         "nufft2_rotate_uv": [H, vp, i32, i32, vp, vp, vp, vp],
         "nufft2_setpts_vector": [H, i64, vp, vp, vp, vp, i32, i32],
         "nufft2_analysis_set_zonal_filter": [H, i32],
+        "nufft2_analysis_set_layout": [H, i32],
         "nufft2_pr_plan": [i32, i64, i64, i32, vp, ctypes.POINTER(H)],
         "nufft2_pr_project": [H, vp, vp],
         "nufft2_pr_synthesize": [H, vp, vp],
@@ -397,6 +400,10 @@ def nufft2_analysis_set_zonal_filter(handle, M0):
     return _lib.nufft2_analysis_set_zonal_filter(handle, int(M0))
 
 
+def nufft2_analysis_set_layout(handle, m_major):
+    return _lib.nufft2_analysis_set_layout(handle, int(m_major))
+
+
 def nufft2_pr_plan(prec, N, M, n_fields, stream=0):
     """Returns (status, partial-regularity plan handle)."""
     h = ctypes.c_void_p()
@@ -451,22 +458,28 @@ class Plan:
     hermitian=True: coefficients of real fields (c[-n][-m] = conj c[n][m]);
     the plan reads the m >= 0 half, works on a real fine grid and returns
     real values (float32 / float64).
+    m_major=True: coefficients given as (F, K_phi, K_theta) (mode m outer),
+    the layout Analysis writes with m_major=True.
     """
 
     def __init__(self, prec, n_modes_theta, n_modes_phi, n_fields=1, eps=1e-6, *, w=0,
-                 beta_over_w=0.0, tile_theta=0, tile_phi=0, real_output=False, hermitian=False, stream=None):
+                 beta_over_w=0.0, tile_theta=0, tile_phi=0, real_output=False, hermitian=False, m_major=False,
+                 stream=None):
         import torch
         self._torch = torch
         self.prec = {"fp32": NUFFT2_FP32, "fp64": NUFFT2_FP64,
                      NUFFT2_FP32: NUFFT2_FP32, NUFFT2_FP64: NUFFT2_FP64}[prec]
         self.cdtype = torch.complex64 if self.prec == NUFFT2_FP32 else torch.complex128
         self.rdtype = torch.float32 if self.prec == NUFFT2_FP32 else torch.float64
-        self.shape = (int(n_fields), int(n_modes_theta), int(n_modes_phi))
+        self.m_major = bool(m_major)
+        # the coefficient tensor's shape: (F, K_theta, K_phi), or (F, K_phi, K_theta) m-major
+        self.shape = ((int(n_fields), int(n_modes_phi), int(n_modes_theta)) if self.m_major
+                      else (int(n_fields), int(n_modes_theta), int(n_modes_phi)))
         self.hermitian = bool(hermitian)
         self.real_output = bool(real_output) or self.hermitian
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opts = nufft2_opts(int(w), float(beta_over_w), int(tile_theta), int(tile_phi),
-                           int(bool(real_output)), int(self.hermitian))
+                           int(bool(real_output)), int(self.hermitian), int(self.m_major), 0)
         st, h = nufft2_plan(self.prec, n_modes_theta, n_modes_phi, n_fields, eps, opts,
                             self.stream.cuda_stream)
         _check(st, "nufft2_plan")
@@ -787,6 +800,11 @@ class Analysis:
     def set_zonal_filter(self, M0=20):
         """Zonal filter of section 4 on the following execs (M0 < 0: off)."""
         _check(nufft2_analysis_set_zonal_filter(self.handle, M0), "nufft2_analysis_set_zonal_filter")
+
+    def set_layout(self, m_major):
+        """m_major=True: write (F, K, K) with the mode m outer (the layout of
+        Plan(..., m_major=True)); the same values either way."""
+        _check(nufft2_analysis_set_layout(self.handle, int(bool(m_major))), "nufft2_analysis_set_layout")
 
     def exec(self, values, out=None):
         t = self._torch

@@ -123,6 +123,10 @@ def test_plan_argument_errors_before_device_work(nf):
     assert P(nf.NUFFT2_FP64, 511, 511, 1, 1e-12, big_tile)[0] == nf.NUFFT2_ERR_ARG
     bad_flag = nf.nufft2_opts(0, 0.0, 0, 0, 0, 2)
     assert P(nf.NUFFT2_FP64, 63, 63, 1, 1e-12, bad_flag)[0] == nf.NUFFT2_ERR_ARG
+    bad_layout = nf.nufft2_opts(0, 0.0, 0, 0, 0, 0, 2, 0)
+    assert P(nf.NUFFT2_FP64, 63, 63, 1, 1e-12, bad_layout)[0] == nf.NUFFT2_ERR_ARG
+    bad_reserved = nf.nufft2_opts(0, 0.0, 0, 0, 0, 0, 0, 1)
+    assert P(nf.NUFFT2_FP64, 63, 63, 1, 1e-12, bad_reserved)[0] == nf.NUFFT2_ERR_ARG
     # real-field plans need mode ranges symmetric about zero (odd counts)
     herm = nf.nufft2_opts(0, 0.0, 0, 0, 0, 1)
     assert P(nf.NUFFT2_FP64, 64, 63, 1, 1e-12, herm)[0] == nf.NUFFT2_ERR_ARG
