@@ -101,7 +101,9 @@ def read_traffic(stage, workload, prec):
 class Runner:
     """One plan on one workload.  hermitian: the real-field plan (the
     workloads' fields are real: their coefficients are Hermitian), real
-    output; otherwise the complex plan, complex output."""
+    output; otherwise the complex plan, complex output.  The coefficients
+    are held m-major ([F][K_phi][K_theta], the layout the analysis writes
+    on request), so the theta pass reads whole mode columns."""
 
     def __init__(self, torch, wl, prec, eps, hermitian=False):
         from paper_2605_01313_amd import Plan
@@ -111,10 +113,10 @@ class Runner:
         self.prec = prec
         self.hermitian = hermitian
         self.real_output = hermitian
-        self.plan = Plan(prec, Kt, Kp, n_fields=F, eps=eps, hermitian=hermitian)
+        self.plan = Plan(prec, Kt, Kp, n_fields=F, eps=eps, hermitian=hermitian, m_major=True)
         cdt = torch.complex64 if prec == "fp32" else torch.complex128
         rdt = torch.float32 if prec == "fp32" else torch.float64
-        self.coeffs = torch.from_numpy(wl.coeffs).to(dev).to(cdt).contiguous()
+        self.coeffs = torch.from_numpy(wl.coeffs).to(dev).to(cdt).transpose(1, 2).contiguous()
         self.phi = torch.from_numpy(wl.phi).to(dev).contiguous()
         self.theta = torch.from_numpy(wl.theta).to(dev).contiguous()
         self.out = torch.empty((F, wl.n_pts), dtype=rdt if hermitian else cdt, device=dev)
@@ -860,6 +862,7 @@ def single_workload(args, torch, which, steps, warmup):
                    "n_points": wl.n_pts, "n_fields": wl.n_fields, "modes": f"{2*J-1}x{2*J-1}", "eps": 1e-6,
                    "w": r32.info["w"], "nf": r32.info["nf_theta"],
                    "fields": "real (Hermitian coefficients): real-field plan, real output",
+                   "coeff_layout": "m-major [F][K_phi][K_theta] (as the analysis writes it on request)",
                    "step": "setpts + exec (all fields)"},
         "latency_ms": {"p50": res32["p50_ms"], "p99": res32["p99_ms"]},
         "cold_cache_ms_per_step": res32["cold_ms"],
