@@ -489,14 +489,16 @@ def ensemble_bench(args, torch, steps, warmup):
     F = members[0].n_fields
     cache = args.tune_cache or os.path.join(tempfile.gettempdir(), "nufft2_tune.json")
     tuned = {}
-    for m in members:
-        K = m.coeffs.shape[-1]
-        if K in tuned:
-            continue
-        phi = torch.from_numpy(m.phi).to(dev)
-        theta = torch.from_numpy(m.theta).to(dev)
-        tuned[K] = autotune("fp32", K, K, F, 1e-6, phi, theta, cache_path=cache, hermitian=True)
-        log(f"bench: tuned K={K}: {tuned[K]}")
+    for K in sorted({m.coeffs.shape[-1] for m in members}):
+        # tiles are timed at the scale the group runs them: a group of as
+        # many plans as there are members of this size, each with the first
+        # such member's points
+        same = [m for m in members if m.coeffs.shape[-1] == K]
+        phi = torch.from_numpy(same[0].phi).to(dev)
+        theta = torch.from_numpy(same[0].theta).to(dev)
+        tuned[K] = autotune("fp32", K, K, F, 1e-6, phi, theta, cache_path=cache, hermitian=True,
+                            members=len(same))
+        log(f"bench: tuned K={K} as a group of {len(same)}: {tuned[K]}")
     plans, coeffs, phis, thetas, outs = [], [], [], [], []
     for m in members:
         K = m.coeffs.shape[-1]

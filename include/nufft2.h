@@ -368,6 +368,21 @@ nufft2_status nufft2_autotune(nufft2_prec prec, int64_t n_modes_theta, int64_t n
                               nufft2_tune_result *result);
 
 /*
+ * nufft2_autotune_group -- nufft2_autotune for plans that will run as
+ * members of a group (nufft2_group_*).  The width is chosen as above; each
+ * tile candidate is timed as a group of `members` plans of that shape, every
+ * member with the caller's n_pts points (group setpts + group exec), so the
+ * tiles are judged at the occupancy the ensemble runs at rather than at one
+ * member's.  members: 1 .. 4096, members * n_pts < 2^31 (else ERR_ARG);
+ * members = 1 is nufft2_autotune.  The cache key records members.  The tuner
+ * allocates members outputs of n_fields * n_pts values besides the plans.
+ */
+nufft2_status nufft2_autotune_group(nufft2_prec prec, int64_t n_modes_theta, int64_t n_modes_phi, int32_t n_fields,
+                                    double eps, int32_t members, int64_t n_pts, const double *phi_dev,
+                                    const double *theta_dev, void *stream, const char *cache_path,
+                                    nufft2_opts *opts_out, nufft2_tune_result *result);
+
+/*
  * Serving: a request loop that evaluates independent interpolation requests
  * of mixed size and tolerance (section 5's evaluation, one request per
  * point set) with continuous batching.  A scheduler thread admits queued

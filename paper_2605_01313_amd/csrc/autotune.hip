@@ -20,6 +20,7 @@ namespace {
 constexpr int kMaxW = 16;
 constexpr int64_t kProbePoints = 16384;
 constexpr int kTimedReps = 3;
+constexpr int32_t kMaxTuneMembers = 4096;  // members of a timed group
 // Gather tile shapes tried (rows, columns of first-tap cells per bin).
 constexpr int kTileCandidates[][2] = {{8, 32}, {16, 32}, {32, 16}, {16, 64}, {32, 32}, {8, 64}, {32, 64}};
 
@@ -122,11 +123,17 @@ double rel_l2(const std::vector<double> &got, const std::vector<double> &ref)
 
 }  // namespace
 
-NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t Kp, int32_t n_fields, double eps,
-                                         int64_t n_pts, const double *phi_dev, const double *theta_dev, void *stream,
-                                         const char *cache_path, nufft2_opts *opts_out, nufft2_tune_result *result)
+namespace {
+
+// members == 1: tiles timed on one plan; members > 1: on a group of that
+// many plans, every member with the caller's points.
+nufft2_status autotune_impl(nufft2_prec prec, int64_t Kt, int64_t Kp, int32_t n_fields, double eps, int64_t n_pts,
+                            const double *phi_dev, const double *theta_dev, void *stream, const char *cache_path,
+                            nufft2_opts *opts_out, nufft2_tune_result *result, int32_t members)
 {
     if (!opts_out || n_pts < 1 || n_pts > (int64_t)0x7fffffff || !phi_dev || !theta_dev || n_fields < 1)
+        return NUFFT2_ERR_ARG;
+    if (members < 1 || members > kMaxTuneMembers || (int64_t)members * n_pts > (int64_t)0x7fffffff)
         return NUFFT2_ERR_ARG;
     // opts_out->hermitian on input: time the tiles on real-field plans
     const int herm = opts_out->hermitian;
@@ -153,8 +160,10 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
             if (*c == '"' || *c == '\\' || *c == ':') *c = '_';
         int64_t nb = 1;
         while (nb < n_pts) nb <<= 1;
-        snprintf(key, sizeof key, "prec%d_K%lldx%lld_F%d_eps%.3e_n%lld_h%d_%s", (int)prec, (long long)Kt,
-                 (long long)Kp, n_fields, eps, (long long)nb, herm, arch);
+        char grp[24] = "";
+        if (members > 1) snprintf(grp, sizeof grp, "_m%d", (int)members);
+        snprintf(key, sizeof key, "prec%d_K%lldx%lld_F%d_eps%.3e_n%lld_h%d%s_%s", (int)prec, (long long)Kt,
+                 (long long)Kp, n_fields, eps, (long long)nb, herm, grp, arch);
     }
     std::vector<CacheEntry> cache = read_cache(cache_path);
     for (const CacheEntry &c : cache)
@@ -185,7 +194,8 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
     void *d_c64 = sc.alloc(c64.size() * sizeof(double));
     void *d_cin = prec == NUFFT2_FP32 ? sc.alloc(c32.size() * sizeof(float)) : d_c64;
     void *d_ref = sc.alloc((size_t)np * 2 * sizeof(double));
-    void *d_out = sc.alloc((size_t)n_pts * n_fields * cs);
+    // one output per member (the members of a timed group write side by side)
+    void *d_out = sc.alloc((size_t)members * n_pts * n_fields * cs);
     void *d_cf = sc.alloc((size_t)n_fields * Kt * Kp * cs);
     if (!d_c64 || !d_cin || !d_ref || !d_out || !d_cf) return NUFFT2_ERR_ALLOC;
     hipError_t e;
@@ -267,14 +277,32 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
     }
     int tt_best = 0, tp_best = 0, timed = 0;
     double ms_best = 1e300;
+    const std::vector<int64_t> g_n(members, n_pts);
+    const std::vector<const double *> g_phi(members, phi_dev), g_theta(members, theta_dev);
+    const std::vector<const void *> g_cf(members, d_cf);
+    std::vector<void *> g_out(members);
+    for (int i = 0; i < members; ++i) g_out[i] = (char *)d_out + (size_t)i * n_pts * n_fields * cs;
     for (const auto &tc : kTileCandidates) {
-        nufft2_handle h;
-        if (make_plan(prec, n_fields, w_best, tc[0], tc[1], &h, herm) != NUFFT2_OK) continue;  // e.g. LDS limit
+        std::vector<nufft2_handle> hs;
+        bool made = true;
+        for (int i = 0; i < members && made; ++i) {
+            nufft2_handle h;
+            made = make_plan(prec, n_fields, w_best, tc[0], tc[1], &h, herm) == NUFFT2_OK;  // e.g. LDS limit
+            if (made) hs.push_back(h);
+        }
+        nufft2_group g = nullptr;
+        if (made && members > 1) made = nufft2_group_create(hs.data(), members, &g) == NUFFT2_OK;
         std::vector<float> ms;
-        for (int rep = 0; rep <= kTimedReps; ++rep) {
+        for (int rep = 0; made && rep <= kTimedReps; ++rep) {
             if (hipEventRecord(ev0, s) != hipSuccess) break;
-            if (nufft2_setpts(h, n_pts, phi_dev, theta_dev) != NUFFT2_OK || nufft2_exec(h, d_cf, d_out) != NUFFT2_OK)
+            if (g) {
+                if (nufft2_group_setpts(g, g_n.data(), g_phi.data(), g_theta.data()) != NUFFT2_OK ||
+                    nufft2_group_exec(g, g_cf.data(), g_out.data()) != NUFFT2_OK)
+                    break;
+            } else if (nufft2_setpts(hs[0], n_pts, phi_dev, theta_dev) != NUFFT2_OK ||
+                       nufft2_exec(hs[0], d_cf, d_out) != NUFFT2_OK) {
                 break;
+            }
             float t = 0;
             if (hipEventRecord(ev1, s) != hipSuccess || hipEventSynchronize(ev1) != hipSuccess ||
                 hipEventElapsedTime(&t, ev0, ev1) != hipSuccess)
@@ -283,8 +311,11 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
         }
         (void)hipGetLastError();
         // release this candidate's workspaces before the next one
-        (void)nufft2_destroy(h);
-        sc.plans.erase(std::find(sc.plans.begin(), sc.plans.end(), h));
+        if (g) (void)nufft2_group_destroy(g);
+        for (nufft2_handle h : hs) {
+            (void)nufft2_destroy(h);
+            sc.plans.erase(std::find(sc.plans.begin(), sc.plans.end(), h));
+        }
         if ((int)ms.size() != kTimedReps) continue;
         std::sort(ms.begin(), ms.end());
         ++timed;
@@ -330,4 +361,23 @@ NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t K
         (void)write_cache(cache_path, cache);
     }
     return NUFFT2_OK;
+}
+
+}  // namespace
+
+NUFFT2_API nufft2_status nufft2_autotune(nufft2_prec prec, int64_t Kt, int64_t Kp, int32_t n_fields, double eps,
+                                         int64_t n_pts, const double *phi_dev, const double *theta_dev, void *stream,
+                                         const char *cache_path, nufft2_opts *opts_out, nufft2_tune_result *result)
+{
+    return autotune_impl(prec, Kt, Kp, n_fields, eps, n_pts, phi_dev, theta_dev, stream, cache_path, opts_out,
+                         result, 1);
+}
+
+NUFFT2_API nufft2_status nufft2_autotune_group(nufft2_prec prec, int64_t Kt, int64_t Kp, int32_t n_fields,
+                                               double eps, int32_t members, int64_t n_pts, const double *phi_dev,
+                                               const double *theta_dev, void *stream, const char *cache_path,
+                                               nufft2_opts *opts_out, nufft2_tune_result *result)
+{
+    return autotune_impl(prec, Kt, Kp, n_fields, eps, n_pts, phi_dev, theta_dev, stream, cache_path, opts_out,
+                         result, members);
 }

@@ -146,9 +146,12 @@ __device__ inline double real_of(double a) { return a; }
 __device__ inline float real_of(float2 a) { return a.x; }
 __device__ inline double real_of(double2 a) { return a.x; }
 
-// 16-byte vector of the plan's real type (a staging chunk).
-template <typename T> struct VecOf { using type = double2; };
-template <> struct VecOf<float> { using type = float4; };
+// 16-byte vector of the plan's real type (a staging chunk).  Native
+// vector types: a copy is one value, not a struct copy (which the compiler
+// lowers to a memory copy through the stack when a barrier sits between
+// the load and the store).
+template <typename T> struct VecOf { using type = double __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<float> { using type = float __attribute__((ext_vector_type(4))); };
 
 template <typename T, bool RG> struct GridElem { using type = cplx<T>; };
 template <typename T> struct GridElem<T, true> { using type = T; };
@@ -187,6 +190,61 @@ __device__ inline int column_rotation(int it, int ip) { return ((it >> 1) ^ (ip 
 template <int TT, int TP> struct TileShape {
     static constexpr bool fixed = TT > 0;
 };
+
+// Deal the points of the chunk starting at base to lanes: counting-sort
+// them by bank key (patch offset of the first tap plus the column rotation,
+// modulo NK), then give sorted position k to lane (k mod R) * NK + k / R.
+// Points R apart in key order share a lane group, so a group holds distinct
+// keys unless one key has more than R points.  The order inside a key
+// (atomic ranks) does not matter: a point's sum does not depend on its lane.
+// Every thread of the workgroup calls it (it has barriers); it touches only
+// the dealing arrays (bucket, slot, dsts, recs), not the patch.  Chunk 0's
+// records (q0, d0) were loaded by the caller.
+template <typename T, int NK, int NT>
+__device__ __forceinline__ void deal_chunk(int base, int cnt, int start, const PointRec<T> &q0, int d0, int r0,
+                                           int c0, int TCP, const PointRec<T> *__restrict__ rec,
+                                           const int32_t *__restrict__ perm, int *bucket, short *slot, int *dsts,
+                                           PointRec<T> *recs)
+{
+    const int n = min(NT, cnt - base);
+    const int R = (n + NK - 1) / NK;
+    const int t = (int)threadIdx.x;
+    if (t < NK) bucket[t] = 0;
+    slot[t] = -1;
+    __syncthreads();
+    int key = 0, rank = 0;
+    if (t < n) {
+        PointRec<T> q = q0;
+        int d = d0;
+        if (base > 0) {
+            q = rec[start + base + t];
+            d = perm[start + base + t];
+        }
+        dsts[t] = d;
+        recs[t] = q;
+        const bool qbad = !(q.vt == q.vt) || !(q.vp == q.vp);
+        key = qbad ? 0 : ((q.it - r0) * TCP + (q.ip - c0) + column_rotation(q.it, q.ip)) & (NK - 1);
+        rank = atomicAdd(&bucket[key], 1);
+    }
+    __syncthreads();
+    if (t < NK) {
+        // exclusive scan of the NK bucket counts within wave 0
+        const int c = bucket[t];
+        int incl = c;
+#pragma unroll
+        for (int d = 1; d < NK; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (t >= d) incl += y;
+        }
+        bucket[t] = incl - c;
+    }
+    __syncthreads();
+    if (t < n) {
+        const int k = bucket[key] + rank;
+        slot[(k % R) * NK + k / R] = (short)t;
+    }
+    __syncthreads();
+}
 
 // blk: this workgroup's index in the stage (8 * ceil(nbins / 8) of them).
 template <typename T, bool RG, int W, int FG, int TT, int TP>
@@ -229,6 +287,11 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
         d0 = perm[start + (int)threadIdx.x];
     }
     constexpr bool FIXED = TileShape<TT, TP>::fixed;
+    // Chunk 0 is dealt while the patch loads are in flight where that was
+    // measured faster: compile-time tiles (one or two load batches) and
+    // FP64 real grids.  Elsewhere the batches held across the dealing cost
+    // more registers than the overlap gains (FP64 complex: 15% slower).
+    constexpr bool kEarlyDeal = FIXED || (sizeof(T) == 8 && RG);
     const int tile_t = FIXED ? TT : gp.tile_t;
     const int tile_p = FIXED ? TP : gp.tile_p;
     const int bt = bin / gp.nbins_phi, bp = bin - bt * gp.nbins_phi;
@@ -287,6 +350,9 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
                     for (int f = 0; f < FG; ++f) buf[u][f] = *reinterpret_cast<const Vec *>(gridf[f] + off);
                 }
             }
+            // chunk 0's dealing waits only for its records (requested
+            // before the patch), so it runs while the patch is in flight
+            if (kEarlyDeal && j0 == 0) deal_chunk<T, NK, NT>(0, cnt, start, q0, d0, r0, c0, TCP, rec, perm, bucket, slot, dsts, recs);
 #pragma unroll
             for (int u = 0; u < kLoadBatch; ++u) {
                 if (lo[u] >= 0) {
@@ -297,51 +363,9 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
         }
         __syncthreads();
         for (int base = 0; base < cnt; base += NT) {
-            // Deal this chunk's points to lanes: counting-sort them by bank
-            // key (patch offset of the first tap plus the column rotation,
-            // modulo NK), then give sorted position k to lane
-            // (k mod R) * NK + k / R.  Points R apart in key order share a
-            // lane group, so a group holds distinct keys unless one key has
-            // more than R points.  The order inside a key (atomic ranks) does
-            // not matter: a point's sum does not depend on its lane.
+            if (base > 0 || !kEarlyDeal) deal_chunk<T, NK, NT>(base, cnt, start, q0, d0, r0, c0, TCP, rec, perm, bucket, slot, dsts, recs);
             const int n = min(NT, cnt - base);
-            const int R = (n + NK - 1) / NK;
             const int t = (int)threadIdx.x;
-            if (t < NK) bucket[t] = 0;
-            slot[t] = -1;
-            __syncthreads();
-            int key = 0, rank = 0;
-            if (t < n) {
-                PointRec<T> q = q0;
-                int d = d0;
-                if (base > 0) {
-                    q = rec[start + base + t];
-                    d = perm[start + base + t];
-                }
-                dsts[t] = d;
-                recs[t] = q;
-                const bool qbad = !(q.vt == q.vt) || !(q.vp == q.vp);
-                key = qbad ? 0 : ((q.it - r0) * TCP + (q.ip - c0) + column_rotation(q.it, q.ip)) & (NK - 1);
-                rank = atomicAdd(&bucket[key], 1);
-            }
-            __syncthreads();
-            if (t < NK) {
-                // exclusive scan of the NK bucket counts within wave 0
-                const int c = bucket[t];
-                int incl = c;
-#pragma unroll
-                for (int d = 1; d < NK; d <<= 1) {
-                    const int y = __shfl_up(incl, d, 64);
-                    if (t >= d) incl += y;
-                }
-                bucket[t] = incl - c;
-            }
-            __syncthreads();
-            if (t < n) {
-                const int k = bucket[key] + rank;
-                slot[(k % R) * NK + k / R] = (short)t;
-            }
-            __syncthreads();
             // In FP64 a bin of at most half a workgroup's points (one chunk,
             // which the dealing put on the lower half of the lanes) is split
             // by rows: lane t + 128 takes rows H1 .. w-1 of lane t's point

@@ -21,6 +21,7 @@ template <> struct alignas(8) PointRec<double> { int32_t it, ip; double vt, vp; 
 // Coordinate split parameters (one per direction).
 struct AxisParams {
     double to_grid;   // nf / (2 pi)
+    double inv_nf;    // 1 / nf (exact)
     int32_t nf;       // fine grid size (power of two)
     int32_t tile;     // bin tile size along this axis (power of two)
 };

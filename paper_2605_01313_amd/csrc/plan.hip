@@ -701,9 +701,11 @@ SetptsParams nufft2::plan_setpts_params(const nufft2_plan_s *p, int64_t n_pts)
     SetptsParams sp{};
     const double inv_two_pi = 0.15915494309189533576888376337251436;
     sp.th.to_grid = (double)p->nft * inv_two_pi;
+    sp.th.inv_nf = 1.0 / (double)p->nft;
     sp.th.nf = p->nft;
     sp.th.tile = p->tile_t;
     sp.ph.to_grid = (double)p->nfp * inv_two_pi;
+    sp.ph.inv_nf = 1.0 / (double)p->nfp;
     sp.ph.nf = p->nfp;
     sp.ph.tile = p->tile_p;
     sp.w = p->w;

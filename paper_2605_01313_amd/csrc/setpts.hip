@@ -39,7 +39,7 @@ __device__ inline void split_axis(double x, const AxisParams &ax, int w, int32_t
 {
     const double nf = (double)ax.nf;
     double t = x * ax.to_grid;
-    t = t - nf * floor(t / nf);
+    t = t - nf * floor(t * ax.inv_nf);  // 1 / nf is exact: no division
     if (t >= nf) t -= nf;             // t slightly below 0 rounds up to nf
     const double c = ceil(t - 0.5 * (double)w);
     const double u = t - c;
@@ -106,6 +106,15 @@ __device__ inline int32_t wave_aggregated_rank_down(int32_t *__restrict__ bincou
     return __shfl(base, g.leader, 64) + g.offset;
 }
 
+// Bin of a first-tap cell: tiles are powers of two and the cell indices
+// non-negative, so the quotients are shifts (the tile is uniform, its
+// exponent a scalar).
+__device__ inline int32_t bin_of(int32_t it, int32_t ip, const SetptsParams &sp)
+{
+    return (int32_t)((uint32_t)it >> __builtin_ctz((unsigned)sp.th.tile)) * sp.nbins_phi +
+           (int32_t)((uint32_t)ip >> __builtin_ctz((unsigned)sp.ph.tile));
+}
+
 // Wrap/split of one point and its bin (non-finite coordinates: bin 0 and a
 // NaN record).
 template <typename T>
@@ -120,7 +129,7 @@ __device__ inline int32_t split_point(double ph, double th, const SetptsParams &
     }
     split_axis<T>(th, sp.th, sp.w, r.it, r.vt);
     split_axis<T>(ph, sp.ph, sp.w, r.ip, r.vp);
-    return (r.it / sp.th.tile) * sp.nbins_phi + r.ip / sp.ph.tile;
+    return bin_of(r.it, r.ip, sp);
 }
 
 // The pair (p, q) of the matrix Q that takes a vector at departure point D
@@ -173,7 +182,7 @@ __device__ inline void setpts_bin_point(int64_t j, double ph, double th, const S
         T vt, vp;
         split_axis<T>(th, sp.th, sp.w, it, vt);
         split_axis<T>(ph, sp.ph, sp.w, ip, vp);
-        bin = (it / sp.th.tile) * sp.nbins_phi + ip / sp.ph.tile;
+        bin = bin_of(it, ip, sp);
         rowmark[it] = 1;
     }
     if (KR) keyrank[j] = make_int2(bin, wave_aggregated_rank(bincount, bin));

@@ -32,7 +32,8 @@ EXPORTED = (
     "nufft2_get_info", "nufft2_check", "nufft2_set_stream", "nufft2_kernel_params",
     "nufft2_kernel_correction", "nufft2_debug_buffer", "nufft2_profile_enable",
     "nufft2_profile_read", "nufft2_group_create", "nufft2_group_setpts", "nufft2_group_exec",
-    "nufft2_group_destroy", "nufft2_group_get_info", "nufft2_autotune", "nufft2_server_create",
+    "nufft2_group_destroy", "nufft2_group_get_info", "nufft2_autotune", "nufft2_autotune_group",
+    "nufft2_server_create",
     "nufft2_server_clock", "nufft2_server_submit", "nufft2_server_wait", "nufft2_server_drain",
     "nufft2_server_stats", "nufft2_server_destroy", "nufft2_analysis_plan", "nufft2_analysis_exec",
     "nufft2_analysis_destroy", "nufft2_rotate_uv", "nufft2_analysis_set_zonal_filter", "nufft2_analysis_set_layout", "nufft2_pr_plan",
@@ -142,6 +143,8 @@ def _load():
         "nufft2_group_get_info": [H, ctypes.POINTER(nufft2_group_info)],
         "nufft2_autotune": [i32, i64, i64, i32, dbl, i64, vp, vp, vp, ctypes.c_char_p,
                             ctypes.POINTER(nufft2_opts), ctypes.POINTER(nufft2_tune_result)],
+        "nufft2_autotune_group": [i32, i64, i64, i32, dbl, i32, i64, vp, vp, vp, ctypes.c_char_p,
+                                  ctypes.POINTER(nufft2_opts), ctypes.POINTER(nufft2_tune_result)],
         "nufft2_server_create": [ctypes.POINTER(nufft2_server_opts), ctypes.POINTER(H)],
         "nufft2_server_submit": [H, ctypes.POINTER(nufft2_request), ctypes.POINTER(ctypes.c_uint64)],
         "nufft2_server_wait": [H, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(dbl)],
@@ -317,6 +320,20 @@ def nufft2_autotune(prec, n_modes_theta, n_modes_phi, n_fields, eps, n_pts, phi_
                               int(n_pts), ctypes.c_void_p(phi_ptr or None), ctypes.c_void_p(theta_ptr or None),
                               ctypes.c_void_p(stream or None),
                               cache_path.encode() if cache_path else None, ctypes.byref(opts), ctypes.byref(res))
+    return st, opts, res
+
+
+def nufft2_autotune_group(prec, n_modes_theta, n_modes_phi, n_fields, eps, members, n_pts, phi_ptr, theta_ptr,
+                          stream=0, cache_path=None, hermitian=False):
+    """Returns (status, nufft2_opts, nufft2_tune_result)."""
+    opts = nufft2_opts()
+    opts.hermitian = int(bool(hermitian))
+    res = nufft2_tune_result()
+    st = _lib.nufft2_autotune_group(int(prec), int(n_modes_theta), int(n_modes_phi), int(n_fields), float(eps),
+                                    int(members), int(n_pts), ctypes.c_void_p(phi_ptr or None),
+                                    ctypes.c_void_p(theta_ptr or None), ctypes.c_void_p(stream or None),
+                                    cache_path.encode() if cache_path else None, ctypes.byref(opts),
+                                    ctypes.byref(res))
     return st, opts, res
 
 
@@ -687,9 +704,11 @@ class Group:
 
 
 def autotune(prec, n_modes_theta, n_modes_phi, n_fields, eps, phi, theta, cache_path=None, stream=None,
-             hermitian=False):
+             hermitian=False, members=1):
     """Tune width and tiles on the given points (float64 device tensors).
 
+    members > 1: the tiles are timed on a group of that many plans, each
+    with these points (nufft2_autotune_group).
     Returns a dict: w, tile_theta, tile_phi (keyword arguments for Plan) and
     the measurement (err, ms, from_cache, n_timed).
     """
@@ -700,8 +719,13 @@ def autotune(prec, n_modes_theta, n_modes_phi, n_fields, eps, phi, theta, cache_
         if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
             raise TypeError("points must be contiguous float64 device tensors")
     s = stream if stream is not None else torch.cuda.current_stream()
-    st, opts, res = nufft2_autotune(prec_code, n_modes_theta, n_modes_phi, n_fields, eps, phi.numel(),
-                                    phi.data_ptr(), theta.data_ptr(), s.cuda_stream, cache_path, hermitian)
+    if members > 1:
+        st, opts, res = nufft2_autotune_group(prec_code, n_modes_theta, n_modes_phi, n_fields, eps, members,
+                                              phi.numel(), phi.data_ptr(), theta.data_ptr(), s.cuda_stream,
+                                              cache_path, hermitian)
+    else:
+        st, opts, res = nufft2_autotune(prec_code, n_modes_theta, n_modes_phi, n_fields, eps, phi.numel(),
+                                        phi.data_ptr(), theta.data_ptr(), s.cuda_stream, cache_path, hermitian)
     _check(st, "nufft2_autotune")
     out = res.as_dict()
     out.update(w=opts.w, tile_theta=opts.tile_theta, tile_phi=opts.tile_phi)

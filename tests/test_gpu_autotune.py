@@ -105,3 +105,49 @@ def test_autotune_at_the_fp32_floor_meets_eps_or_says_it_cannot(torch_dev, tmp_p
         assert st == nufft2.NUFFT2_ERR_EPS_RANGE
         assert res.err > 1e-7 and res.w >= 8
         assert not os.path.exists(cache) or "eps1.000e-07" not in open(cache).read()
+
+
+def test_autotune_group_times_tiles_on_a_group(torch_dev, oracle_mod, tmp_path):
+    """nufft2_autotune_group: the same width as the single-plan tuner (the
+    width search does not depend on members), a tile from the candidate
+    list timed on a group of 6 plans, a cache entry of its own (key with
+    _m6), and a group of plans with the tuned options meets the oracle."""
+    torch, dev = torch_dev
+    from paper_2605_01313_amd import Group, Plan, autotune, nufft2
+    say("case autotune_group fp32 J=64 members=6 real-field")
+    spec = synth.ensemble_members(n_small=1, n_large=0, J_small=64)[0]
+    wl = synth.ensemble_member(spec, n_fields=3)
+    K = wl.coeffs.shape[-1]
+    phi = torch.from_numpy(wl.phi).to(dev)
+    theta = torch.from_numpy(wl.theta).to(dev)
+    cache = str(tmp_path / "tune.json")
+    r1 = autotune("fp32", K, K, 3, 1e-6, phi, theta, cache_path=cache, hermitian=True)
+    rg = autotune("fp32", K, K, 3, 1e-6, phi, theta, cache_path=cache, hermitian=True, members=6)
+    say(f"  single {r1}\n  group  {rg}")
+    assert rg["w"] == r1["w"] and rg["err"] == r1["err"]
+    assert (rg["tile_theta"], rg["tile_phi"]) in TILES
+    assert rg["from_cache"] == 0 and rg["n_timed"] >= 3 and rg["ms"] > 0
+    with open(cache) as f:
+        keys = [e["key"] for e in json.load(f)["nufft2_autotune"]]
+    assert len(keys) == 2 and sum("_m6_" in k for k in keys) == 1
+    rg2 = autotune("fp32", K, K, 3, 1e-6, phi, theta, cache_path=cache, hermitian=True, members=6)
+    assert rg2["from_cache"] == 1 and (rg2["tile_theta"], rg2["tile_phi"]) == (rg["tile_theta"], rg["tile_phi"])
+    plans = [Plan("fp32", K, K, n_fields=3, eps=1e-6, w=rg["w"], tile_theta=rg["tile_theta"],
+                  tile_phi=rg["tile_phi"], hermitian=True) for _ in range(2)]
+    g = Group(plans)
+    g.setpts([phi, phi], [theta, theta])
+    c = torch.from_numpy(wl.coeffs).to(dev).to(torch.complex64)
+    outs = [o.cpu().numpy() for o in g.exec([c, c])]
+    sel = synth.sample_indices(wl.n_pts, 1000)
+    ref = oracle_mod.dfs_eval(wl.coeffs, wl.phi[sel], wl.theta[sel]).real
+    for o in outs:
+        err = max(float(np.linalg.norm(o[f, sel] - ref[f]) / np.linalg.norm(ref[f])) for f in range(3))
+        assert err <= 1e-6, err
+    g.destroy()
+    for p in plans:
+        p.destroy()
+    # argument checks (before any device work)
+    x = torch.zeros(8, dtype=torch.float64, device=dev)
+    for members, n in ((0, 8), (4097, 8), (2, 1 << 30)):
+        st, _, _ = nufft2.nufft2_autotune_group(1, 63, 63, 1, 1e-6, members, n, x.data_ptr(), x.data_ptr())
+        assert st == nufft2.NUFFT2_ERR_ARG, (members, n)
