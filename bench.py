@@ -476,7 +476,7 @@ def ensemble_bench(args, torch, steps, warmup):
     """Uneven ensemble: 64 members on 128x256 grids + 16 on 256x512, 3 fields
     each, own seed, spectrum and 8-mode wind; FP32 eps 1e-6 real-field plans
     (the fields are real), width and tiles from the autotuner; every step is
-    one group setpts + one group exec (two graph launches).  Compared with the plain path on the same GPU: FP64
+    one group run: setpts and exec of all members as one graph launch.  Compared with the plain path on the same GPU: FP64
     eps 1e-12, one field per exec, synchronised after every exec."""
     import tempfile
 
@@ -513,8 +513,7 @@ def ensemble_bench(args, torch, steps, warmup):
     n_pf = sum(F * m.n_pts for m in members)
 
     def step():
-        g.setpts(phis, thetas)
-        g.exec(coeffs, outs)
+        g.run(phis, thetas, coeffs, outs)   # setpts + exec: one graph launch
 
     for _ in range(max(warmup, 1)):
         step()
@@ -579,7 +578,7 @@ def ensemble_bench(args, torch, steps, warmup):
         "config": {"members": len(members), "points_x_fields": n_pf, "eps": 1e-6,
                    "tuned": {str(k): v for k, v in tuned.items()}, "classes": info["n_classes"],
                    "kernels_per_step": info["setpts_kernels"] + info["exec_kernels"],
-                   "step": "group setpts + group exec (two graph launches)"},
+                   "step": "group run: setpts + exec of all members as one graph launch (classes as parallel branches)"},
         "latency_ms": {"p50": pct(0.5), "p99": pct(0.99)},
         "plain_fp64_single_field": {"value": n_pf / (ms64 * 1e-3), "unit": "points*fields/s",
                                     "ms_per_step": ms64, "eps": 1e-12,

@@ -283,14 +283,17 @@ nufft2_status nufft2_profile_read(nufft2_handle p, double *total_ms, int64_t *co
  * kernel width and shape, tiles and output kind form a class; a group runs
  * each setpts kernel once per precision over all members' points, and each
  * exec stage once per class over all of the class's members, as
- * segmented launches captured in one HIP graph per call type.  Results are
+ * segmented launches captured in one HIP graph per call type; in the exec
+ * graph the classes are parallel branches (up to 4, on side streams the
+ * group owns), so one class's kernels overlap another's.  Results are
  * bit-identical to running every plan on its own.
  *
  * nufft2_group_create -- group the n distinct plans (host array of handles).
  *   All plans must use the same stream and device; the group keeps pointers
  *   to them, and they must outlive the group.  The group owns a stream of
  *   its own (ordered after and before the plans' stream with events, so
- *   calls keep the plans' stream order) and small device tables.
+ *   calls keep the plans' stream order), up to three side streams for the
+ *   exec branches (default priority) and small device tables.
  *   Errors: ERR_ARG (n < 1, null or repeated plan, mixed streams or
  *   devices), ERR_ALLOC, ERR_HIP.
  * nufft2_group_setpts -- nufft2_setpts for every member: n_pts[i] points at
@@ -304,6 +307,12 @@ nufft2_status nufft2_profile_read(nufft2_handle p, double *total_ms, int64_t *co
  *   of the same kind rewrites the group's tables (it first waits for the
  *   group's earlier work); a change of the total point count also
  *   re-captures the setpts graph.
+ * nufft2_group_run -- nufft2_group_setpts then nufft2_group_exec as one
+ *   graph launch (every setpts and exec kernel of the group in one HIP
+ *   graph, captured on first use and again when the setpts launches change
+ *   shape), from one host call: the GPU does not wait for the host between
+ *   the two.  Arguments and errors as the two calls; on an error nothing is
+ *   launched and the members keep their previous points.
  * nufft2_group_destroy -- synchronise and free the group (not the plans).
  * nufft2_group_get_info -- members, classes and the kernels per graph.
  */
@@ -320,6 +329,8 @@ nufft2_status nufft2_group_create(const nufft2_handle *plans, int32_t n, nufft2_
 nufft2_status nufft2_group_setpts(nufft2_group g, const int64_t *n_pts, const double *const *phi_dev,
                                   const double *const *theta_dev);
 nufft2_status nufft2_group_exec(nufft2_group g, const void *const *coeffs_dev, void *const *out_dev);
+nufft2_status nufft2_group_run(nufft2_group g, const int64_t *n_pts, const double *const *phi_dev,
+                               const double *const *theta_dev, const void *const *coeffs_dev, void *const *out_dev);
 nufft2_status nufft2_group_destroy(nufft2_group g);
 nufft2_status nufft2_group_get_info(nufft2_group g, nufft2_group_info *info);
 

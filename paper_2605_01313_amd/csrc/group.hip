@@ -2,14 +2,16 @@
 // graphs.  setpts: per precision, one point-binning launch over every
 // member's points, one scan launch (a workgroup per member), one scatter
 // launch.  exec: per class of identically shaped members, one theta-pass,
-// one phi-pass and one gather launch over all of the class's members.  The
-// kernels find their member in device tables that the host rewrites only
+// one phi-pass and one gather launch over all of the class's members, the
+// classes as parallel branches of the exec graph.  The kernels find their
+// member in device tables that the host rewrites only
 // when a pointer or a point count changes; the graphs hold the launches and
 // are captured once (the setpts graph again when the total point count
 // changes).
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -69,14 +71,27 @@ inline uint64_t sig_of(const void *q) { return (uint64_t)(uintptr_t)q; }
 
 }  // namespace
 
+// Exec classes are independent (disjoint members), so the exec graph runs
+// them as parallel branches: class c on branch c mod kExecBranches, branch 0
+// on the group's stream, the others on side streams forked from it and
+// joined back inside the capture.  A class's kernels then fill the tails and
+// launch gaps of another's.
+constexpr int kExecBranches = 4;
+
 struct nufft2_group_s {
     std::vector<nufft2_plan_s *> m;
     hipStream_t user_stream = nullptr;  // the members' stream
     hipStream_t stream = nullptr;       // the group's own (capturable) stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<hipStream_t> side;      // exec branches 1.. (default priority)
+    std::vector<hipEvent_t> ev_join;    // one per side stream
+    hipEvent_t ev_fork = nullptr;
     std::vector<ExecClass> classes;
     std::vector<PointSet> sets;
-    hipGraphExec_t g_setpts = nullptr, g_exec = nullptr;
+    hipGraphExec_t g_setpts = nullptr, g_exec = nullptr, g_run = nullptr;
+    // shape of the setpts launches: bumped whenever they change; a graph
+    // holding them is captured again when its version differs
+    uint64_t setpts_version = 1, g_setpts_version = 0, g_run_version = 0;
     Signature setpts_sig, exec_sig;  // of the tables on the device
     int setpts_kernels = 0, exec_kernels = 0;
     size_t table_bytes = 0;
@@ -115,6 +130,7 @@ void group_free(nufft2_group_s *g)
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     if (g->g_setpts) (void)hipGraphExecDestroy(g->g_setpts);
     if (g->g_exec) (void)hipGraphExecDestroy(g->g_exec);
+    if (g->g_run) (void)hipGraphExecDestroy(g->g_run);
     for (auto &c : g->classes) {
         if (c.d_theta) (void)hipFree(c.d_theta);
         if (c.d_phi) (void)hipFree(c.d_phi);
@@ -126,6 +142,11 @@ void group_free(nufft2_group_s *g)
     }
     if (g->ev_in) (void)hipEventDestroy(g->ev_in);
     if (g->ev_out) (void)hipEventDestroy(g->ev_out);
+    if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+    for (hipEvent_t ev : g->ev_join)
+        if (ev) (void)hipEventDestroy(ev);
+    for (hipStream_t st : g->side)
+        if (st) (void)hipStreamDestroy(st);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
 }
@@ -225,6 +246,24 @@ NUFFT2_API nufft2_status nufft2_group_create(const nufft2_handle *plans, int32_t
         group_free(g);
         return NUFFT2_ERR_HIP;
     }
+    const int n_side = std::min((int)g->classes.size(), kExecBranches) - 1;
+    if (n_side > 0 && (e = hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming)) != hipSuccess) {
+        (void)hipGetLastError();
+        group_free(g);
+        return NUFFT2_ERR_HIP;
+    }
+    for (int b = 0; b < n_side; ++b) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) == hipSuccess) g->side.push_back(st);
+        if (e == hipSuccess && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) == hipSuccess)
+            g->ev_join.push_back(ev);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            group_free(g);
+            return NUFFT2_ERR_HIP;
+        }
+    }
     bool ok = true;
     for (auto &c : g->classes) {
         const size_t k = c.members.size();
@@ -241,10 +280,15 @@ NUFFT2_API nufft2_status nufft2_group_create(const nufft2_handle *plans, int32_t
     return NUFFT2_OK;
 }
 
-NUFFT2_API nufft2_status nufft2_group_setpts(nufft2_group g, const int64_t *n_pts, const double *const *phi_dev,
-                                             const double *const *theta_dev)
+namespace {
+
+// setpts, host side: argument checks, point workspaces, the device tables
+// (rewritten when a pointer or a count changed).  A change of the setpts
+// launches' shape bumps setpts_version.
+nufft2_status prepare_setpts(nufft2_group_s *g, const int64_t *n_pts, const double *const *phi_dev,
+                             const double *const *theta_dev)
 {
-    if (!g || !n_pts || !phi_dev || !theta_dev) return NUFFT2_ERR_ARG;
+    if (!n_pts || !phi_dev || !theta_dev) return NUFFT2_ERR_ARG;
     const int n = (int)g->m.size();
     for (int i = 0; i < n; ++i) {
         if (n_pts[i] < 0 || n_pts[i] > (int64_t)0x7fffffff) return NUFFT2_ERR_ARG;
@@ -262,7 +306,7 @@ NUFFT2_API nufft2_status nufft2_group_setpts(nufft2_group g, const int64_t *n_pt
                                sig_of(p->rec), sig_of(p->perm)});
     }
     const bool rewrite = sig != g->setpts_sig;
-    bool recapture = g->g_setpts == nullptr;
+    bool recap = false;
     for (auto &s : g->sets) {
         std::vector<SetptsJob> jobs;
         std::vector<int32_t> owner;
@@ -291,13 +335,13 @@ NUFFT2_API nufft2_status nufft2_group_setpts(nufft2_group g, const int64_t *n_pt
             jobs.push_back(J);
         }
         if (blocks > (int64_t)0x7fffffff) return NUFFT2_ERR_ARG;
-        if (blocks != s.n_blocks) recapture = true;
+        if (blocks != s.n_blocks) recap = true;
         s.h_jobs.swap(jobs);
         s.h_job_of_block.swap(owner);
         s.n_blocks = blocks;
     }
     hipError_t e;
-    if (rewrite || recapture) {
+    if (rewrite || recap) {
         // earlier launches of the group may still read the tables
         if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return group_fail(g, e);
         for (auto &s : g->sets) {
@@ -305,7 +349,7 @@ NUFFT2_API nufft2_status nufft2_group_setpts(nufft2_group g, const int64_t *n_pt
                 if (s.d_job_of_block) (void)hipFree(s.d_job_of_block);
                 s.d_job_of_block = nullptr;
                 s.block_cap = 0;
-                recapture = true;
+                recap = true;
                 if (!table_alloc(g, &s.d_job_of_block, (size_t)s.n_blocks)) return NUFFT2_ERR_ALLOC;
                 s.block_cap = s.n_blocks;
             }
@@ -319,35 +363,35 @@ NUFFT2_API nufft2_status nufft2_group_setpts(nufft2_group g, const int64_t *n_pt
         }
         g->setpts_sig = sig;
     }
-    if (recapture) {
-        if (g->g_setpts) (void)hipGraphExecDestroy(g->g_setpts);
-        g->g_setpts = nullptr;
-        e = capture(g, &g->g_setpts, [&]() {
-            for (auto &s : g->sets) {
-                hipError_t es = launch_setpts_group(s.prec, s.d_jobs, (int)s.members.size(), s.d_job_of_block,
-                                                    (int)s.n_blocks, g->stream);
-                if (es != hipSuccess) return es;
-            }
-            return hipSuccess;
-        });
-        if (e != hipSuccess) {
-            g->g_setpts = nullptr;
-            return group_fail(g, e);
-        }
-    }
-    if ((e = enter(g)) != hipSuccess || (e = hipGraphLaunch(g->g_setpts, g->stream)) != hipSuccess ||
-        (e = leave(g)) != hipSuccess)
-        return group_fail(g, e);
-    for (int i = 0; i < n; ++i) {
-        g->m[i]->n_pts = n_pts[i];
-        g->m[i]->rot_u = g->m[i]->rot_v = -1;  // group setpts does not rotate
-    }
+    if (recap) ++g->setpts_version;
     return NUFFT2_OK;
 }
 
-NUFFT2_API nufft2_status nufft2_group_exec(nufft2_group g, const void *const *coeffs_dev, void *const *out_dev)
+// The setpts launches, on the group's stream.
+hipError_t issue_setpts(nufft2_group_s *g)
 {
-    if (!g || !coeffs_dev || !out_dev) return NUFFT2_ERR_ARG;
+    for (auto &s : g->sets) {
+        hipError_t es = launch_setpts_group(s.prec, s.d_jobs, (int)s.members.size(), s.d_job_of_block,
+                                            (int)s.n_blocks, g->stream);
+        if (es != hipSuccess) return es;
+    }
+    return hipSuccess;
+}
+
+// After setpts: the members' point counts; group setpts does not rotate.
+void commit_setpts(nufft2_group_s *g, const int64_t *n_pts)
+{
+    for (size_t i = 0; i < g->m.size(); ++i) {
+        g->m[i]->n_pts = n_pts[i];
+        g->m[i]->rot_u = g->m[i]->rot_v = -1;
+    }
+}
+
+// exec, host side: argument checks and the device tables (rewritten when a
+// pointer or a point count changed; the graph launches stay the same).
+nufft2_status prepare_exec(nufft2_group_s *g, const void *const *coeffs_dev, void *const *out_dev)
+{
+    if (!coeffs_dev || !out_dev) return NUFFT2_ERR_ARG;
     const int n = (int)g->m.size();
     for (int i = 0; i < n; ++i) {
         if (g->m[i]->n_pts < 0) return NUFFT2_ERR_NO_POINTS;
@@ -412,27 +456,129 @@ NUFFT2_API nufft2_status nufft2_group_exec(nufft2_group g, const void *const *co
         }
         g->exec_sig = sig;
     }
+    return NUFFT2_OK;
+}
+
+// The exec launches: every class's theta pass, phi pass and gather, the
+// classes as parallel branches forked from the group's stream and joined
+// back into it.
+hipError_t issue_exec(nufft2_group_s *g)
+{
+    // fork: the side streams join the capture by waiting on an event of
+    // the captured stream
+    hipError_t es = hipSuccess;
+    if (!g->side.empty()) es = hipEventRecord(g->ev_fork, g->stream);
+    for (size_t b = 0; es == hipSuccess && b < g->side.size(); ++b) es = hipStreamWaitEvent(g->side[b], g->ev_fork, 0);
+    for (size_t ci = 0; es == hipSuccess && ci < g->classes.size(); ++ci) {
+        const ExecClass &c = g->classes[ci];
+        const int br = (int)(ci % (g->side.size() + 1));
+        hipStream_t st = br == 0 ? g->stream : g->side[br - 1];
+        const nufft2_plan_s *p = g->m[c.members[0]];
+        const int k = (int)c.members.size();
+        const FFTParams cfp = class_fft_params(g, c);
+        es = launch_theta_group(c.prec, cfp, c.d_theta, k, st);
+        if (es == hipSuccess) es = launch_phi_group(c.prec, cfp, c.d_phi, k, st);
+        if (es == hipSuccess) es = launch_gather_group(c.prec, plan_gather_params(p), c.d_gather, k, st);
+    }
+    // join every side stream back (also after an error, so that a capture
+    // can end)
+    for (size_t b = 0; b < g->side.size(); ++b) {
+        hipError_t ej = hipEventRecord(g->ev_join[b], g->side[b]);
+        if (ej == hipSuccess) ej = hipStreamWaitEvent(g->stream, g->ev_join[b], 0);
+        if (es == hipSuccess) es = ej;
+    }
+    return es;
+}
+
+// Launch a graph between the members' stream's earlier and later work.
+nufft2_status launch_graph(nufft2_group_s *g, hipGraphExec_t exec)
+{
+    hipError_t e;
+    if ((e = enter(g)) != hipSuccess || (e = hipGraphLaunch(exec, g->stream)) != hipSuccess ||
+        (e = leave(g)) != hipSuccess)
+        return group_fail(g, e);
+    return NUFFT2_OK;
+}
+
+}  // namespace
+
+NUFFT2_API nufft2_status nufft2_group_setpts(nufft2_group g, const int64_t *n_pts, const double *const *phi_dev,
+                                             const double *const *theta_dev)
+{
+    if (!g) return NUFFT2_ERR_ARG;
+    nufft2_status st = prepare_setpts(g, n_pts, phi_dev, theta_dev);
+    if (st != NUFFT2_OK) return st;
+    if (!g->g_setpts || g->g_setpts_version != g->setpts_version) {
+        if (g->g_setpts) (void)hipGraphExecDestroy(g->g_setpts);
+        g->g_setpts = nullptr;
+        hipError_t e = capture(g, &g->g_setpts, [&]() { return issue_setpts(g); });
+        if (e != hipSuccess) {
+            g->g_setpts = nullptr;
+            return group_fail(g, e);
+        }
+        g->g_setpts_version = g->setpts_version;
+    }
+    if ((st = launch_graph(g, g->g_setpts)) != NUFFT2_OK) return st;
+    commit_setpts(g, n_pts);
+    return NUFFT2_OK;
+}
+
+NUFFT2_API nufft2_status nufft2_group_exec(nufft2_group g, const void *const *coeffs_dev, void *const *out_dev)
+{
+    if (!g) return NUFFT2_ERR_ARG;
+    nufft2_status st = prepare_exec(g, coeffs_dev, out_dev);
+    if (st != NUFFT2_OK) return st;
     if (!g->g_exec) {
-        e = capture(g, &g->g_exec, [&]() {
-            for (auto &c : g->classes) {
-                const nufft2_plan_s *p = g->m[c.members[0]];
-                const int k = (int)c.members.size();
-                const FFTParams cfp = class_fft_params(g, c);
-                hipError_t es = launch_theta_group(c.prec, cfp, c.d_theta, k, g->stream);
-                if (es == hipSuccess) es = launch_phi_group(c.prec, cfp, c.d_phi, k, g->stream);
-                if (es == hipSuccess) es = launch_gather_group(c.prec, plan_gather_params(p), c.d_gather, k, g->stream);
-                if (es != hipSuccess) return es;
-            }
-            return hipSuccess;
-        });
+        hipError_t e = capture(g, &g->g_exec, [&]() { return issue_exec(g); });
         if (e != hipSuccess) {
             g->g_exec = nullptr;
             return group_fail(g, e);
         }
     }
-    if ((e = enter(g)) != hipSuccess || (e = hipGraphLaunch(g->g_exec, g->stream)) != hipSuccess ||
-        (e = leave(g)) != hipSuccess)
-        return group_fail(g, e);
+    return launch_graph(g, g->g_exec);
+}
+
+NUFFT2_API nufft2_status nufft2_group_run(nufft2_group g, const int64_t *n_pts, const double *const *phi_dev,
+                                          const double *const *theta_dev, const void *const *coeffs_dev,
+                                          void *const *out_dev)
+{
+    if (!g || !n_pts || !phi_dev || !theta_dev || !coeffs_dev || !out_dev) return NUFFT2_ERR_ARG;
+    const int n = (int)g->m.size();
+    for (int i = 0; i < n; ++i)
+        if (!coeffs_dev[i] || !out_dev[i]) return NUFFT2_ERR_ARG;
+    nufft2_status st = prepare_setpts(g, n_pts, phi_dev, theta_dev);
+    if (st != NUFFT2_OK) return st;
+    // the exec tables take the new point counts (and workspaces)
+    std::vector<int64_t> old(n);
+    for (int i = 0; i < n; ++i) {
+        old[i] = g->m[i]->n_pts;
+        g->m[i]->n_pts = n_pts[i];
+    }
+    st = prepare_exec(g, coeffs_dev, out_dev);
+    if (st != NUFFT2_OK) {
+        for (int i = 0; i < n; ++i) g->m[i]->n_pts = old[i];
+        return st;
+    }
+    if (!g->g_run || g->g_run_version != g->setpts_version) {
+        if (g->g_run) (void)hipGraphExecDestroy(g->g_run);
+        g->g_run = nullptr;
+        hipError_t e = capture(g, &g->g_run, [&]() {
+            hipError_t es = issue_setpts(g);
+            return es == hipSuccess ? issue_exec(g) : es;
+        });
+        if (e != hipSuccess) {
+            g->g_run = nullptr;
+            for (int i = 0; i < n; ++i) g->m[i]->n_pts = old[i];
+            return group_fail(g, e);
+        }
+        g->g_run_version = g->setpts_version;
+    }
+    st = launch_graph(g, g->g_run);
+    if (st != NUFFT2_OK) {
+        for (int i = 0; i < n; ++i) g->m[i]->n_pts = old[i];
+        return st;
+    }
+    commit_setpts(g, n_pts);
     return NUFFT2_OK;
 }
 

@@ -31,7 +31,7 @@ EXPORTED = (
     "nufft2_plan", "nufft2_setpts", "nufft2_setpts_vector", "nufft2_exec", "nufft2_destroy", "nufft2_strerror",
     "nufft2_get_info", "nufft2_check", "nufft2_set_stream", "nufft2_kernel_params",
     "nufft2_kernel_correction", "nufft2_debug_buffer", "nufft2_profile_enable",
-    "nufft2_profile_read", "nufft2_group_create", "nufft2_group_setpts", "nufft2_group_exec",
+    "nufft2_profile_read", "nufft2_group_create", "nufft2_group_setpts", "nufft2_group_exec", "nufft2_group_run",
     "nufft2_group_destroy", "nufft2_group_get_info", "nufft2_autotune", "nufft2_autotune_group",
     "nufft2_server_create",
     "nufft2_server_clock", "nufft2_server_submit", "nufft2_server_wait", "nufft2_server_drain",
@@ -139,6 +139,7 @@ def _load():
         "nufft2_group_create": [vp, i32, ctypes.POINTER(H)],
         "nufft2_group_setpts": [H, vp, vp, vp],
         "nufft2_group_exec": [H, vp, vp],
+        "nufft2_group_run": [H, vp, vp, vp, vp, vp],
         "nufft2_group_destroy": [H],
         "nufft2_group_get_info": [H, ctypes.POINTER(nufft2_group_info)],
         "nufft2_autotune": [i32, i64, i64, i32, dbl, i64, vp, vp, vp, ctypes.c_char_p,
@@ -298,6 +299,12 @@ def nufft2_group_setpts(group, n_pts, phi_ptrs, theta_ptrs):
 
 def nufft2_group_exec(group, coeffs_ptrs, out_ptrs):
     return _lib.nufft2_group_exec(group, _ptr_array(coeffs_ptrs), _ptr_array(out_ptrs))
+
+
+def nufft2_group_run(group, n_pts, phi_ptrs, theta_ptrs, coeffs_ptrs, out_ptrs):
+    n = (ctypes.c_int64 * len(n_pts))(*[int(x) for x in n_pts])
+    return _lib.nufft2_group_run(group, n, _ptr_array(phi_ptrs), _ptr_array(theta_ptrs), _ptr_array(coeffs_ptrs),
+                                 _ptr_array(out_ptrs))
 
 
 def nufft2_group_destroy(group):
@@ -633,6 +640,7 @@ class Group:
     >>> g = Group([p0, p1, ...])                 # Plan objects on one stream
     >>> g.setpts([phi0, phi1, ...], [theta0, ...])
     >>> outs = g.exec([c0, c1, ...])             # list of output tensors
+    >>> outs = g.run(phis, thetas, coeffs)       # both as one graph launch
     """
 
     def __init__(self, plans):
@@ -648,7 +656,7 @@ class Group:
         _check(st, "nufft2_group_get_info")
         return info.as_dict()
 
-    def setpts(self, phis, thetas):
+    def _points_args(self, phis, thetas):
         t = self._torch
         if len(phis) != len(self.plans) or len(thetas) != len(self.plans):
             raise ValueError("one (phi, theta) pair per member")
@@ -658,14 +666,10 @@ class Group:
         ns = [x.numel() for x in phis]
         if any(a.numel() != b for a, b in zip(thetas, ns)):
             raise ValueError("phi and theta differ in length")
-        _check(nufft2_group_setpts(self.handle, ns, [x.data_ptr() if x.numel() else 0 for x in phis],
-                                   [x.data_ptr() if x.numel() else 0 for x in thetas]),
-               "nufft2_group_setpts")
-        for p, n, a, b in zip(self.plans, ns, phis, thetas):
-            p.n_pts = n
-            p._pts = (a, b)
+        return ns, [x.data_ptr() if x.numel() else 0 for x in phis], [x.data_ptr() if x.numel() else 0 for x in thetas]
 
-    def exec(self, coeffs, outs=None):
+    def _exec_args(self, coeffs, outs, ns):
+        """Checked coefficient tensors and outputs for point counts ns."""
         t = self._torch
         if len(coeffs) != len(self.plans):
             raise ValueError("one coefficient tensor per member")
@@ -675,21 +679,45 @@ class Group:
             # one element at least per field, so that every member has a
             # device pointer (the C call takes none null)
             outs = []
-            for p, c in zip(self.plans, coeffs):
+            for p, c, n in zip(self.plans, coeffs, ns):
                 dt = p.rdtype if p.real_output else p.cdtype
-                outs.append(t.empty((p.shape[0], max(p.n_pts, 1)), dtype=dt, device=c.device))
+                outs.append(t.empty((p.shape[0], max(n, 1)), dtype=dt, device=c.device))
         else:
             if len(outs) != len(self.plans):
                 raise ValueError("one output tensor per member")
-            for p, o in zip(self.plans, outs):
-                if p.n_pts > 0:
-                    p._check_out(o, p.n_pts)
+            for p, o, n in zip(self.plans, outs, ns):
+                if n > 0:
+                    p._check_out(o, n)
                 elif not o.is_cuda:
                     raise ValueError("outputs must be device tensors")
+        return outs
+
+    def setpts(self, phis, thetas):
+        ns, pp, tp = self._points_args(phis, thetas)
+        _check(nufft2_group_setpts(self.handle, ns, pp, tp), "nufft2_group_setpts")
+        for p, n, a, b in zip(self.plans, ns, phis, thetas):
+            p.n_pts = n
+            p._pts = (a, b)
+
+    def exec(self, coeffs, outs=None):
+        ns = [p.n_pts for p in self.plans]
+        outs = self._exec_args(coeffs, outs, ns)
         _check(nufft2_group_exec(self.handle, [c.data_ptr() for c in coeffs],
                                  [o.data_ptr() for o in outs]), "nufft2_group_exec")
         self._keep = (coeffs, outs)
         return [o[:, :p.n_pts] for o, p in zip(outs, self.plans)]
+
+    def run(self, phis, thetas, coeffs, outs=None):
+        """setpts then exec as one graph launch (nufft2_group_run)."""
+        ns, pp, tp = self._points_args(phis, thetas)
+        outs = self._exec_args(coeffs, outs, ns)
+        _check(nufft2_group_run(self.handle, ns, pp, tp, [c.data_ptr() for c in coeffs],
+                                [o.data_ptr() for o in outs]), "nufft2_group_run")
+        for p, n, a, b in zip(self.plans, ns, phis, thetas):
+            p.n_pts = n
+            p._pts = (a, b)
+        self._keep = (coeffs, outs)
+        return [o[:, :n] for o, n in zip(outs, ns)]
 
     def destroy(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -217,3 +217,43 @@ def test_large_member_emptied_and_refilled(torch_dev, oracle_mod):
     g.destroy()
     big.destroy()
     small.destroy()
+
+
+def test_group_run_one_graph_equals_setpts_then_exec(torch_dev):
+    """nufft2_group_run (setpts + exec in one graph launch) gives the
+    outputs of the two calls bit for bit: first call, replays with eager
+    work between them, a change of point counts (the combined graph is
+    captured again) and the separate calls interleaved with it."""
+    torch, dev = torch_dev
+    say("case group_run")
+    plans, g = build(torch_dev)
+    for seed, scale in ((21, 1.0), (22, 1.0), (23, 0.6)):
+        data = make_inputs(seed)
+        if scale != 1.0:
+            data = [(c, p[: int(len(p) * scale)], t[: int(len(t) * scale)]) for c, p, t in data]
+        devin = [to_dev(torch, dev, m[0], *d) for m, d in zip(MEMBERS, data)]
+        phis, thetas, coeffs = [x[1] for x in devin], [x[2] for x in devin], [x[0] for x in devin]
+        ns = [len(d[1]) for d in data]
+        g.setpts(phis, thetas)
+        ref = [o.clone() for o in g.exec(coeffs)]
+        torch.cuda.synchronize()
+        scratch = torch.randn(1 << 20, device=dev)
+        outs = [torch.empty((F, max(n, 1)), dtype=c.dtype, device=dev)
+                for (prec, K, F, _, eps), c, n in zip(MEMBERS, coeffs, ns)]
+        for rep in range(3):
+            scratch.mul_(1.0001).add_(0.5)          # unrelated eager work
+            for o in outs:
+                o.zero_()
+            got = g.run(phis, thetas, coeffs, outs)
+            torch.cuda.synchronize()
+            for i, (a, b) in enumerate(zip(got, ref)):
+                assert a.shape == b.shape == (MEMBERS[i][2], ns[i])
+                assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), (seed, rep, i)
+            assert all(p.n_pts == n for p, n in zip(plans, ns))
+    # errors leave nothing launched: a null coefficient pointer
+    from paper_2605_01313_amd import nufft2
+    n_pts = [p.n_pts for p in plans]
+    st = nufft2.nufft2_group_run(g.handle, n_pts, [x.data_ptr() for x in phis], [x.data_ptr() for x in thetas],
+                                 [0] * len(plans), [o.data_ptr() for o in outs])
+    assert st == nufft2.NUFFT2_ERR_ARG
+    g.destroy()
