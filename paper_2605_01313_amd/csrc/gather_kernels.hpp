@@ -201,7 +201,7 @@ template <int TT, int TP> struct TileShape {
 // the dealing arrays (bucket, slot, dsts, recs), not the patch.  Chunk 0's
 // records (q0, d0) were loaded by the caller.
 template <typename T, int NK, int NT>
-__device__ __forceinline__ void deal_chunk(int base, int cnt, int start, const PointRec<T> &q0, int d0, int r0,
+__device__ __forceinline__ void deal_chunk(int base, int cnt, int start, PointRec<T> q0, int d0, int r0,
                                            int c0, int TCP, const PointRec<T> *__restrict__ rec,
                                            const int32_t *__restrict__ perm, int *bucket, short *slot, int *dsts,
                                            PointRec<T> *recs)

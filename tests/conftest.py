@@ -31,3 +31,12 @@ def wind_large_ref(oracle_mod):
     idx = synth.sample_indices(wl.n_pts, 10000, seed=15)
     ref = oracle_mod.dfs_eval(wl.coeffs, wl.phi[idx], wl.theta[idx])
     return wl, idx, ref
+
+
+@pytest.fixture(scope="session")
+def sbr_full_ref(oracle_mod):
+    """The 256 x 512 solid-body-rotation workload (3 fields, 131,072 points)
+    with the oracle at every point: (workload, oracle values [3][131072])."""
+    import synth
+    wl = synth.workload_sbr()
+    return wl, oracle_mod.dfs_eval(wl.coeffs, wl.phi, wl.theta)

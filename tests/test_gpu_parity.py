@@ -164,20 +164,14 @@ def test_fft_stage_matches_numpy(torch_dev, prec):
 # --------------------------------------------------------------------------
 # Moderate resolution (256 x 512, solid-body rotation), sampled points
 # --------------------------------------------------------------------------
-@pytest.fixture(scope="module")
-def sbr_workload():
-    return synth.workload_sbr()
-
-
 @pytest.mark.parametrize("prec,eps,tol", [("fp64", 1e-12, 1e-12), ("fp32", 1e-6, 1e-6)])
-def test_sbr_workload_sampled(torch_dev, oracle_mod, sbr_workload, prec, eps, tol):
-    wl = sbr_workload
-    say(f"case sbr prec={prec} P={wl.n_pts} F={wl.n_fields}")
+def test_sbr_workload_full(torch_dev, sbr_full_ref, prec, eps, tol):
+    """Every one of the 131,072 points of the 256 x 512 workload, 3 fields."""
+    wl, ref = sbr_full_ref
+    say(f"case sbr prec={prec} P={wl.n_pts} F={wl.n_fields} (all points)")
     plan, got = run_plan(torch_dev, prec, wl.coeffs, wl.phi, wl.theta, eps)
     assert plan.check() == 0
-    idx = synth.sample_indices(wl.n_pts, 1500, seed=5)
-    ref = oracle_mod.dfs_eval(wl.coeffs, wl.phi[idx], wl.theta[idx])
-    errs = field_errors(got[:, idx], ref)
+    errs = field_errors(got, ref)
     say(f"  rel l2 per field {errs}")
     assert max(errs) <= tol
 

@@ -127,20 +127,14 @@ def test_real_fft_stage_matches_numpy(torch_dev, prec):
         assert err_s < tol and err < tol
 
 
-@pytest.fixture(scope="module")
-def sbr_workload():
-    return synth.workload_sbr()
-
-
 @pytest.mark.parametrize("prec,eps,tol", [("fp64", 1e-12, 1e-12), ("fp32", 1e-6, 1e-6)])
-def test_real_sbr_workload_sampled(torch_dev, oracle_mod, sbr_workload, prec, eps, tol):
-    """256 x 512 grid, 131,072 solid-body-rotation departure points, 3 fields."""
-    wl = sbr_workload
-    say(f"case real sbr prec={prec}")
+def test_real_sbr_workload_full(torch_dev, sbr_full_ref, prec, eps, tol):
+    """256 x 512 grid, all 131,072 solid-body-rotation departure points, 3 fields."""
+    wl, ref = sbr_full_ref
+    say(f"case real sbr prec={prec} (all points)")
     plan, got = run_real(torch_dev, prec, wl.coeffs, wl.phi, wl.theta, eps)
     assert plan.check() == 0
-    idx = synth.sample_indices(wl.n_pts, 2000, seed=5)
-    errs = real_errors(got[:, idx], oracle_mod.dfs_eval(wl.coeffs, wl.phi[idx], wl.theta[idx]))
+    errs = real_errors(got, ref)
     say(f"  rel l2 per field {errs}")
     assert max(errs) <= tol
 
