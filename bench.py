@@ -248,8 +248,9 @@ def cpu_baseline(wl, gpu_out, target_s, n_sample=None, one_core_s=5.0):
         r = ref.real if not np.iscomplexobj(out) else ref
         e = [float(np.linalg.norm(out[f, idx] - r[f]) / np.linalg.norm(r[f])) for f in range(F)]
         errs[name] = {"max_over_fields": max(e), "per_field": e}
-    # one core: a sample sized to about one_core_s seconds
-    n1 = int(min(n, max(32, one_core_s * cores / max(per_pt, 1e-9) / 4)))
+    # one core: a sample sized to about one_core_s seconds from the rate
+    # just measured on every thread (one core is up to `cores` times slower)
+    n1 = int(min(n, max(32, one_core_s / max(dt / n * cores, 1e-9))))
     idx1 = synth.sample_indices(wl.n_pts, n1, seed=16)
     oracle.set_num_threads(1)
     try:
