@@ -707,6 +707,39 @@ class Group:
         self._keep = (coeffs, outs)
         return [o[:, :p.n_pts] for o, p in zip(outs, self.plans)]
 
+    def bind(self, phis, thetas, coeffs, outs=None):
+        """Validate one set of per-member tensors and return a callable that
+        runs setpts + exec on them (nufft2_group_run) without checking them
+        again: for time-stepping loops that update these tensors in place
+        every step.  The tensors must keep their storage while bound (no
+        resize_, set_ or reallocation); the callable keeps them alive and
+        returns the output views.
+
+        >>> step = g.bind(phis, thetas, coeffs)
+        >>> for _ in range(n_steps):
+        ...     update(phis, thetas, coeffs)   # in place
+        ...     outs = step()
+        """
+        ns, pp, tp = self._points_args(phis, thetas)
+        outs = self._exec_args(coeffs, outs, ns)
+        n_arr = (ctypes.c_int64 * len(ns))(*ns)
+        args = (n_arr, _ptr_array(pp), _ptr_array(tp), _ptr_array([c.data_ptr() for c in coeffs]),
+                _ptr_array([o.data_ptr() for o in outs]))
+        keep = (list(phis), list(thetas), list(coeffs), list(outs))
+        views = [o[:, :n] for o, n in zip(outs, ns)]
+        handle, plans = self.handle, self.plans
+
+        def step():
+            _check(_lib.nufft2_group_run(handle, *args), "nufft2_group_run")
+            return views
+
+        step.keep = keep
+        for p, n, a, b in zip(plans, ns, phis, thetas):
+            p.n_pts = n
+            p._pts = (a, b)
+        self._keep = keep
+        return step
+
     def run(self, phis, thetas, coeffs, outs=None):
         """setpts then exec as one graph launch (nufft2_group_run)."""
         ns, pp, tp = self._points_args(phis, thetas)
