@@ -335,7 +335,12 @@ nufft2_status prepare_setpts(nufft2_group_s *g, const int64_t *n_pts, const doub
             jobs.push_back(J);
         }
         if (blocks > (int64_t)0x7fffffff) return NUFFT2_ERR_ARG;
-        if (blocks != s.n_blocks) recap = true;
+        if (blocks != s.n_blocks) {
+            // bumped now, not after the uploads: a failed upload below must
+            // still leave the graphs marked stale for the next call
+            recap = true;
+            ++g->setpts_version;
+        }
         s.h_jobs.swap(jobs);
         s.h_job_of_block.swap(owner);
         s.n_blocks = blocks;
@@ -350,6 +355,7 @@ nufft2_status prepare_setpts(nufft2_group_s *g, const int64_t *n_pts, const doub
                 s.d_job_of_block = nullptr;
                 s.block_cap = 0;
                 recap = true;
+                ++g->setpts_version;
                 if (!table_alloc(g, &s.d_job_of_block, (size_t)s.n_blocks)) return NUFFT2_ERR_ALLOC;
                 s.block_cap = s.n_blocks;
             }
@@ -363,7 +369,6 @@ nufft2_status prepare_setpts(nufft2_group_s *g, const int64_t *n_pts, const doub
         }
         g->setpts_sig = sig;
     }
-    if (recap) ++g->setpts_version;
     return NUFFT2_OK;
 }
 
