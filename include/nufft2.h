@@ -72,9 +72,10 @@ typedef enum { NUFFT2_FP32 = 1, NUFFT2_FP64 = 2 } nufft2_prec;
 typedef struct {
     int32_t w;            /* kernel width in fine-grid cells, 2..16; default from eps */
     double beta_over_w;   /* kernel shape beta / w; default 2.30 */
-    int32_t tile_theta;   /* gather tile rows (power of two, 4..128); default 16 */
+    int32_t tile_theta;   /* gather tile rows (power of two, 4..128); default 16,
+                             8 for FP64 plans with hermitian = 1 */
     int32_t tile_phi;     /* gather tile columns (power of two, 4..128); default 32,
-                             64 for FP32 plans with hermitian = 1 */
+                             64 with hermitian = 1 */
     int32_t real_output;  /* 1: write only the real part (fields known to be real) */
     int32_t hermitian;    /* 1: real fields, see below (implies real output) */
     int32_t m_major;      /* 1: coefficients stored mode-m outer, see nufft2_exec */

@@ -22,7 +22,7 @@ constexpr int64_t kProbePoints = 16384;
 constexpr int kTimedReps = 3;
 constexpr int32_t kMaxTuneMembers = 4096;  // members of a timed group
 // Gather tile shapes tried (rows, columns of first-tap cells per bin).
-constexpr int kTileCandidates[][2] = {{8, 32}, {16, 32}, {32, 16}, {16, 64}, {32, 32}, {8, 64}, {32, 64}};
+constexpr int kTileCandidates[][2] = {{8, 32}, {16, 32}, {32, 16}, {16, 64}, {32, 32}, {8, 64}, {32, 64}, {8, 128}};
 
 struct CacheEntry {
     std::string key;

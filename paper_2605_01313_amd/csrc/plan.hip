@@ -26,11 +26,17 @@ constexpr int kMaxW = 16;
 constexpr double kDefaultBetaOverW = 2.30;
 constexpr int kDefaultTileTheta = 16;
 constexpr int kDefaultTilePhi = 32;
-// FP32 real-field plans: a real patch takes half the LDS of a complex one,
-// and the wider tile gives the gather's workgroup about twice the points
-// (16 x 64 measured 7% faster than 16 x 32 at 2048^2 with the tile taken
-// at run time, and faster than 32 x 32, 8 x 64 and 32 x 64).
+// Real-field plans: a real patch takes half the LDS of a complex one, so
+// the tiles are wider.  Measured at 1024 x 2048 (setpts + exec, 3 fields):
+// FP32 16 x 64 (compile-time patch geometry) ahead of 16 x 32, 32 x 32,
+// 8 x 64, 32 x 64 and 16 x 128, and level with 8 x 128 even with that
+// geometry compiled too; FP64 8 x 64 ahead of 16 x 32 (about 1% per step),
+// 32 x 16, 32 x 32, 16 x 64, 8 x 32 and 16 x 16.  Complex plans keep
+// 16 x 32 (FP64 complex: ahead of 8 x 32, 16 x 16, 32 x 16 and 8 x 64).
+constexpr int kDefaultTileThetaReal32 = 16;
 constexpr int kDefaultTilePhiReal32 = 64;
+constexpr int kDefaultTileThetaReal64 = 8;
+constexpr int kDefaultTilePhiReal64 = 64;
 constexpr size_t kGatherLdsLimit = 65536;  // per staged field group
 constexpr size_t kFftLdsLimit = 155648;    // 152 KiB of the 160 KiB per workgroup
 constexpr size_t kCuLds = 163840;          // LDS per CU
@@ -477,8 +483,13 @@ nufft2_status plan_configure(nufft2_plan_s *p, int prec, int64_t n_modes_theta, 
     if ((int64_t)n_fields * nft * nfp > (int64_t(1) << 34)) return NUFFT2_ERR_ARG;
 
     bool bad_tile = false;
-    const int tt = choose_tile(o.tile_theta, kDefaultTileTheta, (int)nft, &bad_tile);
-    const int tp = choose_tile(o.tile_phi, prec == NUFFT2_FP32 && o.hermitian ? kDefaultTilePhiReal32 : kDefaultTilePhi,
+    const int tt = choose_tile(o.tile_theta,
+                               o.hermitian ? (prec == NUFFT2_FP32 ? kDefaultTileThetaReal32 : kDefaultTileThetaReal64)
+                                           : kDefaultTileTheta,
+                               (int)nft, &bad_tile);
+    const int tp = choose_tile(o.tile_phi,
+                               o.hermitian ? (prec == NUFFT2_FP32 ? kDefaultTilePhiReal32 : kDefaultTilePhiReal64)
+                                           : kDefaultTilePhi,
                                (int)nfp, &bad_tile);
     if (bad_tile) return NUFFT2_ERR_ARG;
     {

@@ -10,7 +10,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-TILES = {(8, 32), (16, 32), (32, 16), (16, 64), (32, 32), (8, 64), (32, 64)}
+TILES = {(8, 32), (16, 32), (32, 16), (16, 64), (32, 32), (8, 64), (32, 64), (8, 128)}
 
 
 def say(msg):
