@@ -3,11 +3,11 @@
 // member's points, one scan launch (a workgroup per member), one scatter
 // launch.  exec: per class of identically shaped members, one theta-pass,
 // one phi-pass and one gather launch over all of the class's members, the
-// classes as parallel branches of the exec graph.  The kernels find their
-// member in device tables that the host rewrites only
-// when a pointer or a point count changes; the graphs hold the launches and
-// are captured once (the setpts graph again when the total point count
-// changes).
+// classes as parallel branches of the exec graph.  nufft2_group_run puts
+// both in one graph.  The kernels find their member in device tables that
+// the host rewrites only when a pointer or a point count changes; the graphs
+// hold the launches and are captured once (those holding the setpts
+// launches again when the members' point-block counts change).
 #include <stdint.h>
 #include <string.h>
 
