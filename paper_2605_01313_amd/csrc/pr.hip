@@ -154,118 +154,237 @@ __global__ __launch_bounds__(256) void k_pr_rhs(const C2<T> *__restrict__ e, dou
     r[H * W + (int64_t)j * W + m] = rs;
 }
 
-// One thread per (field, chain parity, column m): forward and backward
-// sweeps of L D L^T x = rhs along j = parity, parity + 2, ... for the cos and
-// sin parts.  fac = [4 classes][3][N + 1 + kPrPad]: L(j, j-2), L(j, j-4),
-// 1 / D(j), zero outside the class range (so the chain runs over all j of
-// its parity and writes zeros there).  z is kept in rhs between the sweeps.
-// The loads do not depend on the recurrence, so each sweep reads a group of
-// kPrUnroll steps ahead of the group it computes.
-constexpr int kPrUnroll = 8;
+// The solve of L D L^T x = rhs along each chain j = parity, parity + 2, ...
+// (cos and sin parts together; fac = [4 classes][3][N + 1 + kPrPad]:
+// L(j, j-2), L(j, j-4), 1 / D(j), zero outside the class range, so a chain
+// runs over all j of its parity and writes zeros there).  With step k for
+// j = parity + 2k the sweeps are linear two-term recurrences:
+//   forward   y_k = r_k - L(j, j-2) y_{k-1} - L(j, j-4) y_{k-2},  z_k = y_k / D(j),
+//   backward  x_k = z_k - L(j+2, j) x_{k+1} - L(j+4, j) x_{k+2}.
+// A chain of N / 2 steps run by one thread leaves the GPU almost idle (one
+// wave per 64 columns, parity and field), so each sweep is split into
+// segments of kPrSeg steps run side by side: a first kernel runs every
+// segment from a zero state and keeps its end state; a second one chains
+// the segments' end states through the segments' homogeneous propagators
+// (2 x 2 products of the recurrence matrices, the same for every column of a
+// class; made on the host in long double) to find the state each segment
+// starts from, and runs the segment again from it, writing the results.
+// By linearity this is the serial recurrence, up to rounding.
+constexpr int kPrSeg = 32;
 
-template <typename T>
-__global__ __launch_bounds__(64) void k_pr_solve(double *__restrict__ rhs, const double *__restrict__ fac,
-                                                 T *__restrict__ out, PrParams p)
+__host__ __device__ inline int pr_steps(int N, int par) { return (N - par) / 2 + 1; }
+__host__ __device__ inline int pr_segments(int N) { return (pr_steps(N, 0) + kPrSeg - 1) / kPrSeg; }
+
+// One workgroup: 64 consecutive columns of one segment, parity and field.
+struct PrSegIdx {
+    int m, seg, par, f, cls, k0, k1;
+    bool valid;
+};
+__device__ inline PrSegIdx pr_seg_idx(const PrParams &p)
 {
+    PrSegIdx q;
+    q.m = (int)blockIdx.x * 64 + (int)threadIdx.x;
+    q.seg = (int)blockIdx.y;
+    q.par = (int)blockIdx.z & 1;
+    q.f = (int)blockIdx.z >> 1;
+    q.cls = pr_class(q.m);
+    const int ns = pr_steps(p.N, q.par);
+    q.k0 = q.seg * kPrSeg;
+    q.k1 = q.k0 + kPrSeg < ns ? q.k0 + kPrSeg : ns;
+    q.valid = q.m <= p.M && q.k0 < ns;
+    return q;
+}
+
+// End states: st[f][par][seg][4][M + 1] = (cos y_a, cos y_b, sin y_a, sin y_b)
+__device__ inline double *pr_state(double *st, const PrParams &p, const PrSegIdx &q, int seg, int e)
+{
+    const int nseg = pr_segments(p.N);
+    return st + ((((int64_t)q.f * 2 + q.par) * nseg + seg) * 4 + e) * (p.M + 1) + q.m;
+}
+
+// Forward, pass 1: every segment from y_{k0-1} = y_{k0-2} = 0; keeps
+// (y_{k1-1}, y_{k1-2}).
+__global__ __launch_bounds__(64) void k_pr_fwd_local(const double *__restrict__ rhs, const double *__restrict__ fac,
+                                                     double *__restrict__ st, PrParams p)
+{
+    const PrSegIdx q = pr_seg_idx(p);
+    if (!q.valid) return;
     const int64_t W = p.M + 1, H = p.N + 1;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= p.F * 2 * (int)W) return;
-    const int m = t % (int)W;
-    const int par = (t / (int)W) & 1;
-    const int f = t / (2 * (int)W);
-    const int cls = pr_class(m);
     const int FL = p.N + 1 + kPrPad;
-    const double *L1 = fac + (int64_t)cls * 3 * FL;
-    const double *L2 = L1 + FL;
-    const double *DI = L2 + FL;
-    double *rc = rhs + (int64_t)f * 2 * H * W + m;
-    double *rs = rc + H * W;
-    const int nsteps = (p.N - par) / 2 + 1;  // j = par + 2 k, k < nsteps
-    constexpr int U = kPrUnroll;
-
-    // forward: y_j = r_j - L(j, j-2) y_{j-2} - L(j, j-4) y_{j-4};  z_j = y_j / D(j)
+    const double *L1 = fac + (int64_t)q.cls * 3 * FL, *L2 = L1 + FL;
+    const double *rc = rhs + (int64_t)q.f * 2 * H * W + q.m, *rs = rc + H * W;
     double yc1 = 0, yc2 = 0, ys1 = 0, ys2 = 0;
-    double ac[U], as[U], a1[U], a2[U], ad[U];
-    auto load_fwd = [&](int k0) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = k0 + u < nsteps ? k0 + u : nsteps - 1;
-            const int j = par + 2 * k;
-            ac[u] = rc[(int64_t)j * W];
-            as[u] = rs[(int64_t)j * W];
-            a1[u] = L1[j];
-            a2[u] = L2[j];
-            ad[u] = DI[j];
-        }
-    };
-    load_fwd(0);
-    for (int k0 = 0; k0 < nsteps; k0 += U) {
-        double bc[U], bs[U], b1[U], b2[U], bd[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            bc[u] = ac[u];
-            bs[u] = as[u];
-            b1[u] = a1[u];
-            b2[u] = a2[u];
-            bd[u] = ad[u];
-        }
-        if (k0 + U < nsteps) load_fwd(k0 + U);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (k0 + u < nsteps) {
-                const int j = par + 2 * (k0 + u);
-                const double yc = bc[u] - b1[u] * yc1 - b2[u] * yc2;
-                const double ys = bs[u] - b1[u] * ys1 - b2[u] * ys2;
-                rc[(int64_t)j * W] = yc * bd[u];
-                rs[(int64_t)j * W] = ys * bd[u];
-                yc2 = yc1;
-                yc1 = yc;
-                ys2 = ys1;
-                ys1 = ys;
-            }
-        }
+#pragma unroll 8
+    for (int k = q.k0; k < q.k1; ++k) {
+        const int j = q.par + 2 * k;
+        const double a = L1[j], b = L2[j];
+        const double yc = rc[(int64_t)j * W] - a * yc1 - b * yc2;
+        const double ys = rs[(int64_t)j * W] - a * ys1 - b * ys2;
+        yc2 = yc1;
+        yc1 = yc;
+        ys2 = ys1;
+        ys1 = ys;
     }
-    // the forward stores and the backward loads are the same thread's
-    // addresses, so program order makes them visible
+    *pr_state(st, p, q, q.seg, 0) = yc1;
+    *pr_state(st, p, q, q.seg, 1) = yc2;
+    *pr_state(st, p, q, q.seg, 2) = ys1;
+    *pr_state(st, p, q, q.seg, 3) = ys2;
+}
 
-    // backward: x_j = z_j - L(j+2, j) x_{j+2} - L(j+4, j) x_{j+4}
-    T *oc = out + (int64_t)f * 2 * H * W + m;
-    T *os = oc + H * W;
+// Forward, pass 2: the start state of the segment from the earlier ones
+// (S_{t+1} = P_t S_t + E_t, S_0 = 0), then the segment again from it, z
+// into rhs.  prop = [4 classes][2 parities][segments][2 x 2].
+__global__ __launch_bounds__(64) void k_pr_fwd_apply(double *__restrict__ rhs, const double *__restrict__ fac,
+                                                     const double *__restrict__ st, const double *__restrict__ prop,
+                                                     PrParams p)
+{
+    const PrSegIdx q = pr_seg_idx(p);
+    if (!q.valid) return;
+    const int64_t W = p.M + 1, H = p.N + 1;
+    const int FL = p.N + 1 + kPrPad;
+    const int nseg = pr_segments(p.N);
+    double yc1 = 0, yc2 = 0, ys1 = 0, ys2 = 0;
+    for (int t = 0; t < q.seg; ++t) {
+        const double *P = prop + (((int64_t)q.cls * 2 + q.par) * nseg + t) * 4;
+        const double c1 = P[0] * yc1 + P[1] * yc2 + *pr_state(const_cast<double *>(st), p, q, t, 0);
+        const double c2 = P[2] * yc1 + P[3] * yc2 + *pr_state(const_cast<double *>(st), p, q, t, 1);
+        const double s1 = P[0] * ys1 + P[1] * ys2 + *pr_state(const_cast<double *>(st), p, q, t, 2);
+        const double s2 = P[2] * ys1 + P[3] * ys2 + *pr_state(const_cast<double *>(st), p, q, t, 3);
+        yc1 = c1;
+        yc2 = c2;
+        ys1 = s1;
+        ys2 = s2;
+    }
+    const double *L1 = fac + (int64_t)q.cls * 3 * FL, *L2 = L1 + FL, *DI = L2 + FL;
+    double *rc = rhs + (int64_t)q.f * 2 * H * W + q.m, *rs = rc + H * W;
+#pragma unroll 8
+    for (int k = q.k0; k < q.k1; ++k) {
+        const int j = q.par + 2 * k;
+        const double a = L1[j], b = L2[j];
+        const double yc = rc[(int64_t)j * W] - a * yc1 - b * yc2;
+        const double ys = rs[(int64_t)j * W] - a * ys1 - b * ys2;
+        rc[(int64_t)j * W] = yc * DI[j];
+        rs[(int64_t)j * W] = ys * DI[j];
+        yc2 = yc1;
+        yc1 = yc;
+        ys2 = ys1;
+        ys1 = ys;
+    }
+}
+
+// Backward, pass 1: every segment from x_{k1} = x_{k1+1} = 0, downwards;
+// keeps (x_{k0}, x_{k0+1}).
+__global__ __launch_bounds__(64) void k_pr_bwd_local(const double *__restrict__ rhs, const double *__restrict__ fac,
+                                                     double *__restrict__ st, PrParams p)
+{
+    const PrSegIdx q = pr_seg_idx(p);
+    if (!q.valid) return;
+    const int64_t W = p.M + 1, H = p.N + 1;
+    const int FL = p.N + 1 + kPrPad;
+    const double *L1 = fac + (int64_t)q.cls * 3 * FL, *L2 = L1 + FL;
+    const double *rc = rhs + (int64_t)q.f * 2 * H * W + q.m, *rs = rc + H * W;
     double xc1 = 0, xc2 = 0, xs1 = 0, xs2 = 0;
-    auto load_bwd = [&](int k0) {  // steps k0, k0 - 1, ...
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = k0 - u >= 0 ? k0 - u : 0;
-            const int j = par + 2 * k;
-            ac[u] = rc[(int64_t)j * W];
-            as[u] = rs[(int64_t)j * W];
-            a1[u] = L1[j + 2];
-            a2[u] = L2[j + 4];
-        }
-    };
-    load_bwd(nsteps - 1);
-    for (int k0 = nsteps - 1; k0 >= 0; k0 -= U) {
-        double bc[U], bs[U], b1[U], b2[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            bc[u] = ac[u];
-            bs[u] = as[u];
-            b1[u] = a1[u];
-            b2[u] = a2[u];
-        }
-        if (k0 - U >= 0) load_bwd(k0 - U);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (k0 - u >= 0) {
-                const int j = par + 2 * (k0 - u);
-                const double xc = bc[u] - b1[u] * xc1 - b2[u] * xc2;
-                const double xs = bs[u] - b1[u] * xs1 - b2[u] * xs2;
-                oc[(int64_t)j * W] = (T)xc;
-                os[(int64_t)j * W] = (T)(m == 0 ? 0.0 : xs);
-                xc2 = xc1;
-                xc1 = xc;
-                xs2 = xs1;
-                xs1 = xs;
+#pragma unroll 8
+    for (int k = q.k1 - 1; k >= q.k0; --k) {
+        const int j = q.par + 2 * k;
+        const double c = L1[j + 2], d = L2[j + 4];
+        const double xc = rc[(int64_t)j * W] - c * xc1 - d * xc2;
+        const double xs = rs[(int64_t)j * W] - c * xs1 - d * xs2;
+        xc2 = xc1;
+        xc1 = xc;
+        xs2 = xs1;
+        xs1 = xs;
+    }
+    *pr_state(st, p, q, q.seg, 0) = xc1;
+    *pr_state(st, p, q, q.seg, 1) = xc2;
+    *pr_state(st, p, q, q.seg, 2) = xs1;
+    *pr_state(st, p, q, q.seg, 3) = xs2;
+}
+
+// Backward, pass 2: the state above the segment from the later segments
+// (T_{t-1} = Q_t T_t + F_t from the last one down, T_last = 0), then the
+// segment again from it, x into out (the sin part of column 0 is zero).
+template <typename T>
+__global__ __launch_bounds__(64) void k_pr_bwd_apply(const double *__restrict__ rhs, const double *__restrict__ fac,
+                                                     const double *__restrict__ st, const double *__restrict__ prop,
+                                                     T *__restrict__ out, PrParams p)
+{
+    const PrSegIdx q = pr_seg_idx(p);
+    if (!q.valid) return;
+    const int64_t W = p.M + 1, H = p.N + 1;
+    const int FL = p.N + 1 + kPrPad;
+    const int nseg = pr_segments(p.N);
+    const int last = (pr_steps(p.N, q.par) - 1) / kPrSeg;
+    double xc1 = 0, xc2 = 0, xs1 = 0, xs2 = 0;
+    for (int t = last; t > q.seg; --t) {
+        const double *Q = prop + (((int64_t)q.cls * 2 + q.par) * nseg + t) * 4;
+        const double c1 = Q[0] * xc1 + Q[1] * xc2 + *pr_state(const_cast<double *>(st), p, q, t, 0);
+        const double c2 = Q[2] * xc1 + Q[3] * xc2 + *pr_state(const_cast<double *>(st), p, q, t, 1);
+        const double s1 = Q[0] * xs1 + Q[1] * xs2 + *pr_state(const_cast<double *>(st), p, q, t, 2);
+        const double s2 = Q[2] * xs1 + Q[3] * xs2 + *pr_state(const_cast<double *>(st), p, q, t, 3);
+        xc1 = c1;
+        xc2 = c2;
+        xs1 = s1;
+        xs2 = s2;
+    }
+    const double *L1 = fac + (int64_t)q.cls * 3 * FL, *L2 = L1 + FL;
+    const double *rc = rhs + (int64_t)q.f * 2 * H * W + q.m, *rs = rc + H * W;
+    T *oc = out + (int64_t)q.f * 2 * H * W + q.m, *os = oc + H * W;
+#pragma unroll 8
+    for (int k = q.k1 - 1; k >= q.k0; --k) {
+        const int j = q.par + 2 * k;
+        const double c = L1[j + 2], d = L2[j + 4];
+        const double xc = rc[(int64_t)j * W] - c * xc1 - d * xc2;
+        const double xs = rs[(int64_t)j * W] - c * xs1 - d * xs2;
+        oc[(int64_t)j * W] = (T)xc;
+        os[(int64_t)j * W] = (T)(q.m == 0 ? 0.0 : xs);
+        xc2 = xc1;
+        xc1 = xc;
+        xs2 = xs1;
+        xs1 = xs;
+    }
+}
+
+// Homogeneous propagators of the segments (long double products of the
+// double factors the kernels use): fwd[cls][par][seg] maps (y_{k0-1},
+// y_{k0-2}) to (y_{k1-1}, y_{k1-2}); bwd[cls][par][seg] maps (x_{k1},
+// x_{k1+1}) to (x_{k0}, x_{k0+1}).  fac as above (host copy).
+void pr_propagators(int N, const std::vector<double> &fac, std::vector<double> &fwd, std::vector<double> &bwd)
+{
+    const int FL = N + 1 + kPrPad, nseg = pr_segments(N);
+    fwd.assign((size_t)4 * 2 * nseg * 4, 0.0);
+    bwd.assign((size_t)4 * 2 * nseg * 4, 0.0);
+    for (int cls = 0; cls < 4; ++cls) {
+        const double *L1 = fac.data() + (size_t)cls * 3 * FL, *L2 = L1 + FL;
+        for (int par = 0; par < 2; ++par) {
+            const int ns = pr_steps(N, par);
+            for (int s = 0; s < nseg; ++s) {
+                const int k0 = s * kPrSeg, k1 = k0 + kPrSeg < ns ? k0 + kPrSeg : ns;
+                long double P[4] = {1, 0, 0, 1}, Q[4] = {1, 0, 0, 1};
+                for (int k = k0; k < k1; ++k) {  // P = M_k P
+                    const int j = par + 2 * k;
+                    const long double a = L1[j], b = L2[j];
+                    const long double r0 = -a * P[0] - b * P[2], r1 = -a * P[1] - b * P[3];
+                    P[2] = P[0];
+                    P[3] = P[1];
+                    P[0] = r0;
+                    P[1] = r1;
+                }
+                for (int k = k1 - 1; k >= k0; --k) {  // Q = M'_k Q
+                    const int j = par + 2 * k;
+                    const long double c = L1[j + 2], d = L2[j + 4];
+                    const long double r0 = -c * Q[0] - d * Q[2], r1 = -c * Q[1] - d * Q[3];
+                    Q[2] = Q[0];
+                    Q[3] = Q[1];
+                    Q[0] = r0;
+                    Q[1] = r1;
+                }
+                double *pf = fwd.data() + (((size_t)cls * 2 + par) * nseg + s) * 4;
+                double *pb = bwd.data() + (((size_t)cls * 2 + par) * nseg + s) * 4;
+                for (int e = 0; e < 4; ++e) {
+                    pf[e] = (double)P[e];
+                    pb[e] = (double)Q[e];
+                }
             }
         }
     }
@@ -334,11 +453,15 @@ template <typename T> hipError_t launch_rhs(const void *e, double *rhs, const Pr
     return hipGetLastError();
 }
 
-template <typename T> hipError_t launch_solve(double *rhs, const double *fac, void *out, const PrParams &p,
-                                              hipStream_t s)
+template <typename T> hipError_t launch_solve(double *rhs, const double *fac, double *st, const double *fwd,
+                                              const double *bwd, void *out, const PrParams &p, hipStream_t s)
 {
-    const int threads = p.F * 2 * (p.M + 1);
-    hipLaunchKernelGGL(k_pr_solve<T>, dim3((threads + 63) / 64), dim3(64), 0, s, rhs, fac, (T *)out, p);
+    const dim3 grid((unsigned)((p.M + 1 + 63) / 64), (unsigned)pr_segments(p.N), (unsigned)(2 * p.F));
+    hipLaunchKernelGGL(k_pr_fwd_local, grid, dim3(64), 0, s, (const double *)rhs, fac, st, p);
+    hipLaunchKernelGGL(k_pr_fwd_apply, grid, dim3(64), 0, s, rhs, fac, (const double *)st, fwd, p);
+    hipLaunchKernelGGL(k_pr_bwd_local, grid, dim3(64), 0, s, (const double *)rhs, fac, st, p);
+    hipLaunchKernelGGL(k_pr_bwd_apply<T>, grid, dim3(64), 0, s, (const double *)rhs, fac, (const double *)st, bwd,
+                       (T *)out, p);
     return hipGetLastError();
 }
 
@@ -351,7 +474,7 @@ template <typename T> hipError_t launch_synth(const void *pr, void *e, const PrP
 }
 
 // G = A^T W A of one class restricted to its range, factored along each
-// parity chain as L D L^T (long double); tables as k_pr_solve reads them.
+// parity chain as L D L^T (long double); tables as the solve kernels read them.
 void factor_class(int cls, int N, double *L1, double *L2, double *DI)
 {
     const int FL = N + 1 + kPrPad;
@@ -402,12 +525,16 @@ struct nufft2_pr_s {
     hipStream_t stream = nullptr;
     double *fac = nullptr;  // [4][3][N + 1 + kPrPad]
     double *rhs = nullptr;  // [F][2][N + 1][M + 1]
+    double *prop = nullptr; // segment propagators: forward then backward, [4][2][segments][4] each
+    double *st = nullptr;   // segment end states [F][2][segments][4][M + 1]
 };
 
 static void pr_free(nufft2_pr_s *h)
 {
     if (h->fac) (void)hipFree(h->fac);
     if (h->rhs) (void)hipFree(h->rhs);
+    if (h->prop) (void)hipFree(h->prop);
+    if (h->st) (void)hipFree(h->st);
     delete h;
 }
 
@@ -430,13 +557,21 @@ NUFFT2_API nufft2_status nufft2_pr_plan(nufft2_prec prec, int64_t N, int64_t M, 
         double *b = fac.data() + (size_t)c * 3 * FL;
         factor_class(c, h->N, b, b + FL, b + 2 * FL);
     }
+    std::vector<double> fwd, bwd;
+    pr_propagators(h->N, fac, fwd, bwd);
+    const size_t nprop = fwd.size();
+    const size_t nst = (size_t)n_fields * 2 * pr_segments(h->N) * 4 * (M + 1);
     if (hipMalloc(&h->fac, sizeof(double) * fac.size()) != hipSuccess ||
-        hipMalloc(&h->rhs, sizeof(double) * 2 * (size_t)n_fields * (N + 1) * (M + 1)) != hipSuccess) {
+        hipMalloc(&h->rhs, sizeof(double) * 2 * (size_t)n_fields * (N + 1) * (M + 1)) != hipSuccess ||
+        hipMalloc(&h->prop, sizeof(double) * 2 * nprop) != hipSuccess ||
+        hipMalloc(&h->st, sizeof(double) * nst) != hipSuccess) {
         (void)hipGetLastError();
         pr_free(h);
         return NUFFT2_ERR_ALLOC;
     }
-    if (hipMemcpy(h->fac, fac.data(), sizeof(double) * fac.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(h->fac, fac.data(), sizeof(double) * fac.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->prop, fwd.data(), sizeof(double) * nprop, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->prop + nprop, bwd.data(), sizeof(double) * nprop, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipGetLastError();
         pr_free(h);
         return NUFFT2_ERR_HIP;
@@ -451,9 +586,11 @@ NUFFT2_API nufft2_status nufft2_pr_project(nufft2_pr h, const void *coeffs_dev, 
     const PrParams p{h->N, h->M, h->F};
     hipError_t e = h->prec == NUFFT2_FP32 ? launch_rhs<float>(coeffs_dev, h->rhs, p, h->stream)
                                           : launch_rhs<double>(coeffs_dev, h->rhs, p, h->stream);
-    if (e == hipSuccess)
-        e = h->prec == NUFFT2_FP32 ? launch_solve<float>(h->rhs, h->fac, pr_dev, p, h->stream)
-                                   : launch_solve<double>(h->rhs, h->fac, pr_dev, p, h->stream);
+    if (e == hipSuccess) {
+        const double *fwd = h->prop, *bwd = h->prop + (size_t)4 * 2 * pr_segments(h->N) * 4;
+        e = h->prec == NUFFT2_FP32 ? launch_solve<float>(h->rhs, h->fac, h->st, fwd, bwd, pr_dev, p, h->stream)
+                                   : launch_solve<double>(h->rhs, h->fac, h->st, fwd, bwd, pr_dev, p, h->stream);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return NUFFT2_ERR_HIP;
