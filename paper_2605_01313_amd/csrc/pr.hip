@@ -390,19 +390,49 @@ void pr_propagators(int N, const std::vector<double> &fac, std::vector<double> &
     }
 }
 
-// Standard coefficient at (n, m) of a pr column (the conversion after
-// eq. std_dfs), from col[k * stride], k in the class range.
+// Standard coefficients (cos and sin parts) at (n, m) of a pr column (the
+// conversion after eq. std_dfs), from cc[k * stride], cs[k * stride], k in
+// the class range F(k):
+//   class 0: F(n)
+//   class 1: F(n-1)/2 - F(n+1)/2 (+ F(0)/2 at n = 1; 0 at n = 0)
+//   class 2: F(n+1)/2 - F(n-1)/2
+//   class 3: F(n)/2 - F(n-2)/4 - F(n+2)/4 (+ F(1)/4 at n = 1; 0 at n = 0)
+// written as one weighted sum of the five entries n - 2 .. n + 2 whose
+// weights the class selects: neighbouring lanes hold columns of alternating
+// classes (even and odd m), and a branch per class would make every wave
+// run both.  Entries of weight zero are not read.
 template <typename T>
-__device__ inline double pr_to_std_entry(const T *__restrict__ col, int64_t stride, int cls, int n, int N)
+__device__ inline void pr_to_std_pair(const T *__restrict__ cc, const T *__restrict__ cs, int64_t stride, int cls,
+                                      int n, int N, double &c, double &s)
 {
     int lo, hi;
     pr_range(cls, N, lo, hi);
-    auto F = [&](int k) { return (k >= lo && k <= hi) ? (double)col[(int64_t)k * stride] : 0.0; };
-    switch (cls) {
-    case 0: return F(n);
-    case 1: return n == 0 ? 0.0 : 0.5 * F(n - 1) - 0.5 * F(n + 1) + (n == 1 ? 0.5 * F(0) : 0.0);
-    case 2: return 0.5 * F(n + 1) - 0.5 * F(n - 1);
-    default: return n == 0 ? 0.0 : 0.5 * F(n) - 0.25 * F(n - 2) - 0.25 * F(n + 2) + (n == 1 ? 0.25 * F(1) : 0.0);
+    // weights of F(n - 2) .. F(n + 2) (the n = 1 cases fold F(0) resp. F(1) in)
+    double w[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (cls == 0) {
+        w[2] = 1.0;
+    } else if (cls == 1) {
+        if (n > 0) {
+            w[1] = n == 1 ? 1.0 : 0.5;
+            w[3] = -0.5;
+        }
+    } else if (cls == 2) {
+        w[1] = -0.5;
+        w[3] = 0.5;
+    } else if (n > 0) {
+        w[0] = -0.25;
+        w[2] = n == 1 ? 0.75 : 0.5;
+        w[4] = -0.25;
+    }
+    c = 0.0;
+    s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+        const int k = n - 2 + d;
+        if (w[d] != 0.0 && k >= lo && k <= hi) {
+            c += w[d] * (double)cc[(int64_t)k * stride];
+            s += w[d] * (double)cs[(int64_t)k * stride];
+        }
     }
 }
 
@@ -423,8 +453,9 @@ __global__ __launch_bounds__(256) void k_pr_synth(const T *__restrict__ pr, C2<T
     const T *pc = pr + (int64_t)f * 2 * H * W + am;
     const T *ps = pc + H * W;
     const int cls = pr_class(am);
-    const double c = pr_to_std_entry(pc, W, cls, an, p.N);
-    const double s = am == 0 ? 0.0 : pr_to_std_entry(ps, W, cls, an, p.N);
+    double c, s;
+    pr_to_std_pair(pc, ps, W, cls, an, p.N, c, s);
+    if (am == 0) s = 0.0;
     double re, im;
     if (am == 0) {
         re = n == 0 ? c : 0.5 * c;
