@@ -22,9 +22,11 @@
 // Kernel weights: FP32 plans of width >= 7 evaluate each tap's weight as a
 // degree-8 polynomial in the point's centred offset (coefficients from the
 // plan, interpolated in long double, within 1e-7 of the kernel; mirrored
-// taps share the even and odd parts of one polynomial); the direct
-// form is used otherwise, written as exp(-beta z^2 / (1 + sqrt(1 - z^2)))
-// in FP32, which has no cancellation near the kernel's peak.
+// taps share the even and odd parts of one polynomial); FP64 plans of width
+// >= 7 do the same with degree-14 polynomials (within 2e-15) for all but the
+// two edge taps, which are evaluated directly.  The direct form is used
+// otherwise, in FP32 written as exp(-beta z^2 / (1 + sqrt(1 - z^2))), which
+// has no cancellation near the kernel's peak.
 #pragma once
 
 #include "nufft2_internal.hpp"
@@ -119,6 +121,106 @@ __device__ __forceinline__ void tap_weights2(T v0, T v1, const GatherParams &gp,
         w0[b] = es_kernel<T>(((T)(b - H) - v0) * inv_hw, kc);
         w1[b] = es_kernel<T>(((T)(b - H) - v1) * inv_hw, kc);
     }
+}
+
+// FP64 tap-weight polynomials in the power basis: t = u^2 and its powers
+// tp[k] = t^k, k <= (kPolyCoefs64 - 1) / 2, computed once per point and axis,
+// so that every coefficient enters as a multiplicand (a scalar operand of one
+// FMA) rather than as the addend of a Horner step (which the compiler feeds
+// through two vector moves per coefficient).  |t| <= 1/4: the terms decrease
+// with k and are summed from the highest degree down.
+constexpr int kPow64 = (kPolyCoefs64 + 1) / 2;
+__device__ __forceinline__ void powers_f64(double u, double (&tp)[kPow64])
+{
+    tp[0] = 1.0;
+    tp[1] = u * u;
+#pragma unroll
+    for (int k = 2; k < kPow64; ++k) tp[k] = tp[k - 1] * tp[1];
+}
+
+// Even and odd parts of the polynomial of row r of the table c at t:
+// p_r(u) = e + u o.
+using cdouble = const __attribute__((address_space(4))) double;
+__device__ __forceinline__ void poly_parts_f64(cdouble *c, int r, const double (&tp)[kPow64], double &e, double &o)
+{
+    constexpr int D = kPolyCoefs64;
+    static_assert(D % 2 == 1, "even part of degree D - 1");
+    cdouble *q = c + r * D;
+    e = q[D - 1] * tp[kPow64 - 1];
+#pragma unroll
+    for (int k = kPow64 - 2; k >= 1; --k) e = fma(q[2 * k], tp[k], e);
+    e += q[0];
+    o = q[D - 2] * tp[kPow64 - 2];
+#pragma unroll
+    for (int k = kPow64 - 3; k >= 1; --k) o = fma(q[2 * k + 1], tp[k], o);
+    o += q[1];
+}
+
+// The plan's FP64 table, read through the constant address space (scalar
+// loads into SGPRs).  The pointer is made opaque where it is taken, so that
+// the compiler cannot hoist the loads of the whole table out of the point
+// loop (which would hold every coefficient in registers across it).
+__device__ __forceinline__ cdouble *poly_table_f64(const GatherParams &gp)
+{
+    cdouble *c = (cdouble *)gp.wpoly;
+    __asm__ volatile("" : "+s"(c));
+    return c;
+}
+
+// FP64 weights of the W taps along one axis for a point with offset v: taps
+// 1 .. W - 2 from the plan's polynomials when it has them (mirrored taps
+// share the even and odd parts of one polynomial, as in FP32), taps 0 and
+// W - 1 directly (the kernel's square-root edge lies in their intervals,
+// where no polynomial of modest degree follows it to 1e-15).
+template <int W>
+__device__ __forceinline__ void tap_weights_f64(double v, const GatherParams &gp, double (&wt)[W])
+{
+    constexpr int H = W / 2;
+    const double inv_hw = 2.0 / (double)W;
+    const double kc = gp.beta;
+    if constexpr (W >= kPolyMinW64) {
+        if (gp.wpoly) {
+            const double u = (W & 1) ? v : v + 0.5;
+            cdouble *c = poly_table_f64(gp);
+            double tp[kPow64];
+            powers_f64(u, tp);
+#pragma unroll
+            for (int b = 1; b < (W + 1) / 2; ++b) {
+                double e, o;
+                poly_parts_f64(c, b, tp, e, o);
+                if ((W & 1) && b == W / 2) {
+                    wt[b] = e;
+                    break;
+                }
+                wt[b] = fma(u, o, e);
+                wt[W - 1 - b] = fma(-u, o, e);
+            }
+            wt[0] = es_kernel<double>(((double)(-H) - v) * inv_hw, kc);
+            wt[W - 1] = es_kernel<double>(((double)(W - 1 - H) - v) * inv_hw, kc);
+            return;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < W; ++b) wt[b] = es_kernel<double>(((double)(b - H) - v) * inv_hw, kc);
+}
+
+// FP64 weight of tap a for the offset v (a is the same for every lane of
+// the wave, so that the coefficients come in by scalar loads): the row's
+// polynomial at the powers tp of the centred offset u for interior taps,
+// the kernel itself for the edge taps and for plans without polynomials.
+template <int W>
+__device__ __forceinline__ double row_weight_f64(int a, double v, double u, const double (&tp)[kPow64],
+                                                 const GatherParams &gp)
+{
+    constexpr int H = W / 2;
+    if constexpr (W >= kPolyMinW64) {
+        if (gp.wpoly && a > 0 && a < W - 1) {
+            double e, o;
+            poly_parts_f64(poly_table_f64(gp), a, tp, e, o);
+            return fma(u, o, e);
+        }
+    }
+    return es_kernel<double>(((double)(a - H) - v) * (2.0 / (double)W), gp.beta);
 }
 
 // Accumulation a += w v for real and complex grid values.
@@ -374,6 +476,7 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
             // the bin's count only, never on which chunk a point fell in, so
             // a point's sum stays independent of the order inside its bin.
             constexpr int HALF = NT / 2;
+            static_assert(HALF % 64 == 0, "the split halves are whole waves");
             const bool split = kSplitRows<T> && cnt <= HALF;
             const bool upper = split && t >= HALF;
             const int mine = upper ? slot[t - HALF] : slot[t];
@@ -395,7 +498,8 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
                 // FP32 takes the row weights with the column weights; FP64
                 // computes them row by row below
                 T pw[W], wp[W], pt[W];
-                tap_weights2<T, W>(bad ? (T)0 : pr.vp, bad ? (T)0 : pr.vt, gp, pw, pt);
+                if constexpr (sizeof(T) == 4) tap_weights2<T, W>(bad ? (T)0 : pr.vp, bad ? (T)0 : pr.vt, gp, pw, pt);
+                else tap_weights_f64<W>(bad ? 0.0 : pr.vp, gp, pw);
 #pragma unroll
                 for (int b = 0; b < W; ++b) wp[b] = rot ? pw[(b + 1) % W] : pw[b];
                 const E *row0 = tiles + lr * TCP + lc;
@@ -426,13 +530,18 @@ __device__ inline void gather_body(int blk, const typename GridElem<T, RG>::type
                     }
                 } else {
                     // FP64: rows stay a loop (two per iteration), row weights
-                    // on the fly; split points take their half of the rows
-                    const int a_begin = upper ? H1 : 0, a_end = split && !upper ? H1 : W;
-                    const T inv_hw = (T)2 / (T)W;
-                    const T kc = es_constant<T>(gp.beta);
+                    // on the fly; split points take their half of the rows.
+                    // The row range is the same for every lane of a wave
+                    // (the split halves are whole waves), which readfirstlane
+                    // tells the compiler, so that the row index is scalar.
+                    const int a_begin = __builtin_amdgcn_readfirstlane(upper ? H1 : 0);
+                    const int a_end = __builtin_amdgcn_readfirstlane(split && !upper ? H1 : W);
+                    const double ut = (W & 1) ? pr.vt : pr.vt + 0.5;
+                    double tpt[kPow64];
+                    powers_f64(ut, tpt);
 #pragma unroll 2
                     for (int a = a_begin; a < a_end; ++a) {
-                        const T wt = es_kernel<T>(((T)(a - H) - pr.vt) * inv_hw, kc);
+                        const T wt = row_weight_f64<W>(a, pr.vt, ut, tpt, gp);
                         const E *row = row0 + a * TCP;
                         const E *rrow = row + rot;
                         E r[FG];

@@ -157,10 +157,12 @@ struct GatherParams {
     int64_t n_pts;
     int32_t real_output;
     int32_t real_grid;         // 1: the fine grid is real (Hermitian plans); the output is real
-    // FP32 plans with w >= kPolyMinW: the tap weights as polynomials in the
-    // point's centred offset (device table [w][kPolyCoefs], lowest degree
-    // first); nullptr otherwise.
-    const float *wpoly;
+    // The tap weights as polynomials in the point's centred offset, lowest
+    // degree first: FP32 plans with w >= kPolyMinW, FP32 table
+    // [w][kPolyCoefs]; FP64 plans with w >= kPolyMinW64, FP64 table
+    // [w][kPolyCoefs64] whose edge rows (taps 0 and w - 1, evaluated
+    // directly) are unused.  nullptr: direct evaluation.
+    const void *wpoly;
     // vector rotation: the (p, q) pair of each sorted point (plan
     // precision) and the fields (u, v) it rotates, in one gather pass;
     // pq == nullptr: none
@@ -169,6 +171,8 @@ struct GatherParams {
 };
 constexpr int kPolyCoefs = 9;
 constexpr int kPolyMinW = 7;
+constexpr int kPolyCoefs64 = 15;
+constexpr int kPolyMinW64 = 7;
 
 // binlist holds the non-empty bins in increasing order and their number in
 // entry nbins; after it (16-byte aligned, see bin_items) one int4 per

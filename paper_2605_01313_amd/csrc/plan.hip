@@ -167,28 +167,27 @@ long double es_kernel_ld(long double z, long double beta)
     return expl(-beta * z2 / (1.0L + sqrtl(1.0L - z2)));
 }
 
-// Tap weights of an FP32 plan as polynomials.  A point's offset v (first
-// tap i0 = ceil(t - w/2), v = t - i0 - floor(w/2)) lies in [vlo, vlo + 1],
-// vlo = w/2 - 1 - floor(w/2); tap b has weight phi((b - floor(w/2) - v) /
-// (w/2)), a smooth function of v except for the square-root edge of the
-// kernel at the end of the support.  Each tap's weight is interpolated in
-// long double by a polynomial of degree kPolyCoefs - 1 in u = v - (vlo +
-// 1/2) at the Chebyshev points of [-1/2, 1/2] (coefficients lowest degree
-// first, rounded to FP32).  Returns false, leaving the plan on the direct
-// evaluation, when the polynomials miss the kernel by more than 1e-7 on a
-// fine grid of u (w < 7 at beta = 2.30 w, where the edge taps' square-root
-// term is too large).
-bool weight_polynomials(int w, double beta, std::vector<float> &out)
+// Tap weights as polynomials.  A point's offset v (first tap i0 = ceil(t -
+// w/2), v = t - i0 - floor(w/2)) lies in [vlo, vlo + 1], vlo = w/2 - 1 -
+// floor(w/2); tap b has weight phi((b - floor(w/2) - v) / (w/2)), a smooth
+// function of v except for the square-root edge of the kernel at the end of
+// the support, which lies in the intervals of taps 0 and w - 1.  Tap b's
+// weight (taps first .. last - 1) is interpolated in long double by a
+// polynomial of degree D - 1 in u = v - (vlo + 1/2) at the Chebyshev points
+// of [-1/2, 1/2] (coefficients lowest degree first, rounded to C, row b of
+// out; other rows zero).  False when a rounded polynomial misses the kernel
+// by more than tol on a fine grid of u.
+template <int D, typename C>
+static bool fit_tap_polynomials(int w, double beta, long double tol, int first, int last, std::vector<C> &out)
 {
-    constexpr int D = kPolyCoefs;
     const long double pi = 3.141592653589793238462643383279502884L;
     const int H = w / 2;
     const long double hw = (long double)w / 2.0L;
     const long double c = ((long double)w / 2.0L - 1.0L - (long double)H) + 0.5L;
-    out.assign((size_t)w * D, 0.0f);
+    out.assign((size_t)w * D, (C)0);
     std::vector<long double> u(D);
     for (int i = 0; i < D; ++i) u[i] = 0.5L * cosl(pi * (2.0L * i + 1.0L) / (2.0L * D));
-    for (int b = 0; b < w; ++b) {
+    for (int b = first; b < last; ++b) {
         // Vandermonde system at the nodes, Gaussian elimination with pivoting
         long double A[D][D + 1];
         for (int i = 0; i < D; ++i) {
@@ -210,19 +209,40 @@ bool weight_polynomials(int w, double beta, std::vector<float> &out)
                 for (int k = col; k <= D; ++k) A[r][k] -= f * A[col][k];
             }
         }
-        long double coef[D];
-        for (int j = 0; j < D; ++j) coef[j] = A[j][D] / A[j][j];
-        for (int j = 0; j < D; ++j) out[(size_t)b * D + j] = (float)coef[j];
+        for (int j = 0; j < D; ++j) out[(size_t)b * D + j] = (C)(A[j][D] / A[j][j]);
         // check the rounded polynomial against the kernel
-        for (int q = 0; q <= 256; ++q) {
-            const long double uu = -0.5L + (long double)q / 256.0L;
+        for (int q = 0; q <= 1024; ++q) {
+            const long double uu = -0.5L + (long double)q / 1024.0L;
             long double acc = 0.0L;
             for (int j = D - 1; j >= 0; --j) acc = acc * uu + (long double)out[(size_t)b * D + j];
             const long double ex = es_kernel_ld(((long double)(b - H) - (uu + c)) / hw, beta);
-            if (fabsl(acc - ex) > 1e-7L) return false;
+            if (fabsl(acc - ex) > tol) return false;
         }
     }
     return true;
+}
+
+// FP32 plans: every tap, degree kPolyCoefs - 1, within 1e-7 (false for w < 7
+// at beta = 2.30 w, where the edge taps' square-root term is too large).
+// FP64 plans: the interior taps 1 .. w - 2, degree kPolyCoefs64 - 1, within
+// 2e-15 (at beta = 2.30 w and w >= 7 they reach 1e-15); the edge taps are
+// evaluated directly.  The table is raw device storage: FP64 coefficients
+// occupy two floats each.
+bool weight_polynomials(int prec, int w, double beta, std::vector<float> &out)
+{
+    if (prec == NUFFT2_FP32) return fit_tap_polynomials<kPolyCoefs>(w, beta, 1e-7L, 0, w, out);
+    std::vector<double> c;
+    if (!fit_tap_polynomials<kPolyCoefs64>(w, beta, 2e-15L, 1, w - 1, c)) return false;
+    out.resize(2 * c.size());
+    memcpy(out.data(), c.data(), sizeof(double) * c.size());
+    return true;
+}
+
+// Floats of a plan's polynomial table (0: direct evaluation).
+size_t poly_table_floats(int prec, int w)
+{
+    if (prec == NUFFT2_FP32) return w >= kPolyMinW ? (size_t)w * kPolyCoefs : 0;
+    return w >= kPolyMinW64 ? 2 * (size_t)w * kPolyCoefs64 : 0;
 }
 
 void free_all(nufft2_plan_s *p)
@@ -651,7 +671,7 @@ NUFFT2_API nufft2_status nufft2_plan(nufft2_prec prec, int64_t n_modes_theta, in
         return st;
     }
     std::vector<float> wpoly;
-    const bool use_poly = prec == NUFFT2_FP32 && p->w >= kPolyMinW && weight_polynomials(p->w, p->beta, wpoly);
+    const bool use_poly = poly_table_floats(prec, p->w) > 0 && weight_polynomials(prec, p->w, p->beta, wpoly);
     if (!plan_workspaces(p, use_poly ? wpoly.size() : 0, [&](void **q, size_t n) { return dev_alloc(p, q, n); })) {
         free_all(p);
         delete p;
@@ -1037,7 +1057,7 @@ NUFFT2_API nufft2_status nufft2_exec_noalloc(nufft2_prec prec, int64_t n_modes_t
         used = at + n;
         return true;
     };
-    const size_t n_poly = p.prec == NUFFT2_FP32 && p.w >= kPolyMinW ? (size_t)p.w * kPolyCoefs : 0;
+    const size_t n_poly = poly_table_floats(p.prec, p.w);
     const size_t recsz = p.prec == NUFFT2_FP32 ? sizeof(PointRec<float>) : sizeof(PointRec<double>);
     if (!plan_workspaces(&p, n_poly, carve) || !carve((void **)&p.keyrank, sizeof(int2) * (size_t)n_pts) ||
         !carve(&p.rec, recsz * (size_t)n_pts) || !carve((void **)&p.perm, sizeof(int32_t) * (size_t)n_pts))
@@ -1060,7 +1080,7 @@ NUFFT2_API nufft2_status nufft2_exec_noalloc(nufft2_prec prec, int64_t n_modes_t
     if (!dev.tables_valid || !(dev.tables == key)) {
         dev.tables_valid = false;
         std::vector<float> wpoly;
-        if (n_poly && !weight_polynomials(p.w, p.beta, wpoly)) p.wpoly = nullptr;
+        if (n_poly && !weight_polynomials(p.prec, p.w, p.beta, wpoly)) p.wpoly = nullptr;
         // earlier work on this stream may still read the old tables
         if ((e = hipStreamSynchronize(p.stream)) != hipSuccess) {
             (void)hipGetLastError();

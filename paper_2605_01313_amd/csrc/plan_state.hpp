@@ -37,7 +37,7 @@ struct nufft2_plan_s {
     void *twist_t = nullptr;                // [2][Kt]: corr_t[a], corr_t[a] e^{2 pi i n / nft}
     void *S = nullptr, *grid = nullptr;
     void *c2r = nullptr;    // real-field plans: e^{2 pi i k / nfp}, k < ncols
-    float *wpoly = nullptr; // FP32 plans with w >= kPolyMinW: tap-weight polynomials
+    float *wpoly = nullptr; // tap-weight polynomials (FP32 w >= kPolyMinW, FP64 w >= kPolyMinW64)
     int32_t *bincount = nullptr, *binstart = nullptr;
     int32_t *binlist = nullptr;  // non-empty bins in order, their number last
     uint8_t *rowmark = nullptr, *rowtouched = nullptr;
