@@ -19,11 +19,13 @@
  * Accuracy contract (relative l2 error of a field against the exact sum,
  * at the default kernel width for eps): at most eps for the decaying
  * spectra of smooth fields at general points; up to about 1.5 eps (FP32)
- * and 2.5 eps (FP64) for flat (white-noise) spectra or for points that sit
- * exactly on fine-grid nodes, where the width rule of the cited method is
- * at its limit (measured: 1.06 eps at w = 7 on grid nodes in exact
- * arithmetic, 2.35 eps at w = 13 on flat spectra).  Asking for eps / 10
- * (one more tap per axis) gives at most eps in every case.
+ * and 2.5 eps (FP64, eps >= 1e-12; 3.5 eps below) for flat (white-noise)
+ * spectra or for points that sit exactly on fine-grid nodes, where the
+ * width rule of the cited method is at its limit (measured: 1.06 eps at
+ * w = 7 on grid nodes in exact arithmetic; on flat spectra 1.2 eps at
+ * w = 7, 1.6 at w = 9 and 11, 2.35 at w = 13, 2.8 at w = 14, 3.35 at
+ * w = 15).  Asking for eps / 10 (one more tap per axis) gives at most eps
+ * in every case.
  *
  * Around the interpolation (declared further down):
  *   nufft2_group_*     many plans of uneven size as one unit (an ensemble);
