@@ -736,24 +736,38 @@ template <typename T> struct AnaRowLoad {
 };
 // The zonal filter of section 4, when on (cut != nullptr), keeps at row i
 // only the wavenumbers |m| <= cut[i] (the integer part of M_zf(theta_i)).
+//
+// Layout of A (one field): lb < 0, rows [J][K] (what the Gauss-Legendre
+// latitude product reads); lb >= 0, column blocks [2J >> lb][J][1 << lb],
+// block width = the theta step's columns per workgroup, so that each theta
+// workgroup reads one contiguous run instead of short segments of J rows
+// 8 K elements apart.  A blocked field takes 2J x J elements (the width is
+// a power of two that divides 2J = K + 1; the last block's last slot is
+// never written or read).
+__device__ inline int64_t ana_index(int i, int col, int J, int K, int lb)
+{
+    if (lb < 0) return (int64_t)i * K + col;
+    return (((int64_t)(col >> lb) * J + i) << lb) + (col & ((1 << lb) - 1));
+}
 template <typename T> struct AnaRowStore {
-    cplx<T> *A;  // this field, [J][K]
+    cplx<T> *A;  // this field
     const int32_t *cut;
-    int J, K, i0;
+    int J, K, i0, lb;
     __device__ void operator()(int o, int b, cplx<T> v) const
     {
         // frequency o <-> m = o (o < J) or o - 2J (o > J); o = J (Nyquist) is dropped
         if (o == J) return;
         const int m = o < J ? o : o - 2 * J;
         const bool keep = !cut || (m < 0 ? -m : m) <= cut[i0 + b];
-        A[(int64_t)(i0 + b) * K + m + J - 1] = keep ? cplx<T>{v.x, -v.y} : cplx<T>{(T)0, (T)0};
+        A[ana_index(i0 + b, m + J - 1, J, K, lb)] = keep ? cplx<T>{v.x, -v.y} : cplx<T>{(T)0, (T)0};
     }
 };
 
 template <typename T, int LOGN, int E>
 __global__ __launch_bounds__(256) void k_analysis_phi(const T *__restrict__ vals, const cplx<T> *__restrict__ tws,
                                                       const int32_t *__restrict__ cut, cplx<T> *__restrict__ A,
-                                                      int J, int rows_per_wg, int log_rows_per_wg)
+                                                      int J, int rows_per_wg, int log_rows_per_wg, int lb,
+                                                      int64_t fstride)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int N = 1 << LOGN;  // = 2J
@@ -764,7 +778,7 @@ __global__ __launch_bounds__(256) void k_analysis_phi(const T *__restrict__ vals
     const int f = (int)blockIdx.x / nrb;
     const int i0 = ((int)blockIdx.x - f * nrb) * rows_per_wg;
     AnaRowLoad<T> ld{vals + (int64_t)f * J * N, N, i0};
-    AnaRowStore<T> st{A + (int64_t)f * J * K, cut, J, K, i0};
+    AnaRowStore<T> st{A + (int64_t)f * fstride, cut, J, K, i0, lb};
     TwiddleCopy<cplx<T>> pro{tw, tws, tw_lds_len(N)};
     fft_stages<T, LOGN, 0, E, false>(s, log_rows_per_wg, 1, lds_seq_len(N), tw, ld, st, pro);
 }
@@ -773,14 +787,14 @@ __global__ __launch_bounds__(256) void k_analysis_phi(const T *__restrict__ vals
 // length 2J with the glide sign, forward transform over theta, then the
 // half-cell phase and the normalisation: ft[n][m] = Z[n] e^{-i n pi/(2J)} / (2J)^2.
 template <typename T> struct AnaColLoad {
-    const cplx<T> *A;  // this field, [J][K]
-    int J, K, m0;
+    const cplx<T> *A;  // this field, layout as for AnaRowStore
+    int J, K, m0, lb;
     __device__ cplx<T> operator()(int i, int b) const
     {
         const int mi = m0 + b;
         const int mc = mi < K ? mi : K - 1;
         const int r = i < J ? i : 2 * J - 1 - i;
-        const cplx<T> v = A[(int64_t)r * K + mc];
+        const cplx<T> v = A[ana_index(r, mc, J, K, lb)];
         const bool neg = i >= J && (((mc - (J - 1)) & 1) != 0);
         const T sre = neg ? -v.x : v.x, sim = neg ? -v.y : v.y;
         return {sre, -sim};  // conj
@@ -806,7 +820,8 @@ __global__ __launch_bounds__(512) void k_analysis_theta(const cplx<T> *__restric
                                                         const cplx<T> *__restrict__ tws,
                                                         const cplx<T> *__restrict__ phase,
                                                         cplx<T> *__restrict__ out, int J, int cols_per_wg,
-                                                        int log_cols_per_wg, int m_major)
+                                                        int log_cols_per_wg, int m_major, int lb,
+                                                        int64_t fstride)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int N = 1 << LOGN;  // = 2J
@@ -816,7 +831,7 @@ __global__ __launch_bounds__(512) void k_analysis_theta(const cplx<T> *__restric
     const int ntiles = (K + cols_per_wg - 1) / cols_per_wg;
     const int f = (int)blockIdx.x / ntiles;
     const int m0 = ((int)blockIdx.x - f * ntiles) * cols_per_wg;
-    AnaColLoad<T> ld{A + (int64_t)f * J * K, J, K, m0};
+    AnaColLoad<T> ld{A + (int64_t)f * fstride, J, K, m0, lb};
     AnaColStore<T> st{out + (int64_t)f * K * K, phase, J, K, m0, m_major};
     TwiddleCopy<cplx<T>> pro{tw, tws, tw_lds_len(N)};
     fft_stages<T, LOGN, 0, E, true>(s, log_cols_per_wg, cols_per_wg, 1, tw, ld, st, pro);
@@ -825,7 +840,7 @@ __global__ __launch_bounds__(512) void k_analysis_theta(const cplx<T> *__restric
 // phi step only: rows per workgroup so that it transforms 4096 elements
 template <typename T, int LOGN>
 static hipError_t launch_analysis_rows_t(const AnalysisParams &ap, const void *vals, const void *tws, void *A,
-                                         hipStream_t s)
+                                         hipStream_t s, int lb = -1)
 {
     constexpr int N = 1 << LOGN;
     const int J = N / 2;
@@ -840,7 +855,8 @@ static hipError_t launch_analysis_rows_t(const AnalysisParams &ap, const void *v
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3((J / rb) * ap.n_fields), dim3(threads), lds, s, (const T *)vals,
-                       (const cplx<T> *)tws, ap.zonal_cut, (cplx<T> *)A, J, rb, lrb);
+                       (const cplx<T> *)tws, ap.zonal_cut, (cplx<T> *)A, J, rb, lrb, lb,
+                       lb < 0 ? (int64_t)J * (2 * J - 1) : (int64_t)2 * J * J);
     return hipGetLastError();
 }
 
@@ -850,15 +866,9 @@ static hipError_t launch_analysis_t(const AnalysisParams &ap, const void *vals, 
 {
     constexpr int N = 1 << LOGN;
     const int J = N / 2;
-    int threads;
-    size_t lds;
-    {
-        const hipError_t e = launch_analysis_rows_t<T, LOGN>(ap, vals, tws, A, s);
-        if (e != hipSuccess) return e;
-    }
     // theta step: columns per workgroup so that a workgroup has 64..512
     // threads and at most 80 KB of LDS (two workgroups per CU); wider tiles
-    // make longer row segments of A and of the output
+    // make longer row segments of the output
     int cb = 1;
     while (N * cb / kElemsPerThread < 64) cb *= 2;
     while (cb < 16 && N * cb * 2 / kElemsPerThread <= 512 &&
@@ -866,9 +876,18 @@ static hipError_t launch_analysis_t(const AnalysisParams &ap, const void *vals, 
         cb *= 2;
     int lcb = 0;
     while ((1 << lcb) < cb) ++lcb;
-    threads = N * cb / kElemsPerThread;
-    if (threads < 1 || threads > 512 || threads % cb != 0) return hipErrorInvalidConfiguration;
-    lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * cb + tw_lds_len(N));
+    const int threads = N * cb / kElemsPerThread;
+    if (threads < 1 || threads > 512 || threads % cb != 0 || cb > N) return hipErrorInvalidConfiguration;
+    const size_t lds = sizeof(cplx<T>) * ((size_t)lds_seq_len(N) * cb + tw_lds_len(N));
+    // A in column blocks of the theta tile's width (one column, where the
+    // tile is one column wide, stays in rows: a column-major A would make
+    // the phi step's stores single elements J apart)
+    const int lb = cb >= 2 ? lcb : -1;
+    const int64_t fstride = lb < 0 ? (int64_t)J * (2 * J - 1) : (int64_t)2 * J * J;
+    {
+        const hipError_t e = launch_analysis_rows_t<T, LOGN>(ap, vals, tws, A, s, lb);
+        if (e != hipSuccess) return e;
+    }
     {
         auto kern = k_analysis_theta<T, LOGN, kElemsPerThread>;
         if (lds > 65536)
@@ -876,7 +895,8 @@ static hipError_t launch_analysis_t(const AnalysisParams &ap, const void *vals, 
         const int K = 2 * J - 1;
         const int ntiles = (K + cb - 1) / cb;
         hipLaunchKernelGGL(kern, dim3(ntiles * ap.n_fields), dim3(threads), lds, s, (const cplx<T> *)A,
-                           (const cplx<T> *)tws, (const cplx<T> *)phase, (cplx<T> *)out, J, cb, lcb, ap.m_major);
+                           (const cplx<T> *)tws, (const cplx<T> *)phase, (cplx<T> *)out, J, cb, lcb, ap.m_major,
+                           lb, fstride);
     }
     return hipGetLastError();
 }

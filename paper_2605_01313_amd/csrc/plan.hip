@@ -1192,7 +1192,7 @@ NUFFT2_API nufft2_status nufft2_analysis_plan(nufft2_prec prec, int64_t J, int32
     const size_t cs = prec == NUFFT2_FP32 ? sizeof(float2) : sizeof(double2);
     const size_t K = 2 * (size_t)J - 1;
     if (hipMalloc(&a->tws, cs * (64 + 2 * (size_t)J)) != hipSuccess || hipMalloc(&a->phase, cs * K) != hipSuccess ||
-        hipMalloc(&a->A, cs * (size_t)n_fields * J * K) != hipSuccess ||
+        hipMalloc(&a->A, cs * (size_t)n_fields * J * (2 * (size_t)J)) != hipSuccess ||  // 2J x J: blocked layout
         hipMalloc(&a->cut, sizeof(int32_t) * (size_t)J) != hipSuccess) {
         (void)hipGetLastError();
         analysis_free(a);
