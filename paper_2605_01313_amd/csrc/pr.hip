@@ -84,6 +84,11 @@ struct PrParams {
 
 template <typename T> struct C2 { T x, y; };
 
+// The elementwise kernels (k_pr_rhs, k_pr_synth) run kPrThreads-thread
+// blocks along one row of their output each.
+constexpr int kPrThreads = 256;
+__host__ __device__ inline int pr_row_blocks(int width) { return (width + kPrThreads - 1) / kPrThreads; }
+
 // Standard coefficients (c, s) at (n, m), n, m >= 0, read from exp-form
 // entries e(+-n, +-m) as the least-squares inverse of eq. dfs_fourier_coeffs.
 template <typename T>
@@ -122,15 +127,17 @@ __device__ inline void exp_to_std(const C2<T> *__restrict__ e, const PrParams &p
 
 // rhs[f][cs][j][m] = sum_i A[i][j] w_i b_i (zero outside the column's range).
 template <typename T>
-__global__ __launch_bounds__(256) void k_pr_rhs(const C2<T> *__restrict__ e, double *__restrict__ rhs, PrParams p)
+__global__ __launch_bounds__(kPrThreads) void k_pr_rhs(const C2<T> *__restrict__ e, double *__restrict__ rhs, PrParams p)
 {
     const int64_t W = p.M + 1, H = p.N + 1;
-    const int64_t total = (int64_t)p.F * H * W;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    const int m = (int)(t % W);
-    const int j = (int)((t / W) % H);
-    const int f = (int)(t / (W * H));
+    // blocks of one row (f, j) each: the row and field come from one
+    // block-uniform division instead of 64-bit divisions per thread
+    const int nbx = pr_row_blocks((int)W);
+    const int row = (int)blockIdx.x / nbx;
+    const int m = ((int)blockIdx.x - row * nbx) * kPrThreads + (int)threadIdx.x;
+    if (m >= W) return;
+    const int f = row / (int)H;
+    const int j = row - f * (int)H;
     const int cls = pr_class(m);
     int lo, hi;
     pr_range(cls, p.N, lo, hi);
@@ -439,14 +446,17 @@ __device__ inline void pr_to_std_pair(const T *__restrict__ cc, const T *__restr
 // Exp-form entry (n, m) of the pr expansion: standard coefficients of column
 // |m| at |n|, then the map of eq. dfs_fourier_coeffs.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pr_synth(const T *__restrict__ pr, C2<T> *__restrict__ e, PrParams p)
+__global__ __launch_bounds__(kPrThreads) void k_pr_synth(const T *__restrict__ pr, C2<T> *__restrict__ e, PrParams p)
 {
     const int64_t Wd = 2 * p.M + 1, Hd = 2 * p.N + 1;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)p.F * Hd * Wd) return;
-    const int b = (int)(t % Wd);
-    const int a = (int)((t / Wd) % Hd);
-    const int f = (int)(t / (Wd * Hd));
+    // one row (f, a) per group of blocks, as in k_pr_rhs
+    const int nbx = pr_row_blocks((int)Wd);
+    const int row = (int)blockIdx.x / nbx;
+    const int b = ((int)blockIdx.x - row * nbx) * kPrThreads + (int)threadIdx.x;
+    if (b >= Wd) return;
+    const int f = row / (int)Hd;
+    const int a = row - f * (int)Hd;
+    const int64_t t = (int64_t)row * Wd + b;
     const int n = a - p.N, m = b - p.M;
     const int an = n < 0 ? -n : n, am = m < 0 ? -m : m;
     const int64_t W = p.M + 1, H = p.N + 1;
@@ -478,9 +488,9 @@ __global__ __launch_bounds__(256) void k_pr_synth(const T *__restrict__ pr, C2<T
 
 template <typename T> hipError_t launch_rhs(const void *e, double *rhs, const PrParams &p, hipStream_t s)
 {
-    const int64_t total = (int64_t)p.F * (p.N + 1) * (p.M + 1);
-    hipLaunchKernelGGL(k_pr_rhs<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const C2<T> *)e, rhs,
-                       p);
+    const int64_t blocks = (int64_t)p.F * (p.N + 1) * pr_row_blocks(p.M + 1);
+    if (blocks > INT32_MAX) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_pr_rhs<T>, dim3((unsigned)blocks), dim3(kPrThreads), 0, s, (const C2<T> *)e, rhs, p);
     return hipGetLastError();
 }
 
@@ -498,9 +508,10 @@ template <typename T> hipError_t launch_solve(double *rhs, const double *fac, do
 
 template <typename T> hipError_t launch_synth(const void *pr, void *e, const PrParams &p, hipStream_t s)
 {
-    const int64_t total = (int64_t)p.F * (2 * p.N + 1) * (2 * p.M + 1);
-    hipLaunchKernelGGL(k_pr_synth<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const T *)pr,
-                       (C2<T> *)e, p);
+    const int64_t blocks = (int64_t)p.F * (2 * p.N + 1) * pr_row_blocks(2 * p.M + 1);
+    if (blocks > INT32_MAX) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_pr_synth<T>, dim3((unsigned)blocks), dim3(kPrThreads), 0, s, (const T *)pr, (C2<T> *)e,
+                       p);
     return hipGetLastError();
 }
 
